@@ -1,0 +1,156 @@
+"""Benchmark: Stokes solves per second to 1e-10 relative residual.
+
+Workload (default): P4-P3 Taylor-Hood on the unit square, 64x64 squares each
+cut into two triangles, 5-level hierarchy (4x4 .. 64x64), composite Vanka
+patches, V(2,2) cycles with damping 0.5, FGMRES(30) to 1e-10, plain FP64.
+One step = one full solve (hierarchy resident, patches factored); the
+right-hand side is resident in HBM before the timed region.
+
+Prints one JSON line with the throughput, per-solve latency percentiles, the
+roofline of the dominant kernel (finest-level patch apply, timed with HIP
+events around every launch inside the timed region) and a CPU baseline: the
+oracle timed on one FGMRES iteration of the same workload, on one host core.
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "p4p3-64": dict(k=4, n0=4, levels=5, desc="P4-P3 Taylor-Hood, 64x64 two-triangle mesh of the unit square, "
+                                           "5-level hierarchy, composite Vanka, V(2,2), omega 0.5, FGMRES(30) to 1e-10"),
+    "p2p1-16": dict(k=2, n0=4, levels=3, desc="P2-P1 Taylor-Hood, 16x16 two-triangle mesh of the unit square, "
+                                           "3-level hierarchy, vertex Vanka, V(2,2), omega 0.5, FGMRES(30) to 1e-10"),
+}
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_sample(workload, iterations):
+    """Oracle timing (run in a child process with one BLAS/OpenMP thread)."""
+    import numpy as np
+
+    import synth
+    from oracle import fields, solve
+    w = WORKLOADS[workload]
+    H, V = solve.setup(2, w["k"], w["n0"], w["levels"], 1.0, fields.baseline_mms)
+    L = H.finest
+    v = synth.vector(L.N, 1)
+    v /= np.linalg.norm(v)
+    t0 = time.perf_counter()
+    z = V.apply(v)
+    _ = L.K @ z
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / (dt * iterations), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FGMRES iteration (V(2,2) cycle + SpMV, {dt:.2f} s) of the numpy/scipy oracle on the "
+                      f"full workload, scaled by the {iterations} iterations of a solve"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="p4p3-64", choices=sorted(WORKLOADS))
+    ap.add_argument("--store", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-iterations", type=int, default=0, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+
+    if args.cpu_sample:
+        print(json.dumps(cpu_sample(args.cpu_sample, args.cpu_iterations)))
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the solver path here is single-GPU (multi-GPU sharding is a design "
+              "note, not built). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2409_14222_amd as vk
+    w = WORKLOADS[args.workload]
+    store = vk.VK_STORE_FP32 if args.store == "fp32" else vk.VK_STORE_FP64
+    torch.cuda.init()
+    t0 = time.perf_counter()
+    H = vk.Hierarchy(w["k"], w["n0"], w["levels"], store=store)
+    t_host = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    H.bind()
+    H.setup()
+    torch.cuda.synchronize()
+    t_dev = time.perf_counter() - t0
+    Lf = w["levels"] - 1
+    info = H.level_info(Lf)
+    b = torch.tensor(H.rhs(), device="cuda")
+    x = torch.empty_like(b)
+    for _ in range(args.warmup):
+        res = H.solve(b, x)
+    torch.cuda.synchronize()
+    H.kernel_timing(enable=True, reset=True)
+    lat = []
+    its = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        res = H.solve(b, x)
+        lat.append(time.perf_counter() - s0)
+        its.append(res["iterations"])
+        if not res["converged"]:
+            raise SystemExit(f"solve did not converge: {res}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    launches, kms = H.kernel_timing(enable=False, reset=True)
+    solves_per_s = args.steps / elapsed
+    its_mean = float(np.mean(its))
+
+    # dominant kernel: finest-level additive patch apply
+    s = 4 if store == vk.VK_STORE_FP32 else 8
+    apply_bytes = info.sum_n2 * s + info.sum_n * (4 + 8 + s)
+    avg_s = kms / 1e3 / max(launches, 1)
+    achieved = apply_bytes / avg_s / 1e9
+    out = {
+        "metric": "Stokes solves/s to 1e-10 rel. residual",
+        "value": solves_per_s,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if store == vk.VK_STORE_FP64 else "f64 (patch inverses stored/applied in f32)",
+        "data": "synthetic (manufactured solution)",
+        "config": {"workload": w["desc"], "dofs_free": info.n_free, "nnz": info.nnz, "patches": info.n_patches,
+                   "patch_dofs_sum": info.sum_n, "max_patch": info.max_n, "store": args.store},
+        "iterations": its_mean,
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
+        "vanka_dof_sweeps_per_s_finest": info.n_free * 4 * its_mean * solves_per_s,
+        "setup_s": {"host_assembly": t_host, "device_upload_gather_invert": t_dev},
+        "roofline": {"kernel": "patch_apply_kernel (finest level)", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": apply_bytes, "avg_launch_us": avg_s * 1e6,
+                     "launches": launches},
+    }
+    if not args.no_cpu_baseline:
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+                   HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample", args.workload,
+                            "--cpu-iterations", str(int(round(its_mean)))], capture_output=True, text=True, env=env,
+                           timeout=600)
+        if r.returncode == 0:
+            out["cpu_baseline"] = json.loads(r.stdout.strip().splitlines()[-1])
+        else:
+            out["cpu_baseline"] = {"error": r.stderr[-500:]}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * vk.h -- C ABI of the MI355X (gfx950) matrix-full additive Vanka multigrid
+ * Stokes solver.
+ *
+ * The method is the monolithic h-multigrid preconditioned FGMRES solver of
+ * Rafiei & MacLachlan, "Achieving h- and p-robust monolithic multigrid
+ * solvers for the Stokes equations": Taylor-Hood (P_k, P_{k-1}) on
+ * structured triangle meshes of the unit square (Sec. 3, Case 1; Sec. 4 for
+ * the mesh), and (P2, P1) on Kuhn tetrahedral meshes of the unit cube as an
+ * extension.  The relaxation is additive subspace correction over composite
+ * ("topological") Vanka patches (Sec. 3.1, Algorithm 1), implemented
+ * matrix-full: patch submatrices are gathered from the assembled global CSR
+ * matrix by DoF index lists and inverted once.
+ *
+ * Conventions
+ *  - Every function returns vk_status: 0 = VK_OK, > 0 = warning with valid
+ *    outputs, < 0 = error (outputs undefined).  vk_last_error() returns a
+ *    thread-local message for the last non-zero status.  No C++ exception
+ *    crosses this boundary.
+ *  - Levels are numbered 0 (coarsest, n_coarse) .. n_levels-1 (finest,
+ *    n_coarse * 2^(n_levels-1)).
+ *  - "d_" pointers are device pointers (HIP), "h_" pointers host pointers;
+ *    all are owned by the caller, who keeps them alive while a call that
+ *    uses them is in flight.  Vectors at the boundary are always float64.
+ *  - Device memory is owned by the caller: the library reports how many bytes
+ *    it needs (vk_hierarchy_workspace_bytes), the caller allocates one buffer
+ *    and binds it together with a HIP stream (vk_hierarchy_bind).  The library
+ *    never allocates or frees device memory.  All device work is enqueued on
+ *    the bound stream; calls return without synchronising unless stated.
+ *  - Free-DoF numbering: velocity lattice points of the P_k lattice (spacing
+ *    1/(k n)) that are not on the boundary, lexicographic with x fastest,
+ *    components interleaved (dof = dim * idx + c); then all points of the
+ *    P_{k-1} pressure lattice, lexicographic with x fastest.  Dirichlet
+ *    velocity DoFs are eliminated (lifted into the right-hand side).
+ *  - A hierarchy is not thread-safe; distinct hierarchies are independent.
+ */
+#ifndef VK_H
+#define VK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int vk_status;
+
+enum {
+  VK_OK = 0,
+  VK_NOT_CONVERGED = 1, /* solve reached maxit; outputs valid */
+  VK_EINVAL = -1,       /* bad argument */
+  VK_ENOMEM = -2,       /* workspace too small / host allocation failed */
+  VK_EHIP = -3,         /* a HIP runtime call failed */
+  VK_ESINGULAR = -4,    /* a patch matrix had a zero pivot */
+  VK_ENAN = -5,         /* non-finite input or breakdown to NaN */
+  VK_EBUSY = -6,        /* resource busy */
+  VK_ESTATE = -7        /* call out of order (e.g. solve before bind) */
+};
+
+enum { VK_TH = 0 }; /* Taylor-Hood (P_k, P_{k-1}), continuous pressure */
+
+enum {
+  VK_F_BASELINE_MMS = 0, /* u = (sin pi x sin pi y, cos pi x cos pi y), p = 0 */
+  VK_F_PAPER_MMS = 1,    /* u = (sin pi x cos pi y, -cos pi x sin pi y), p = 0 (Sec. 4) */
+  VK_F_RANDOM = 2,       /* sum_{a,b} g[c][a][b] sin(a pi x) sin(b pi y)/(a^2+b^2), u = 0 on the boundary */
+  VK_F_CUBE_MMS = 3      /* 3D divergence-free sin/cos field, p = 0 */
+};
+
+enum { VK_PATCH_COMPOSITE = 0, VK_PATCH_STAR = 1 };
+enum { VK_STORE_FP64 = 0, VK_STORE_FP32 = 1 };
+
+/* Problem statement (Sec. 2 weak form; Sec. 3 hierarchy; Sec. 4 mesh). */
+typedef struct vk_problem {
+  int dim;          /* 2 (triangles) or 3 (Kuhn tetrahedra, k = 2 only) */
+  int family;       /* VK_TH */
+  int k;            /* velocity order, pressure order k-1; 2 <= k <= 6 in 2D */
+  int n_coarse;     /* cells per direction on level 0 (>= 1) */
+  int n_levels;     /* >= 2 */
+  double viscosity; /* nu > 0 in a(u,v) = 2 nu int eps(u):eps(v) */
+  int forcing;      /* VK_F_* */
+  int n_modes;      /* VK_F_RANDOM: modes per direction M (coefficients 2*M*M) */
+  const double* h_forcing_coeffs; /* VK_F_RANDOM: g[c][a][b], copied at create */
+} vk_problem;
+
+/* Relaxation options (Sec. 3.1, Algorithm 1 as a damped smoother). */
+typedef struct vk_patch_opts {
+  int construct; /* VK_PATCH_COMPOSITE (vertex + edge + cell patches) or VK_PATCH_STAR */
+  int store;     /* VK_STORE_FP64, or VK_STORE_FP32: inverses factored in FP64, stored and applied in FP32 */
+  double omega;  /* global damping; each DoF is further scaled by 1/multiplicity */
+} vk_patch_opts;
+
+typedef struct vk_level_info {
+  int n;           /* cells per direction */
+  int n_free;      /* free DoFs N */
+  int n_velocity;  /* free velocity DoFs (the first n_velocity of the numbering) */
+  int64_t nnz;     /* CSR nonzeros of K */
+  int n_patches;   /* J (0 on level 0, which is solved directly) */
+  int64_t sum_n;   /* sum of patch sizes */
+  int64_t sum_n2;  /* sum of squared patch sizes */
+  int max_n;       /* largest patch */
+  int64_t p_nnz;   /* nonzeros of the prolongation from level-1 (0 on level 0) */
+} vk_level_info;
+
+typedef struct vk_solve_opts {
+  int restart;  /* FGMRES restart length m (30) */
+  int maxit;    /* total iteration cap (100) */
+  double rtol;  /* stop when ||b - K x||_2 <= rtol ||b||_2 (1e-10) */
+  int nu_pre;   /* pre-smoothing sweeps per level (2) */
+  int nu_post;  /* post-smoothing sweeps per level (2) */
+} vk_solve_opts;
+
+typedef struct vk_solve_info {
+  int iterations;        /* total FGMRES iterations */
+  int converged;         /* 1 if the true relative residual is <= rtol */
+  double rel_residual;   /* ||b - K x|| / ||b|| of the returned x */
+  double* h_history;     /* optional, caller-owned, maxit+1 entries: residual estimates */
+} vk_solve_info;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* vk_last_error(void);
+
+typedef struct vk_hierarchy vk_hierarchy;
+
+/* Host-side setup of every level (Sec. 3): structured meshes, Taylor-Hood
+ * spaces, K = [A B^T; B 0] on the free DoFs (rediscretised per level), the
+ * finest right-hand side with Dirichlet lifting, prolongations by nodal
+ * interpolation (restriction = transpose) and the patch DoF lists and
+ * inverse map (Sec. 3.1).  No device memory is touched.  VK_EINVAL on bad
+ * sizes; *out receives a hierarchy to be freed with vk_hierarchy_destroy. */
+vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts, vk_hierarchy** out);
+
+/* Frees host memory.  Device memory (the bound workspace) stays the caller's. */
+vk_status vk_hierarchy_destroy(vk_hierarchy* h);
+
+/* Bytes of device workspace needed by vk_hierarchy_bind (all levels, the
+ * patch inverses in the chosen precision, the V-cycle vectors and an FGMRES
+ * basis of max_restart vectors). */
+vk_status vk_hierarchy_workspace_bytes(const vk_hierarchy* h, int max_restart, size_t* bytes);
+
+/* Carves the caller's buffer d_workspace (>= the reported bytes, 256-byte
+ * aligned) and enqueues the upload of every level on hip_stream (a
+ * hipStream_t; NULL = default stream).  VK_ENOMEM if bytes is too small. */
+vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_workspace, size_t bytes, int max_restart,
+                            void* hip_stream);
+
+/* Matrix-full patch setup on the device: gathers every K_i = K[I_i, I_i]
+ * from the CSR matrix (Sec. 3.1), inverts it by Gauss-Jordan elimination
+ * with partial pivoting in FP64 and stores the inverse (FP64 or FP32).
+ * Synchronises; VK_ESINGULAR (and the level/patch in vk_last_error) on a zero
+ * pivot. */
+vk_status vk_patches_setup(vk_hierarchy* h);
+
+vk_status vk_level_info_get(const vk_hierarchy* h, int level, vk_level_info* info);
+
+/* Host copies of level data, for tests.  Arrays sized from vk_level_info. */
+vk_status vk_level_csr(const vk_hierarchy* h, int level, int* h_rowptr, int* h_col, double* h_val);
+vk_status vk_level_prolongation(const vk_hierarchy* h, int level, int* h_rowptr, int* h_col,
+                                double* h_val); /* P from level-1 to level, rows = level's DoFs */
+vk_status vk_level_patches(const vk_hierarchy* h, int level, int* h_ptr, int* h_dofs);
+vk_status vk_dof_coords(const vk_hierarchy* h, int level, double* h_xyz /* N*dim */, int* h_kind /* N */);
+/* Finest-level right-hand side, made consistent (constant pressure removed). */
+vk_status vk_rhs(const vk_hierarchy* h, double* h_b);
+
+/* Copies the dense matrices K_i (count patches from first, each n_i x n_i,
+ * column-major, packed back to back) gathered on the device, to d_out. */
+vk_status vk_patch_gather(vk_hierarchy* h, int level, int first, int count, double* d_out);
+/* Copies the stored inverse of one patch (n_i x n_i column-major, as float64) to d_out. */
+vk_status vk_patch_inverse(vk_hierarchy* h, int level, int patch, double* d_out);
+
+/* d_y = K_level d_x */
+vk_status vk_spmv(vk_hierarchy* h, int level, const double* d_x, double* d_y);
+/* d_rc = P_level^T d_rf (restriction from level to level-1) */
+vk_status vk_restrict(vk_hierarchy* h, int level, const double* d_rf, double* d_rc);
+/* d_ef += P_level d_ec (prolongation from level-1 to level) */
+vk_status vk_prolong_add(vk_hierarchy* h, int level, const double* d_ec, double* d_ef);
+/* nsweeps damped additive Vanka sweeps on K_level x = b (Algorithm 1):
+ * x <- x + omega W sum_i R_i^T K_i^{-1} R_i (b - K x), W = diag(1/multiplicity). */
+vk_status vk_smooth(vk_hierarchy* h, int level, const double* d_b, double* d_x, int nsweeps);
+/* Coarsest-level solve of the bordered system [K_0 z; z^T 0][e; mu] = [r; 0]. */
+vk_status vk_coarse_solve(vk_hierarchy* h, const double* d_r, double* d_e);
+/* One V(nu_pre, nu_post) cycle on the finest level with zero initial guess: d_e = B d_r. */
+vk_status vk_vcycle(vk_hierarchy* h, const double* d_r, double* d_e, int nu_pre, int nu_post);
+/* FGMRES preconditioned by one V-cycle per iteration (Sec. 3; Sec. 4 settings).
+ * d_b is made consistent in a private copy; d_x receives the solution with
+ * zero-sum pressure.  Synchronous.  VK_NOT_CONVERGED if rtol was not met. */
+vk_status vk_solve(vk_hierarchy* h, const double* d_b, double* d_x, const vk_solve_opts* opts,
+                   vk_solve_info* info);
+
+/* Timing of the finest-level patch-apply kernel (HIP events around every
+ * launch while enabled): launches and total milliseconds since the last reset. */
+vk_status vk_kernel_timing(vk_hierarchy* h, int enable, int reset, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VK_H */

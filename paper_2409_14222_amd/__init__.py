@@ -1,0 +1,233 @@
+"""Python binding of libvk.so: the MI355X matrix-full additive Vanka multigrid
+Stokes solver (monolithic h-multigrid preconditioned FGMRES for Taylor-Hood).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch is used for device memory (one workspace tensor per hierarchy, plus the
+caller's vectors) and for the HIP stream.  Importing fails loudly if the
+library has not been built (python paper_2409_14222_amd/build.py).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libvk.so")
+if not os.path.exists(LIBPATH):
+    raise ImportError(f"{LIBPATH} is missing: build it with `python {_HERE}/build.py`")
+lib = ctypes.CDLL(LIBPATH)
+
+# ---------------------------------------------------------------- constants (include/vk.h)
+VK_OK, VK_NOT_CONVERGED = 0, 1
+VK_EINVAL, VK_ENOMEM, VK_EHIP, VK_ESINGULAR, VK_ENAN, VK_EBUSY, VK_ESTATE = -1, -2, -3, -4, -5, -6, -7
+VK_TH = 0
+VK_F_BASELINE_MMS, VK_F_PAPER_MMS, VK_F_RANDOM, VK_F_CUBE_MMS = 0, 1, 2, 3
+VK_PATCH_COMPOSITE, VK_PATCH_STAR = 0, 1
+VK_STORE_FP64, VK_STORE_FP32 = 0, 1
+
+_c_int, _c_dbl, _p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+
+
+class vk_problem(ctypes.Structure):
+    _fields_ = [("dim", _c_int), ("family", _c_int), ("k", _c_int), ("n_coarse", _c_int), ("n_levels", _c_int),
+                ("viscosity", _c_dbl), ("forcing", _c_int), ("n_modes", _c_int),
+                ("h_forcing_coeffs", ctypes.POINTER(_c_dbl))]
+
+
+class vk_patch_opts(ctypes.Structure):
+    _fields_ = [("construct", _c_int), ("store", _c_int), ("omega", _c_dbl)]
+
+
+class vk_level_info(ctypes.Structure):
+    _fields_ = [("n", _c_int), ("n_free", _c_int), ("n_velocity", _c_int), ("nnz", ctypes.c_int64),
+                ("n_patches", _c_int), ("sum_n", ctypes.c_int64), ("sum_n2", ctypes.c_int64), ("max_n", _c_int),
+                ("p_nnz", ctypes.c_int64)]
+
+
+class vk_solve_opts(ctypes.Structure):
+    _fields_ = [("restart", _c_int), ("maxit", _c_int), ("rtol", _c_dbl), ("nu_pre", _c_int), ("nu_post", _c_int)]
+
+
+class vk_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", _c_int), ("converged", _c_int), ("rel_residual", _c_dbl),
+                ("h_history", ctypes.POINTER(_c_dbl))]
+
+
+_P = ctypes.POINTER
+_SIGS = {
+    "vk_last_error": ([], ctypes.c_char_p),
+    "vk_hierarchy_create": ([_P(vk_problem), _P(vk_patch_opts), _P(_p)], _c_int),
+    "vk_hierarchy_destroy": ([_p], _c_int),
+    "vk_hierarchy_workspace_bytes": ([_p, _c_int, _P(ctypes.c_size_t)], _c_int),
+    "vk_hierarchy_bind": ([_p, _p, ctypes.c_size_t, _c_int, _p], _c_int),
+    "vk_patches_setup": ([_p], _c_int),
+    "vk_level_info_get": ([_p, _c_int, _P(vk_level_info)], _c_int),
+    "vk_level_csr": ([_p, _c_int, _p, _p, _p], _c_int),
+    "vk_level_prolongation": ([_p, _c_int, _p, _p, _p], _c_int),
+    "vk_level_patches": ([_p, _c_int, _p, _p], _c_int),
+    "vk_dof_coords": ([_p, _c_int, _p, _p], _c_int),
+    "vk_rhs": ([_p, _p], _c_int),
+    "vk_patch_gather": ([_p, _c_int, _c_int, _c_int, _p], _c_int),
+    "vk_patch_inverse": ([_p, _c_int, _c_int, _p], _c_int),
+    "vk_spmv": ([_p, _c_int, _p, _p], _c_int),
+    "vk_restrict": ([_p, _c_int, _p, _p], _c_int),
+    "vk_prolong_add": ([_p, _c_int, _p, _p], _c_int),
+    "vk_smooth": ([_p, _c_int, _p, _p, _c_int], _c_int),
+    "vk_coarse_solve": ([_p, _p, _p], _c_int),
+    "vk_vcycle": ([_p, _p, _p, _c_int, _c_int], _c_int),
+    "vk_solve": ([_p, _p, _p, _P(vk_solve_opts), _P(vk_solve_info)], _c_int),
+    "vk_kernel_timing": ([_p, _c_int, _c_int, _P(ctypes.c_int64), _P(_c_dbl)], _c_int),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+EXPORTS = tuple(_SIGS)
+
+
+class VkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"vk status {code}: {msg}")
+        self.code = code
+
+
+def check(status):
+    if status < 0:
+        raise VkError(status, lib.vk_last_error().decode())
+    return status
+
+
+def _ptr(a):
+    """Address of a numpy array or a torch tensor (device pointer for CUDA tensors)."""
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+class Hierarchy:
+    """One Stokes problem hierarchy.  Host-side data is available right after
+    construction; device work needs bind() (allocates the workspace with torch
+    on the current device and binds the current stream) and setup()."""
+
+    def __init__(self, k, n_coarse, n_levels, dim=2, viscosity=1.0, forcing=VK_F_BASELINE_MMS, coeffs=None,
+                 construct=VK_PATCH_COMPOSITE, store=VK_STORE_FP64, omega=0.5):
+        self._coeffs = None
+        n_modes = 0
+        cptr = None
+        if coeffs is not None:
+            self._coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+            n_modes = self._coeffs.shape[-1]
+            cptr = self._coeffs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.prob = vk_problem(dim, VK_TH, k, n_coarse, n_levels, viscosity, forcing, n_modes, cptr)
+        self.opts = vk_patch_opts(construct, store, omega)
+        h = ctypes.c_void_p()
+        check(lib.vk_hierarchy_create(ctypes.byref(self.prob), ctypes.byref(self.opts), ctypes.byref(h)))
+        self.h = h
+        self.n_levels = n_levels
+        self.dim = dim
+        self.ws = None
+        self.stream = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib.vk_hierarchy_destroy(h)
+            self.h = None
+
+    # ------------------------------------------------------------ host data
+    def level_info(self, level):
+        info = vk_level_info()
+        check(lib.vk_level_info_get(self.h, level, ctypes.byref(info)))
+        return info
+
+    def csr(self, level):
+        inf = self.level_info(level)
+        rp = np.empty(inf.n_free + 1, np.int32); col = np.empty(inf.nnz, np.int32); val = np.empty(inf.nnz)
+        check(lib.vk_level_csr(self.h, level, _ptr(rp), _ptr(col), _ptr(val)))
+        return rp, col, val
+
+    def prolongation(self, level):
+        inf = self.level_info(level)
+        rp = np.empty(inf.n_free + 1, np.int32); col = np.empty(inf.p_nnz, np.int32); val = np.empty(inf.p_nnz)
+        check(lib.vk_level_prolongation(self.h, level, _ptr(rp), _ptr(col), _ptr(val)))
+        return rp, col, val
+
+    def patches(self, level):
+        inf = self.level_info(level)
+        ptr = np.empty(inf.n_patches + 1, np.int32); dofs = np.empty(inf.sum_n, np.int32)
+        check(lib.vk_level_patches(self.h, level, _ptr(ptr), _ptr(dofs)))
+        return ptr, dofs
+
+    def dof_coords(self, level):
+        inf = self.level_info(level)
+        X = np.empty((inf.n_free, self.dim)); kind = np.empty(inf.n_free, np.int32)
+        check(lib.vk_dof_coords(self.h, level, _ptr(X), _ptr(kind)))
+        return X, kind
+
+    def rhs(self):
+        b = np.empty(self.level_info(self.n_levels - 1).n_free)
+        check(lib.vk_rhs(self.h, _ptr(b)))
+        return b
+
+    # ------------------------------------------------------------ device
+    def workspace_bytes(self, max_restart=30):
+        nb = ctypes.c_size_t()
+        check(lib.vk_hierarchy_workspace_bytes(self.h, max_restart, ctypes.byref(nb)))
+        return nb.value
+
+    def bind(self, max_restart=30, device="cuda"):
+        import torch
+        nbytes = self.workspace_bytes(max_restart)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.ws.device)
+        check(lib.vk_hierarchy_bind(self.h, aligned, nbytes + 256 - (aligned - base), max_restart,
+                                    self.stream.cuda_stream))
+        self.max_restart = max_restart
+        return self
+
+    def setup(self):
+        check(lib.vk_patches_setup(self.h))
+        return self
+
+    def patch_gather(self, level, first, count, out):
+        check(lib.vk_patch_gather(self.h, level, first, count, _ptr(out)))
+
+    def patch_inverse(self, level, patch, out):
+        check(lib.vk_patch_inverse(self.h, level, patch, _ptr(out)))
+
+    def spmv(self, level, x, y):
+        check(lib.vk_spmv(self.h, level, _ptr(x), _ptr(y)))
+
+    def restrict(self, level, rf, rc):
+        check(lib.vk_restrict(self.h, level, _ptr(rf), _ptr(rc)))
+
+    def prolong_add(self, level, ec, ef):
+        check(lib.vk_prolong_add(self.h, level, _ptr(ec), _ptr(ef)))
+
+    def smooth(self, level, b, x, nsweeps):
+        check(lib.vk_smooth(self.h, level, _ptr(b), _ptr(x), nsweeps))
+
+    def coarse_solve(self, r, e):
+        check(lib.vk_coarse_solve(self.h, _ptr(r), _ptr(e)))
+
+    def vcycle(self, r, e, nu_pre=2, nu_post=2):
+        check(lib.vk_vcycle(self.h, _ptr(r), _ptr(e), nu_pre, nu_post))
+
+    def solve(self, b, x, restart=30, maxit=100, rtol=1e-10, nu_pre=2, nu_post=2, history=False):
+        opts = vk_solve_opts(restart, maxit, rtol, nu_pre, nu_post)
+        hist = np.zeros(maxit + 1) if history else None
+        info = vk_solve_info(0, 0, 0.0, hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if history else None)
+        status = check(lib.vk_solve(self.h, _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(info)))
+        out = {"status": status, "iterations": info.iterations, "converged": bool(info.converged),
+               "rel_residual": info.rel_residual}
+        if history:
+            out["history"] = hist[: info.iterations + 1].copy()
+        return out
+
+    def kernel_timing(self, enable=True, reset=False):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        check(lib.vk_kernel_timing(self.h, int(enable), int(reset), ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value

@@ -1,0 +1,730 @@
+// Device-side hierarchy: workspace carving, upload, the additive Vanka
+// smoother, the V-cycle and FGMRES (Sec. 3 and Sec. 4 of the paper), and the
+// C ABI declared in include/vk.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "vk_internal.hpp"
+
+using namespace vk;
+
+#define HIPCHECK(expr)                                                                                   \
+  do {                                                                                                   \
+    hipError_t _e = (expr);                                                                              \
+    if (_e != hipSuccess) throw Error(VK_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));       \
+  } while (0)
+
+namespace {
+
+struct DevLevel {
+  int N = 0, nvel = 0, J = 0;
+  double mean_row = 0, p_mean = 0, pt_mean = 0;
+  int *rowptr = nullptr, *col = nullptr;
+  double* val = nullptr;
+  int *prow = nullptr, *pcol = nullptr, *ptrow = nullptr, *ptcol = nullptr;
+  double *pval = nullptr, *ptval = nullptr;
+  int *pptr = nullptr, *pdofs = nullptr, *dptr = nullptr, *dslot = nullptr, *order = nullptr, *classes = nullptr;
+  int64_t* inv_off = nullptr;
+  double* scale = nullptr;
+  void* inv = nullptr;
+  void* delta = nullptr;
+  double *b = nullptr, *x = nullptr, *t = nullptr;
+  double* M = nullptr;  // coarsest level
+  int class_count[3] = {0, 0, 0};  // patches with n <= 32, <= 64, <= 128 (ids in `classes`)
+};
+
+// Sequential carving of one caller buffer into 256-byte aligned pieces.  Run
+// once with base == nullptr to size the workspace.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) / 256 * 256;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct vk_hierarchy {
+  Problem pr;
+  vk_patch_opts opts{};
+  std::vector<LevelHost> H;
+  std::vector<double> coarse_M;
+  std::vector<std::vector<int>> class_lists;  // per level: ids of class 0, then 1, then 2
+  bool bound = false, ready = false;
+  hipStream_t stream = nullptr;
+  int max_restart = 0;
+  std::vector<DevLevel> D;
+  double *V = nullptr, *Z = nullptr, *bb = nullptr, *r = nullptr, *partial = nullptr, *small = nullptr, *ydev = nullptr;
+  int* singular = nullptr;
+  std::vector<double> ybuf;
+  // kernel timing of the finest-level patch apply
+  bool timing = false;
+  int64_t t_launches = 0;
+  double t_ms = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free, ev_pending;
+
+  bool fp32() const { return opts.store == VK_STORE_FP32; }
+  int L() const { return (int)H.size(); }
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+// Lays out every device array of the hierarchy `Hs` in the carver; pointers go
+// to `h` (a scratch object when only sizing).
+void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver& cv, int max_restart) {
+  const int L = (int)Hs.size();
+  h->D.assign(L, DevLevel());
+  const size_t es = fp32 ? sizeof(float) : sizeof(double);
+  for (int l = 0; l < L; ++l) {
+    const LevelHost& lh = Hs[l];
+    DevLevel& d = h->D[l];
+    d.N = lh.N;
+    d.nvel = lh.nvel;
+    d.mean_row = (double)lh.K.nnz() / lh.N;
+    d.rowptr = cv.take<int>(lh.N + 1);
+    d.col = cv.take<int>(lh.K.col.size());
+    d.val = cv.take<double>(lh.K.val.size());
+    d.b = cv.take<double>(lh.N);
+    d.x = cv.take<double>(lh.N);
+    d.t = cv.take<double>(lh.N);
+    if (l == 0) {
+      d.M = cv.take<double>((size_t)lh.N * lh.N);
+      continue;
+    }
+    d.prow = cv.take<int>(lh.P.rowptr.size());
+    d.pcol = cv.take<int>(lh.P.col.size());
+    d.pval = cv.take<double>(lh.P.val.size());
+    d.ptrow = cv.take<int>(lh.PT.rowptr.size());
+    d.ptcol = cv.take<int>(lh.PT.col.size());
+    d.ptval = cv.take<double>(lh.PT.val.size());
+    d.p_mean = (double)lh.P.nnz() / std::max(1, lh.P.nrows);
+    d.pt_mean = (double)lh.PT.nnz() / std::max(1, lh.PT.nrows);
+    d.J = (int)lh.pptr.size() - 1;
+    d.pptr = cv.take<int>(lh.pptr.size());
+    d.pdofs = cv.take<int>(lh.pdofs.size());
+    d.dptr = cv.take<int>(lh.dptr.size());
+    d.dslot = cv.take<int>(lh.dslot.size());
+    d.order = cv.take<int>(lh.order.size());
+    d.classes = cv.take<int>(lh.order.size());
+    d.inv_off = cv.take<int64_t>(lh.inv_off.size());
+    d.scale = cv.take<double>(lh.scale.size());
+    d.inv = cv.take<char>((size_t)lh.inv_elems * es);
+    d.delta = cv.take<char>(lh.pdofs.size() * es);
+  }
+  const int N = Hs.back().N;
+  h->V = cv.take<double>((size_t)(max_restart + 1) * N);
+  h->Z = cv.take<double>((size_t)max_restart * N);
+  h->bb = cv.take<double>(N);
+  h->r = cv.take<double>(N);
+  h->partial = cv.take<double>((size_t)kReduceBlocks * 2 * (max_restart + 2) + 512);
+  h->small = cv.take<double>(4 * (max_restart + 2) + 16);
+  h->ydev = cv.take<double>(max_restart + 2);
+  h->singular = cv.take<int>(64);
+}
+
+template <typename T>
+void up(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (!src.empty()) HIPCHECK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+void check_launch() { HIPCHECK(hipGetLastError()); }
+
+void require_ready(const vk_hierarchy* h) {
+  require(h != nullptr, VK_EINVAL, "null hierarchy");
+  require(h->bound, VK_ESTATE, "hierarchy is not bound to a workspace");
+  require(h->ready, VK_ESTATE, "vk_patches_setup has not run");
+}
+
+void require_level(const vk_hierarchy* h, int level, int lo) {
+  require(level >= lo && level < h->L(), VK_EINVAL, "level out of range");
+}
+
+// ---------------------------------------------------------------- smoother
+void patch_apply(vk_hierarchy* h, int l, const double* t) {
+  DevLevel& d = h->D[l];
+  const bool timed = h->timing && l == h->L() - 1;
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (timed) {
+    if (h->ev_free.empty()) {
+      hipEvent_t a, b;
+      HIPCHECK(hipEventCreate(&a));
+      HIPCHECK(hipEventCreate(&b));
+      h->ev_free.push_back({a, b});
+    }
+    ev = h->ev_free.back();
+    h->ev_free.pop_back();
+    HIPCHECK(hipEventRecord(ev.first, h->stream));
+  }
+  launch_patch_apply(h->fp32(), d.J, d.order, d.pptr, d.pdofs, d.inv_off, d.inv, t, d.delta, h->stream);
+  check_launch();
+  if (timed) {
+    HIPCHECK(hipEventRecord(ev.second, h->stream));
+    h->ev_pending.push_back(ev);
+  }
+}
+
+// nsweeps of x <- x + omega W sum_i R_i^T K_i^{-1} R_i (b - K x); if x_zero the
+// first residual is b itself (x = 0) and the first update overwrites x.
+void smooth(vk_hierarchy* h, int l, const double* b, double* x, int nsweeps, bool x_zero) {
+  DevLevel& d = h->D[l];
+  const hipStream_t s = h->stream;
+  for (int it = 0; it < nsweeps; ++it) {
+    const bool first_zero = x_zero && it == 0;
+    const double* t = b;
+    if (!first_zero) {
+      launch_csr(1, d.N, d.mean_row, d.rowptr, d.col, d.val, x, b, d.t, s);
+      t = d.t;
+    }
+    patch_apply(h, l, t);
+    if (first_zero) launch_scatter_set(h->fp32(), d.N, d.dptr, d.dslot, d.delta, d.scale, x, s);
+    else launch_scatter(h->fp32(), d.N, d.dptr, d.dslot, d.delta, d.scale, x, s);
+    check_launch();
+  }
+  if (x_zero && nsweeps == 0) launch_fill(d.N, 0.0, x, s);
+}
+
+// e = V-cycle(level l) applied to r, zero initial guess
+void vcycle(vk_hierarchy* h, int l, const double* r, double* e, int nu_pre, int nu_post) {
+  DevLevel& d = h->D[l];
+  const hipStream_t s = h->stream;
+  if (l == 0) {
+    launch_dense_gemv(d.N, d.M, r, e, s);
+    check_launch();
+    return;
+  }
+  DevLevel& c = h->D[l - 1];
+  smooth(h, l, r, e, nu_pre, true);
+  launch_csr(1, d.N, d.mean_row, d.rowptr, d.col, d.val, e, r, d.t, s);        // t = r - K e
+  launch_csr(0, c.N, d.pt_mean, d.ptrow, d.ptcol, d.ptval, d.t, nullptr, c.b, s);  // r_c = P^T t
+  check_launch();
+  vcycle(h, l - 1, c.b, c.x, nu_pre, nu_post);
+  launch_csr(2, d.N, d.p_mean, d.prow, d.pcol, d.pval, c.x, nullptr, e, s);     // e += P e_c
+  check_launch();
+  smooth(h, l, r, e, nu_post, false);
+}
+
+double dot_host(vk_hierarchy* h, int n, const double* a, const double* b) {
+  launch_multidot(n, 1, a, 0, b, h->partial, h->small, h->stream);
+  check_launch();
+  double v;
+  HIPCHECK(hipMemcpyAsync(&v, h->small, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  return v;
+}
+
+void collect_timing(vk_hierarchy* h) {
+  for (auto& ev : h->ev_pending) {
+    float ms = 0.f;
+    HIPCHECK(hipEventSynchronize(ev.second));
+    HIPCHECK(hipEventElapsedTime(&ms, ev.first, ev.second));
+    h->t_ms += ms;
+    h->t_launches += 1;
+    h->ev_free.push_back(ev);
+  }
+  h->ev_pending.clear();
+}
+
+// FGMRES(m) preconditioned by one V-cycle (right preconditioning, stored Z).
+vk_status fgmres(vk_hierarchy* h, const double* b_in, double* x, const vk_solve_opts& o, vk_solve_info* info) {
+  const int N = h->H.back().N;
+  const int Lf = h->L() - 1;
+  const int nvel = h->H.back().nvel;
+  const double zv = 1.0 / std::sqrt((double)h->H.back().npres);
+  const hipStream_t s = h->stream;
+  DevLevel& F = h->D[Lf];
+  const int m = o.restart;
+  // consistent right-hand side: remove the constant-pressure component
+  launch_copy(N, b_in, h->bb, s);
+  launch_project(N, nvel, zv, h->bb, h->partial, s);
+  check_launch();
+  const double bnorm = std::sqrt(dot_host(h, N, h->bb, h->bb));
+  require(std::isfinite(bnorm), VK_ENAN, "right-hand side is not finite");
+  launch_fill(N, 0.0, x, s);
+  int its = 0;
+  bool converged = false;
+  if (info && info->h_history) info->h_history[0] = bnorm;
+  if (bnorm == 0.0) {
+    if (info) { info->iterations = 0; info->converged = 1; info->rel_residual = 0.0; }
+    return VK_OK;
+  }
+  launch_copy(N, h->bb, h->r, s);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hh(3 * (m + 2));
+  double beta = bnorm;
+  while (true) {
+    beta = std::sqrt(dot_host(h, N, h->r, h->r));
+    require(std::isfinite(beta), VK_ENAN, "residual is not finite");
+    if (beta <= o.rtol * bnorm) { converged = true; break; }
+    if (its >= o.maxit) break;
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    launch_div(N, h->r, beta, h->V, s);
+    int jlast = -1;
+    for (int j = 0; j < m; ++j) {
+      double* vj = h->V + (size_t)j * N;
+      double* zj = h->Z + (size_t)j * N;
+      double* w = h->V + (size_t)(j + 1) * N;
+      vcycle(h, Lf, vj, zj, o.nu_pre, o.nu_post);
+      launch_csr(0, N, F.mean_row, F.rowptr, F.col, F.val, zj, nullptr, w, s);
+      // CGS2: two classical Gram-Schmidt passes against v_0..v_j
+      launch_multidot(N, j + 1, h->V, N, w, h->partial, h->small, s);
+      launch_multiaxpy(N, j + 1, -1.0, h->V, N, h->small, w, s);
+      launch_multidot(N, j + 1, h->V, N, w, h->partial, h->small + (m + 2), s);
+      launch_multiaxpy(N, j + 1, -1.0, h->V, N, h->small + (m + 2), w, s);
+      launch_multidot(N, 1, w, 0, w, h->partial, h->small + 2 * (m + 2), s);
+      check_launch();
+      HIPCHECK(hipMemcpyAsync(hh.data(), h->small, 3 * (m + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      const double hn = std::sqrt(hh[2 * (m + 2)]);
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[(m + 2) + i];
+      H[(size_t)(j + 1) * m + j] = hn;
+      require(std::isfinite(hn), VK_ENAN, "Arnoldi breakdown to a non-finite value");
+      if (hn > 0.0) launch_div(N, w, hn, w, s);
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], c2 = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * c2;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c2;
+      }
+      const double a = H[(size_t)j * m + j], c2 = H[(size_t)(j + 1) * m + j];
+      const double den = std::hypot(a, c2);
+      cs[j] = a / den;
+      sn[j] = c2 / den;
+      H[(size_t)j * m + j] = den;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++its;
+      jlast = j;
+      if (info && info->h_history) info->h_history[its] = std::fabs(g[j + 1]);
+      if (std::fabs(g[j + 1]) <= o.rtol * bnorm || its >= o.maxit || hn == 0.0) break;
+    }
+    const int nk = jlast + 1;
+    h->ybuf.assign(nk, 0.0);
+    for (int i = nk - 1; i >= 0; --i) {
+      double sacc = g[i];
+      for (int q = i + 1; q < nk; ++q) sacc -= H[(size_t)i * m + q] * h->ybuf[q];
+      h->ybuf[i] = sacc / H[(size_t)i * m + i];
+    }
+    HIPCHECK(hipMemcpyAsync(h->ydev, h->ybuf.data(), nk * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_multiaxpy(N, nk, 1.0, h->Z, N, h->ydev, x, s);
+    launch_project(N, nvel, zv, x, h->partial, s);
+    launch_csr(1, N, F.mean_row, F.rowptr, F.col, F.val, x, h->bb, h->r, s);
+    check_launch();
+  }
+  if (info) {
+    info->iterations = its;
+    info->converged = converged ? 1 : 0;
+    info->rel_residual = beta / bnorm;
+  }
+  if (h->timing) collect_timing(h);
+  return converged ? VK_OK : VK_NOT_CONVERGED;
+}
+
+template <typename F>
+vk_status guarded(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return VK_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return VK_EINVAL;
+  }
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+const char* vk_last_error(void) { return g_err.c_str(); }
+
+vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts, vk_hierarchy** out) {
+  return guarded([&]() -> vk_status {
+    require(prob && opts && out, VK_EINVAL, "null argument");
+    const vk_problem& p = *prob;
+    require(p.dim == 2 || p.dim == 3, VK_EINVAL, "dim must be 2 or 3");
+    require(p.family == VK_TH, VK_EINVAL, "unsupported family");
+    require(p.k >= 2 && p.k <= (p.dim == 2 ? 6 : 2), VK_EINVAL, "unsupported order k");
+    require(p.n_coarse >= 1 && p.n_levels >= 2 && p.n_levels <= 12, VK_EINVAL, "bad hierarchy size");
+    require(p.viscosity > 0 && std::isfinite(p.viscosity), VK_EINVAL, "viscosity must be positive");
+    require(opts->omega > 0 && std::isfinite(opts->omega), VK_EINVAL, "omega must be positive");
+    require(opts->store == VK_STORE_FP64 || opts->store == VK_STORE_FP32, VK_EINVAL, "bad store");
+    require(opts->construct == VK_PATCH_COMPOSITE || (opts->construct == VK_PATCH_STAR && p.dim == 2), VK_EINVAL,
+            "bad patch construction");
+    const int nf = p.n_coarse << (p.n_levels - 1);
+    require((int64_t)nf * p.k <= (p.dim == 2 ? 4096 : 256), VK_EINVAL, "mesh too fine");
+    if (p.dim == 3) require(p.forcing == VK_F_CUBE_MMS, VK_EINVAL, "3D supports the cube field only");
+    else require(p.forcing == VK_F_BASELINE_MMS || p.forcing == VK_F_PAPER_MMS || p.forcing == VK_F_RANDOM,
+                 VK_EINVAL, "bad forcing");
+    auto h = std::make_unique<vk_hierarchy>();
+    h->pr.p = p;
+    if (p.forcing == VK_F_RANDOM) {
+      require(p.n_modes >= 1 && p.n_modes <= 64 && p.h_forcing_coeffs, VK_EINVAL, "random forcing needs coefficients");
+      h->pr.coeffs.assign(p.h_forcing_coeffs, p.h_forcing_coeffs + 2 * p.n_modes * p.n_modes);
+    }
+    h->pr.p.h_forcing_coeffs = nullptr;
+    h->opts = *opts;
+    h->H.resize(p.n_levels);
+    for (int l = 0; l < p.n_levels; ++l) {
+      LevelHost& L = h->H[l];
+      L.dim = p.dim;
+      L.k = p.k;
+      L.n = p.n_coarse << l;
+      build_level(L, h->pr, l == p.n_levels - 1);
+      if (l > 0) {
+        build_prolongation(h->H[l - 1], L);
+        build_patches(L, opts->construct, opts->omega, opts->store);
+        require(L.max_n <= 128, VK_EINVAL, "patches above 128 DoFs are not supported");
+      }
+    }
+    h->coarse_M = bordered_inverse(h->H[0]);
+    h->class_lists.assign(p.n_levels, {});
+    for (int l = 1; l < p.n_levels; ++l) {
+      const LevelHost& L = h->H[l];
+      std::vector<int>& cl = h->class_lists[l];
+      const int lim[3] = {32, 64, 128};
+      for (int c = 0; c < 3; ++c)
+        for (int i = 0; i + 1 < (int)L.pptr.size(); ++i) {
+          const int n = L.pptr[i + 1] - L.pptr[i];
+          if (n <= lim[c] && (c == 0 || n > lim[c - 1])) cl.push_back(i);
+        }
+    }
+    *out = h.release();
+    return VK_OK;
+  });
+}
+
+vk_status vk_hierarchy_destroy(vk_hierarchy* h) {
+  return guarded([&]() -> vk_status {
+    if (!h) return VK_OK;
+    for (auto& e : h->ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto& e : h->ev_pending) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    delete h;
+    return VK_OK;
+  });
+}
+
+vk_status vk_hierarchy_workspace_bytes(const vk_hierarchy* h, int max_restart, size_t* bytes) {
+  return guarded([&]() -> vk_status {
+    require(h && bytes, VK_EINVAL, "null argument");
+    require(max_restart >= 1 && max_restart <= 200, VK_EINVAL, "max_restart out of range");
+    vk_hierarchy tmp;  // sizing pass: pointers land in a scratch object
+    Carver cv(nullptr);
+    carve(h->H, h->fp32(), &tmp, cv, max_restart);
+    *bytes = cv.off + 256;
+    return VK_OK;
+  });
+}
+
+vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_restart, void* stream) {
+  return guarded([&]() -> vk_status {
+    require(h && d_ws, VK_EINVAL, "null argument");
+    require(((uintptr_t)d_ws & 255) == 0, VK_EINVAL, "workspace must be 256-byte aligned");
+    require(max_restart >= 1 && max_restart <= 200, VK_EINVAL, "max_restart out of range");
+    Carver dry(nullptr);
+    {
+      vk_hierarchy tmp;
+      carve(h->H, h->fp32(), &tmp, dry, max_restart);
+    }
+    require(bytes >= dry.off, VK_ENOMEM, "workspace too small");
+    h->stream = (hipStream_t)stream;
+    h->max_restart = max_restart;
+    Carver cv(d_ws);
+    carve(h->H, h->fp32(), h, cv, max_restart);
+    const hipStream_t s = h->stream;
+    for (int l = 0; l < h->L(); ++l) {
+      const LevelHost& L = h->H[l];
+      DevLevel& d = h->D[l];
+      up(d.rowptr, L.K.rowptr, s);
+      up(d.col, L.K.col, s);
+      up(d.val, L.K.val, s);
+      if (l == 0) {
+        up(d.M, h->coarse_M, s);
+        continue;
+      }
+      up(d.prow, L.P.rowptr, s);
+      up(d.pcol, L.P.col, s);
+      up(d.pval, L.P.val, s);
+      up(d.ptrow, L.PT.rowptr, s);
+      up(d.ptcol, L.PT.col, s);
+      up(d.ptval, L.PT.val, s);
+      up(d.pptr, L.pptr, s);
+      up(d.pdofs, L.pdofs, s);
+      up(d.dptr, L.dptr, s);
+      up(d.dslot, L.dslot, s);
+      up(d.order, L.order, s);
+      up(d.classes, h->class_lists[l], s);
+      up(d.inv_off, L.inv_off, s);
+      up(d.scale, L.scale, s);
+      const int lim[3] = {32, 64, 128};
+      for (int c = 0; c < 3; ++c) {
+        d.class_count[c] = 0;
+        for (int i = 0; i + 1 < (int)L.pptr.size(); ++i) {
+          const int n = L.pptr[i + 1] - L.pptr[i];
+          if (n <= lim[c] && (c == 0 || n > lim[c - 1])) d.class_count[c]++;
+        }
+      }
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+    h->bound = true;
+    h->ready = false;
+    return VK_OK;
+  });
+}
+
+vk_status vk_patches_setup(vk_hierarchy* h) {
+  return guarded([&]() -> vk_status {
+    require(h && h->bound, VK_ESTATE, "hierarchy is not bound");
+    const hipStream_t s = h->stream;
+    for (int l = 1; l < h->L(); ++l) {
+      DevLevel& d = h->D[l];
+      std::vector<int> init(1, INT_MAX);
+      HIPCHECK(hipMemcpyAsync(h->singular, init.data(), sizeof(int), hipMemcpyHostToDevice, s));
+      int first = 0;
+      const int lim[3] = {32, 64, 128};
+      for (int c = 0; c < 3; ++c) {
+        launch_gather_invert(lim[c], h->fp32(), d.class_count[c], d.classes + first, d.pptr, d.pdofs, d.rowptr,
+                             d.col, d.val, d.inv_off, d.inv, h->singular, s);
+        check_launch();
+        first += d.class_count[c];
+      }
+      int sing = INT_MAX;
+      HIPCHECK(hipMemcpyAsync(&sing, h->singular, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      require(sing == INT_MAX, VK_ESINGULAR,
+              "zero pivot in patch " + std::to_string(sing) + " on level " + std::to_string(l));
+    }
+    h->ready = true;
+    return VK_OK;
+  });
+}
+
+vk_status vk_level_info_get(const vk_hierarchy* h, int level, vk_level_info* info) {
+  return guarded([&]() -> vk_status {
+    require(h && info, VK_EINVAL, "null argument");
+    require_level(h, level, 0);
+    const LevelHost& L = h->H[level];
+    info->n = L.n;
+    info->n_free = L.N;
+    info->n_velocity = L.nvel;
+    info->nnz = L.K.nnz();
+    info->n_patches = level == 0 ? 0 : (int)L.pptr.size() - 1;
+    info->sum_n = level == 0 ? 0 : (int64_t)L.pdofs.size();
+    info->sum_n2 = level == 0 ? 0 : L.sum_n2;
+    info->max_n = level == 0 ? 0 : L.max_n;
+    info->p_nnz = level == 0 ? 0 : L.P.nnz();
+    return VK_OK;
+  });
+}
+
+vk_status vk_level_csr(const vk_hierarchy* h, int level, int* rp, int* col, double* val) {
+  return guarded([&]() -> vk_status {
+    require(h && rp && col && val, VK_EINVAL, "null argument");
+    require_level(h, level, 0);
+    const Csr& K = h->H[level].K;
+    std::copy(K.rowptr.begin(), K.rowptr.end(), rp);
+    std::copy(K.col.begin(), K.col.end(), col);
+    std::copy(K.val.begin(), K.val.end(), val);
+    return VK_OK;
+  });
+}
+
+vk_status vk_level_prolongation(const vk_hierarchy* h, int level, int* rp, int* col, double* val) {
+  return guarded([&]() -> vk_status {
+    require(h && rp && col && val, VK_EINVAL, "null argument");
+    require_level(h, level, 1);
+    const Csr& P = h->H[level].P;
+    std::copy(P.rowptr.begin(), P.rowptr.end(), rp);
+    std::copy(P.col.begin(), P.col.end(), col);
+    std::copy(P.val.begin(), P.val.end(), val);
+    return VK_OK;
+  });
+}
+
+vk_status vk_level_patches(const vk_hierarchy* h, int level, int* ptr, int* dofs) {
+  return guarded([&]() -> vk_status {
+    require(h && ptr && dofs, VK_EINVAL, "null argument");
+    require_level(h, level, 1);
+    const LevelHost& L = h->H[level];
+    std::copy(L.pptr.begin(), L.pptr.end(), ptr);
+    std::copy(L.pdofs.begin(), L.pdofs.end(), dofs);
+    return VK_OK;
+  });
+}
+
+vk_status vk_dof_coords(const vk_hierarchy* h, int level, double* xyz, int* kind) {
+  return guarded([&]() -> vk_status {
+    require(h && xyz && kind, VK_EINVAL, "null argument");
+    require_level(h, level, 0);
+    dof_coords(h->H[level], xyz, kind);
+    return VK_OK;
+  });
+}
+
+vk_status vk_rhs(const vk_hierarchy* h, double* hb) {
+  return guarded([&]() -> vk_status {
+    require(h && hb, VK_EINVAL, "null argument");
+    const LevelHost& L = h->H.back();
+    // consistent right-hand side: b - (z.b) z, z = constant pressure / sqrt(#pressure)
+    const double zv = 1.0 / std::sqrt((double)L.npres);
+    double zb = 0.0;
+    for (int i = L.nvel; i < L.N; ++i) zb += L.b[i] * zv;
+    for (int i = 0; i < L.N; ++i) hb[i] = i < L.nvel ? L.b[i] : L.b[i] - zb * zv;
+    return VK_OK;
+  });
+}
+
+vk_status vk_patch_gather(vk_hierarchy* h, int level, int first, int count, double* d_out) {
+  return guarded([&]() -> vk_status {
+    require(h && h->bound && d_out, VK_ESTATE, "hierarchy not bound or null output");
+    require_level(h, level, 1);
+    const LevelHost& L = h->H[level];
+    const int J = (int)L.pptr.size() - 1;
+    require(first >= 0 && count >= 0 && first + count <= J, VK_EINVAL, "patch range out of bounds");
+    if (count == 0) return VK_OK;
+    // the per-patch output offsets go to the FGMRES basis, unused outside a solve
+    std::vector<int64_t> off(count);
+    int64_t o = 0;
+    int nmax = 0;
+    for (int i = 0; i < count; ++i) {
+      const int n = L.pptr[first + i + 1] - L.pptr[first + i];
+      off[i] = o;
+      o += (int64_t)n * n;
+      nmax = std::max(nmax, n);
+    }
+    const size_t scratch_bytes = (size_t)(h->max_restart + 1) * h->H.back().N * sizeof(double);
+    require(off.size() * sizeof(int64_t) <= scratch_bytes, VK_ENOMEM, "too many patches for one gather call");
+    int64_t* d_off = (int64_t*)h->V;
+    HIPCHECK(hipMemcpyAsync(d_off, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, h->stream));
+    DevLevel& d = h->D[level];
+    launch_gather_dense(nmax, first, count, d.pptr, d.pdofs, d.rowptr, d.col, d.val, d_off, d_out, h->stream);
+    check_launch();
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return VK_OK;
+  });
+}
+
+vk_status vk_patch_inverse(vk_hierarchy* h, int level, int patch, double* d_out) {
+  return guarded([&]() -> vk_status {
+    require_ready(h);
+    require(d_out, VK_EINVAL, "null output");
+    require_level(h, level, 1);
+    const LevelHost& L = h->H[level];
+    require(patch >= 0 && patch + 1 < (int)L.pptr.size(), VK_EINVAL, "patch out of range");
+    const int n = L.pptr[patch + 1] - L.pptr[patch];
+    launch_copy_inverse(h->fp32(), n, h->D[level].inv, L.inv_off[patch], d_out, h->stream);
+    check_launch();
+    return VK_OK;
+  });
+}
+
+vk_status vk_spmv(vk_hierarchy* h, int level, const double* x, double* y) {
+  return guarded([&]() -> vk_status {
+    require(h && h->bound && x && y, VK_ESTATE, "hierarchy not bound or null vector");
+    require_level(h, level, 0);
+    DevLevel& d = h->D[level];
+    launch_csr(0, d.N, d.mean_row, d.rowptr, d.col, d.val, x, nullptr, y, h->stream);
+    check_launch();
+    return VK_OK;
+  });
+}
+
+vk_status vk_restrict(vk_hierarchy* h, int level, const double* rf, double* rc) {
+  return guarded([&]() -> vk_status {
+    require(h && h->bound && rf && rc, VK_ESTATE, "hierarchy not bound or null vector");
+    require_level(h, level, 1);
+    DevLevel& d = h->D[level];
+    launch_csr(0, h->D[level - 1].N, d.pt_mean, d.ptrow, d.ptcol, d.ptval, rf, nullptr, rc, h->stream);
+    check_launch();
+    return VK_OK;
+  });
+}
+
+vk_status vk_prolong_add(vk_hierarchy* h, int level, const double* ec, double* ef) {
+  return guarded([&]() -> vk_status {
+    require(h && h->bound && ec && ef, VK_ESTATE, "hierarchy not bound or null vector");
+    require_level(h, level, 1);
+    DevLevel& d = h->D[level];
+    launch_csr(2, d.N, d.p_mean, d.prow, d.pcol, d.pval, ec, nullptr, ef, h->stream);
+    check_launch();
+    return VK_OK;
+  });
+}
+
+vk_status vk_smooth(vk_hierarchy* h, int level, const double* b, double* x, int nsweeps) {
+  return guarded([&]() -> vk_status {
+    require_ready(h);
+    require(b && x && nsweeps >= 0, VK_EINVAL, "bad argument");
+    require_level(h, level, 1);
+    smooth(h, level, b, x, nsweeps, false);
+    return VK_OK;
+  });
+}
+
+vk_status vk_coarse_solve(vk_hierarchy* h, const double* r, double* e) {
+  return guarded([&]() -> vk_status {
+    require(h && h->bound && r && e, VK_ESTATE, "hierarchy not bound or null vector");
+    launch_dense_gemv(h->D[0].N, h->D[0].M, r, e, h->stream);
+    check_launch();
+    return VK_OK;
+  });
+}
+
+vk_status vk_vcycle(vk_hierarchy* h, const double* r, double* e, int nu_pre, int nu_post) {
+  return guarded([&]() -> vk_status {
+    require_ready(h);
+    require(r && e && nu_pre >= 0 && nu_post >= 0, VK_EINVAL, "bad argument");
+    vcycle(h, h->L() - 1, r, e, nu_pre, nu_post);
+    return VK_OK;
+  });
+}
+
+vk_status vk_solve(vk_hierarchy* h, const double* b, double* x, const vk_solve_opts* opts, vk_solve_info* info) {
+  return guarded([&]() -> vk_status {
+    require_ready(h);
+    require(b && x && opts, VK_EINVAL, "null argument");
+    require(opts->restart >= 1 && opts->restart <= h->max_restart, VK_EINVAL, "restart exceeds the bound basis");
+    require(opts->maxit >= 0 && opts->rtol >= 0 && opts->nu_pre >= 0 && opts->nu_post >= 0, VK_EINVAL,
+            "bad solve options");
+    return fgmres(h, b, x, *opts, info);
+  });
+}
+
+vk_status vk_kernel_timing(vk_hierarchy* h, int enable, int reset, int64_t* launches, double* total_ms) {
+  return guarded([&]() -> vk_status {
+    require(h, VK_EINVAL, "null hierarchy");
+    if (h->bound) {
+      HIPCHECK(hipStreamSynchronize(h->stream));
+      collect_timing(h);
+    }
+    if (launches) *launches = h->t_launches;
+    if (total_ms) *total_ms = h->t_ms;
+    if (reset) { h->t_launches = 0; h->t_ms = 0.0; }
+    h->timing = enable != 0;
+    return VK_OK;
+  });
+}
+
+}  // extern "C"

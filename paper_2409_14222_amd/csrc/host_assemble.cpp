@@ -1,0 +1,500 @@
+// Host-side assembly of one multigrid level: structured mesh, Taylor-Hood
+// DoF numbering, K = [A B^T; B 0] on the free DoFs, right-hand side with
+// Dirichlet lifting (Sec. 2 weak form, Sec. 3 per-level saddle-point
+// matrix), and the prolongation by nodal interpolation (Sec. 3, grid
+// transfers: natural embedding of the nested spaces).
+#include <algorithm>
+#include <cmath>
+
+#include "vk_internal.hpp"
+
+namespace vk {
+
+static const double PI = 3.14159265358979323846;
+
+int LevelHost::vel_dof(const int* G, int c) const {
+  const int M = k * n;
+  int idx = 0;
+  for (int d = dim - 1; d >= 0; --d) {
+    if (G[d] <= 0 || G[d] >= M) return -1;
+    idx = idx * (M - 1) + (G[d] - 1);
+  }
+  return dim * idx + c;
+}
+
+int LevelHost::pres_dof(const int* G) const {
+  const int M = (k - 1) * n;
+  int idx = 0;
+  for (int d = dim - 1; d >= 0; --d) idx = idx * (M + 1) + G[d];
+  return nvel + idx;
+}
+
+static void make_cells(LevelHost& L) {
+  const int n = L.n;
+  L.cells.clear();
+  if (L.dim == 2) {
+    // square (i,j) cut from top-left to bottom-right: (BL, BR, TL) and (TR, TL, BR)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        Cell lo = {{{i, j, 0}, {i + 1, j, 0}, {i, j + 1, 0}, {0, 0, 0}}};
+        Cell up = {{{i + 1, j + 1, 0}, {i, j + 1, 0}, {i + 1, j, 0}, {0, 0, 0}}};
+        L.cells.push_back(lo);
+        L.cells.push_back(up);
+      }
+  } else {
+    // six Kuhn tetrahedra per cube, one per ordering of the axes, all sharing
+    // the cube diagonal; orderings in lexicographic order of the permutation
+    static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    for (int l = 0; l < n; ++l)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i)
+          for (auto& p : perms) {
+            Cell c;
+            int v[3] = {i, j, l};
+            for (int d = 0; d < 3; ++d) c.v[0][d] = v[d];
+            for (int s = 0; s < 3; ++s) {
+              v[p[s]] += 1;
+              for (int d = 0; d < 3; ++d) c.v[s + 1][d] = v[d];
+            }
+            L.cells.push_back(c);
+          }
+  }
+}
+
+// exact velocity, forcing (returns dim components)
+static void field_u(const Problem& pr, const double* x, double* u) {
+  const double X = x[0], Y = x[1];
+  switch (pr.p.forcing) {
+    case VK_F_BASELINE_MMS:
+      u[0] = std::sin(PI * X) * std::sin(PI * Y);
+      u[1] = std::cos(PI * X) * std::cos(PI * Y);
+      break;
+    case VK_F_PAPER_MMS:
+      u[0] = std::sin(PI * X) * std::cos(PI * Y);
+      u[1] = -std::cos(PI * X) * std::sin(PI * Y);
+      break;
+    case VK_F_CUBE_MMS: {
+      const double Z = x[2];
+      u[0] = std::sin(PI * X) * std::cos(PI * Y) - std::sin(PI * X) * std::cos(PI * Z);
+      u[1] = std::sin(PI * Y) * std::cos(PI * Z) - std::cos(PI * X) * std::sin(PI * Y);
+      u[2] = std::sin(PI * Z) * std::cos(PI * X) - std::cos(PI * Y) * std::sin(PI * Z);
+      break;
+    }
+    default:
+      for (int c = 0; c < pr.p.dim; ++c) u[c] = 0.0;
+  }
+}
+
+static void field_f(const Problem& pr, const double* x, double* f) {
+  const double nu = pr.p.viscosity;
+  if (pr.p.forcing == VK_F_RANDOM) {
+    const int M = pr.p.n_modes;
+    for (int c = 0; c < 2; ++c) {
+      double s = 0.0;
+      for (int a = 1; a <= M; ++a)
+        for (int b = 1; b <= M; ++b)
+          s += pr.coeffs[(c * M + (a - 1)) * M + (b - 1)] * std::sin(a * PI * x[0]) * std::sin(b * PI * x[1]) /
+               (double)(a * a + b * b);
+      f[c] = s;
+    }
+    return;
+  }
+  // divergence-free eigenfunction fields with p = 0: f = -nu Laplace u = 2 nu pi^2 u
+  double u[3];
+  field_u(pr, x, u);
+  for (int c = 0; c < pr.p.dim; ++c) f[c] = 2.0 * nu * PI * PI * u[c];
+}
+
+// local P_kk node j of a cell -> global lattice point (units 1/(kk n))
+static inline void node_lattice(const Cell& c, const std::vector<int>& a, int dim, int* G) {
+  for (int d = 0; d < dim; ++d) {
+    int g = 0;
+    for (int i = 0; i <= dim; ++i) g += a[i] * c.v[i][d];
+    G[d] = g;
+  }
+}
+
+void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
+  const int dim = L.dim, k = L.k;
+  const double nu = pr.p.viscosity;
+  make_cells(L);
+  const int Mv = k * L.n, Mp = (k - 1) * L.n;
+  int nint = 1, np = 1;
+  for (int d = 0; d < dim; ++d) {
+    nint *= (Mv - 1);
+    np *= (Mp + 1);
+  }
+  L.nvel = dim * nint;
+  L.npres = np;
+  L.N = L.nvel + L.npres;
+
+  const Basis vb = make_basis(dim, k), pb = make_basis(dim, k - 1);
+  const int nbv = vb.size(), nbp = pb.size();
+  const int nlv = nbv * dim;
+  const SimplexRule rule = simplex_rule(dim, k + 3);
+  const int nq = rule.npts;
+
+  // local -> global DoFs of every cell
+  const int ncell = (int)L.cells.size();
+  std::vector<int> cvd((size_t)ncell * nlv), cpd((size_t)ncell * nbp);
+  for (int e = 0; e < ncell; ++e) {
+    int G[3];
+    for (int j = 0; j < nbv; ++j) {
+      node_lattice(L.cells[e], vb.nodes[j], dim, G);
+      for (int c = 0; c < dim; ++c) cvd[(size_t)e * nlv + j * dim + c] = L.vel_dof(G, c);
+    }
+    for (int j = 0; j < nbp; ++j) {
+      node_lattice(L.cells[e], pb.nodes[j], dim, G);
+      cpd[(size_t)e * nbp + j] = L.pres_dof(G);
+    }
+  }
+
+  // sparsity pattern: the element closure (all DoF pairs sharing a cell, no
+  // pressure-pressure pairs); rows collected through DoF -> cells lists
+  std::vector<std::vector<int>> dcells(L.N);
+  for (int e = 0; e < ncell; ++e) {
+    for (int j = 0; j < nlv; ++j) {
+      int d = cvd[(size_t)e * nlv + j];
+      if (d >= 0) dcells[d].push_back(e);
+    }
+    for (int j = 0; j < nbp; ++j) dcells[cpd[(size_t)e * nbp + j]].push_back(e);
+  }
+  Csr& K = L.K;
+  K.nrows = K.ncols = L.N;
+  K.rowptr.assign(L.N + 1, 0);
+  std::vector<int> tmp;
+  for (int r = 0; r < L.N; ++r) {
+    tmp.clear();
+    const bool rp = r >= L.nvel;
+    for (int e : dcells[r]) {
+      for (int j = 0; j < nlv; ++j) {
+        int d = cvd[(size_t)e * nlv + j];
+        if (d >= 0) tmp.push_back(d);
+      }
+      if (!rp)
+        for (int j = 0; j < nbp; ++j) tmp.push_back(cpd[(size_t)e * nbp + j]);
+    }
+    std::sort(tmp.begin(), tmp.end());
+    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+    K.col.insert(K.col.end(), tmp.begin(), tmp.end());
+    K.rowptr[r + 1] = (int)K.col.size();
+  }
+  K.val.assign(K.col.size(), 0.0);
+  dcells.clear();
+  dcells.shrink_to_fit();
+
+  auto addto = [&](int r, int c, double v) {
+    const int* b = K.col.data() + K.rowptr[r];
+    const int* e = K.col.data() + K.rowptr[r + 1];
+    const int* it = std::lower_bound(b, e, c);
+    K.val[K.rowptr[r] + (it - b)] += v;
+  };
+
+  // basis values and barycentric derivatives at the quadrature points (the
+  // same on every cell; the geometry enters through grad lambda)
+  std::vector<double> phv((size_t)nq * nbv), php((size_t)nq * nbp), dv((size_t)nq * nbv * (dim + 1));
+  for (int q = 0; q < nq; ++q) {
+    double kl[4], kl1[4];
+    for (int i = 0; i <= dim; ++i) {
+      kl[i] = k * rule.lam[q * (dim + 1) + i];
+      kl1[i] = (k - 1) * rule.lam[q * (dim + 1) + i];
+    }
+    vb.eval(kl, &phv[(size_t)q * nbv]);
+    pb.eval(kl1, &php[(size_t)q * nbp]);
+    vb.dlam(&rule.lam[q * (dim + 1)], &dv[(size_t)q * nbv * (dim + 1)]);
+  }
+
+  if (with_rhs) L.b.assign(L.N, 0.0);
+  std::vector<double> Aloc((size_t)nlv * nlv), Bloc((size_t)nbp * nlv), Floc(nlv), uD(nlv);
+  std::vector<double> gx((size_t)nbv * dim);
+  for (int e = 0; e < ncell; ++e) {
+    const Cell& C = L.cells[e];
+    // affine map x = x0 + J xi, J columns = (x_i - x_0), x = v / n
+    double J[3][3], Ji[3][3];
+    for (int d = 0; d < dim; ++d)
+      for (int i = 0; i < dim; ++i) J[d][i] = (double)(C.v[i + 1][d] - C.v[0][d]) / L.n;
+    double det;
+    if (dim == 2) {
+      det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      Ji[0][0] = J[1][1] / det; Ji[0][1] = -J[0][1] / det;
+      Ji[1][0] = -J[1][0] / det; Ji[1][1] = J[0][0] / det;
+    } else {
+      det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+            J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+      Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+      Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+      Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+      Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+      Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+      Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+      Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+      Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    }
+    const double adet = std::fabs(det);
+    // grad lambda_i (i >= 1) = row i-1 of J^{-1}; grad lambda_0 = -sum
+    double gl[4][3];
+    for (int d = 0; d < dim; ++d) {
+      double s = 0.0;
+      for (int i = 1; i <= dim; ++i) {
+        gl[i][d] = Ji[i - 1][d];
+        s += Ji[i - 1][d];
+      }
+      gl[0][d] = -s;
+    }
+    std::fill(Aloc.begin(), Aloc.end(), 0.0);
+    std::fill(Bloc.begin(), Bloc.end(), 0.0);
+    std::fill(Floc.begin(), Floc.end(), 0.0);
+    for (int q = 0; q < nq; ++q) {
+      const double w = rule.w[q] * adet;
+      const double* dq = &dv[(size_t)q * nbv * (dim + 1)];
+      for (int j = 0; j < nbv; ++j)
+        for (int d = 0; d < dim; ++d) {
+          double s = 0.0;
+          for (int i = 0; i <= dim; ++i) s += dq[j * (dim + 1) + i] * gl[i][d];
+          gx[j * dim + d] = s;
+        }
+      // A[(i,c),(j,d)] += w nu (delta_cd grad phi_i . grad phi_j + d_d phi_i d_c phi_j)
+      for (int i = 0; i < nbv; ++i)
+        for (int j = 0; j < nbv; ++j) {
+          double dot = 0.0;
+          for (int d = 0; d < dim; ++d) dot += gx[i * dim + d] * gx[j * dim + d];
+          for (int c = 0; c < dim; ++c)
+            for (int d = 0; d < dim; ++d) {
+              double v = gx[i * dim + d] * gx[j * dim + c];
+              if (c == d) v += dot;
+              Aloc[(size_t)(i * dim + c) * nlv + (j * dim + d)] += w * nu * v;
+            }
+        }
+      // B[q,(j,d)] += -w psi_q d_d phi_j
+      const double* pq = &php[(size_t)q * nbp];
+      for (int p = 0; p < nbp; ++p)
+        for (int j = 0; j < nbv; ++j)
+          for (int d = 0; d < dim; ++d) Bloc[(size_t)p * nlv + j * dim + d] -= w * pq[p] * gx[j * dim + d];
+      if (with_rhs) {
+        double x[3] = {0, 0, 0};
+        for (int d = 0; d < dim; ++d) {
+          double s = C.v[0][d] / (double)L.n;
+          for (int i = 1; i <= dim; ++i) s += J[d][i - 1] * rule.lam[q * (dim + 1) + i];
+          x[d] = s;
+        }
+        double f[3];
+        field_f(pr, x, f);
+        const double* vq = &phv[(size_t)q * nbv];
+        for (int i = 0; i < nbv; ++i)
+          for (int c = 0; c < dim; ++c) Floc[i * dim + c] += w * f[c] * vq[i];
+      }
+    }
+    const int* vd = &cvd[(size_t)e * nlv];
+    const int* pd = &cpd[(size_t)e * nbp];
+    // Dirichlet data: nodal values of the exact velocity at boundary nodes
+    if (with_rhs) {
+      for (int j = 0; j < nbv; ++j) {
+        if (vd[j * dim] >= 0) continue;
+        int G[3];
+        node_lattice(C, vb.nodes[j], dim, G);
+        double x[3];
+        for (int d = 0; d < dim; ++d) x[d] = (double)G[d] / (k * L.n);
+        field_u(pr, x, &uD[j * dim]);
+      }
+    }
+    for (int a = 0; a < nlv; ++a) {
+      const int r = vd[a];
+      if (r < 0) continue;
+      for (int c = 0; c < nlv; ++c)
+        if (vd[c] >= 0) addto(r, vd[c], Aloc[(size_t)a * nlv + c]);
+      for (int p = 0; p < nbp; ++p) {
+        addto(r, pd[p], Bloc[(size_t)p * nlv + a]);
+        addto(pd[p], r, Bloc[(size_t)p * nlv + a]);
+      }
+      if (with_rhs) {
+        double s = Floc[a];
+        for (int c = 0; c < nlv; ++c)
+          if (vd[c] < 0) s -= Aloc[(size_t)a * nlv + c] * uD[c];
+        L.b[r] += s;
+      }
+    }
+    if (with_rhs)
+      for (int p = 0; p < nbp; ++p) {
+        double s = 0.0;
+        for (int c = 0; c < nlv; ++c)
+          if (vd[c] < 0) s -= Bloc[(size_t)p * nlv + c] * uD[c];
+        L.b[pd[p]] += s;
+      }
+  }
+}
+
+// ---------------------------------------------------------------- prolongation
+// Fine lattice point G (units 1/(kk nf)), nf = 2 nc.  The containing coarse
+// cell is found from the structured mesh; barycentric coordinates are exact
+// multiples of 1/(2 kk), so kk * lambda is an exact half-integer and the
+// interpolation weights that vanish are exact zeros (dropped).
+static void locate(int dim, int nc, int kk, const int* G, Cell& cell, double* klam) {
+  const int span = 2 * kk;  // fine lattice points per coarse cell edge
+  int base[3], off[3];
+  for (int d = 0; d < dim; ++d) {
+    int i = G[d] / span;
+    if (i >= nc) i = nc - 1;
+    base[d] = i;
+    off[d] = G[d] - i * span;  // 0..span
+  }
+  if (dim == 2) {
+    const int i = base[0], j = base[1];
+    if (off[0] + off[1] <= span) {  // lower triangle (BL, BR, TL)
+      cell = {{{i, j, 0}, {i + 1, j, 0}, {i, j + 1, 0}, {0, 0, 0}}};
+      klam[0] = 0.5 * (span - off[0] - off[1]);
+      klam[1] = 0.5 * off[0];
+      klam[2] = 0.5 * off[1];
+    } else {  // upper triangle (TR, TL, BR)
+      cell = {{{i + 1, j + 1, 0}, {i, j + 1, 0}, {i + 1, j, 0}, {0, 0, 0}}};
+      klam[0] = 0.5 * (off[0] + off[1] - span);
+      klam[1] = 0.5 * (span - off[0]);
+      klam[2] = 0.5 * (span - off[1]);
+    }
+  } else {
+    // Kuhn tetrahedron of the axis ordering with off[p0] >= off[p1] >= off[p2]
+    int p[3] = {0, 1, 2};
+    std::stable_sort(p, p + 3, [&](int a, int b) { return off[a] > off[b]; });
+    int v[3] = {base[0], base[1], base[2]};
+    for (int d = 0; d < 3; ++d) cell.v[0][d] = v[d];
+    for (int s = 0; s < 3; ++s) {
+      v[p[s]] += 1;
+      for (int d = 0; d < 3; ++d) cell.v[s + 1][d] = v[d];
+    }
+    klam[0] = 0.5 * (span - off[p[0]]);
+    klam[1] = 0.5 * (off[p[0]] - off[p[1]]);
+    klam[2] = 0.5 * (off[p[1]] - off[p[2]]);
+    klam[3] = 0.5 * off[p[2]];
+  }
+}
+
+void build_prolongation(const LevelHost& C, LevelHost& F) {
+  const int dim = F.dim;
+  Csr P;
+  P.nrows = F.N;
+  P.ncols = C.N;
+  P.rowptr.assign(F.N + 1, 0);
+  std::vector<std::vector<std::pair<int, double>>> rows(F.N);
+  for (int part = 0; part < 2; ++part) {
+    const int kk = part == 0 ? F.k : F.k - 1;
+    const Basis cb = make_basis(dim, kk);
+    const int M = kk * F.n;
+    int total = 1;
+    for (int d = 0; d < dim; ++d) total *= (M + 1);
+    std::vector<double> phi(cb.size());
+    for (int idx = 0; idx < total; ++idx) {
+      int G[3] = {0, 0, 0}, r = idx;
+      for (int d = 0; d < dim; ++d) {
+        G[d] = r % (M + 1);
+        r /= (M + 1);
+      }
+      int frow0;
+      if (part == 0) {
+        frow0 = F.vel_dof(G, 0);
+        if (frow0 < 0) continue;
+      } else {
+        frow0 = F.pres_dof(G);
+      }
+      Cell cell;
+      double klam[4];
+      locate(dim, C.n, kk, G, cell, klam);
+      cb.eval(klam, phi.data());
+      for (int j = 0; j < cb.size(); ++j) {
+        if (phi[j] == 0.0) continue;
+        int CG[3];
+        node_lattice(cell, cb.nodes[j], dim, CG);
+        if (part == 0) {
+          if (C.vel_dof(CG, 0) < 0) continue;
+          for (int c = 0; c < dim; ++c) rows[frow0 + c].push_back({C.vel_dof(CG, c), phi[j]});
+        } else {
+          rows[frow0].push_back({C.pres_dof(CG), phi[j]});
+        }
+      }
+    }
+  }
+  for (int r = 0; r < F.N; ++r) {
+    auto& v = rows[r];
+    std::sort(v.begin(), v.end());
+    for (auto& e : v) {
+      P.col.push_back(e.first);
+      P.val.push_back(e.second);
+    }
+    P.rowptr[r + 1] = (int)P.col.size();
+  }
+  F.P = std::move(P);
+  F.PT = transpose(F.P);
+}
+
+void dof_coords(const LevelHost& L, double* xyz, int* kind) {
+  const int dim = L.dim, Mv = L.k * L.n, Mp = (L.k - 1) * L.n;
+  const int nint = L.nvel / dim;
+  for (int idx = 0; idx < nint; ++idx) {
+    int r = idx;
+    double x[3];
+    for (int d = 0; d < dim; ++d) {
+      x[d] = (double)(r % (Mv - 1) + 1) / Mv;
+      r /= (Mv - 1);
+    }
+    for (int c = 0; c < dim; ++c) {
+      for (int d = 0; d < dim; ++d) xyz[(size_t)(dim * idx + c) * dim + d] = x[d];
+      kind[dim * idx + c] = c;
+    }
+  }
+  for (int idx = 0; idx < L.npres; ++idx) {
+    int r = idx;
+    for (int d = 0; d < dim; ++d) {
+      xyz[(size_t)(L.nvel + idx) * dim + d] = (double)(r % (Mp + 1)) / Mp;
+      r /= (Mp + 1);
+    }
+    kind[L.nvel + idx] = dim;
+  }
+}
+
+// ---------------------------------------------------------------- coarsest level
+std::vector<double> bordered_inverse(const LevelHost& L) {
+  const int N = L.N, M = N + 1;
+  std::vector<double> A((size_t)M * M, 0.0);
+  for (int r = 0; r < N; ++r)
+    for (int q = L.K.rowptr[r]; q < L.K.rowptr[r + 1]; ++q) A[(size_t)r * M + L.K.col[q]] = L.K.val[q];
+  const double zv = 1.0 / std::sqrt((double)L.npres);
+  for (int r = L.nvel; r < N; ++r) {
+    A[(size_t)r * M + N] = zv;
+    A[(size_t)N * M + r] = zv;
+  }
+  // Gauss-Jordan inversion with partial pivoting (row swaps undone as column
+  // swaps at the end)
+  std::vector<int> perm(M);
+  for (int c = 0; c < M; ++c) {
+    int p = c;
+    double best = std::fabs(A[(size_t)c * M + c]);
+    for (int r = c + 1; r < M; ++r) {
+      double v = std::fabs(A[(size_t)r * M + c]);
+      if (v > best) { best = v; p = r; }
+    }
+    require(best > 0.0, VK_ESINGULAR, "coarsest bordered matrix is singular");
+    perm[c] = p;
+    if (p != c)
+      for (int j = 0; j < M; ++j) std::swap(A[(size_t)c * M + j], A[(size_t)p * M + j]);
+    const double piv = A[(size_t)c * M + c];
+    A[(size_t)c * M + c] = 1.0;
+    for (int j = 0; j < M; ++j) A[(size_t)c * M + j] /= piv;
+    for (int r = 0; r < M; ++r) {
+      if (r == c) continue;
+      const double f = A[(size_t)r * M + c];
+      if (f == 0.0) continue;
+      A[(size_t)r * M + c] = 0.0;
+      double* ar = &A[(size_t)r * M];
+      const double* ac = &A[(size_t)c * M];
+      for (int j = 0; j < M; ++j) ar[j] -= f * ac[j];
+    }
+  }
+  for (int c = M - 1; c >= 0; --c)
+    if (perm[c] != c)
+      for (int r = 0; r < M; ++r) std::swap(A[(size_t)r * M + c], A[(size_t)r * M + perm[c]]);
+  std::vector<double> out((size_t)N * N);
+  for (int r = 0; r < N; ++r)
+    for (int c = 0; c < N; ++c) out[(size_t)r * N + c] = A[(size_t)r * M + c];
+  return out;
+}
+
+}  // namespace vk

@@ -1,0 +1,150 @@
+// Host-side finite-element building blocks: quadrature on simplices and the
+// equispaced Lagrange basis in barycentric form (Sec. 2, Taylor-Hood spaces).
+#include <cmath>
+
+#include "vk_internal.hpp"
+
+namespace vk {
+
+// Gauss-Legendre nodes/weights on [0,1] by Newton iteration on the Legendre
+// polynomial P_q (three-term recurrence), started from the Chebyshev-like guess
+// cos(pi (i + 3/4) / (q + 1/2)).
+static void gauss_legendre01(int q, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(q, 0.0);
+  w.assign(q, 0.0);
+  for (int i = 0; i < q; ++i) {
+    double t = std::cos(M_PI * (i + 0.75) / (q + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int m = 2; m <= q; ++m) {
+        double p2 = ((2.0 * m - 1.0) * t * p1 - (m - 1.0) * p0) / m;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (q == 1) { p1 = t; p0 = 1.0; }
+      dp = q * (t * p1 - p0) / (t * t - 1.0);
+      double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    // recompute the derivative at the converged root
+    double p0 = 1.0, p1 = t;
+    for (int m = 2; m <= q; ++m) {
+      double p2 = ((2.0 * m - 1.0) * t * p1 - (m - 1.0) * p0) / m;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (q == 1) { p1 = t; p0 = 1.0; }
+    dp = q * (t * p1 - p0) / (t * t - 1.0);
+    // map from [-1,1] (descending roots) to [0,1] ascending
+    x[q - 1 - i] = 0.5 * (t + 1.0);
+    w[q - 1 - i] = 1.0 / ((1.0 - t * t) * dp * dp);  // = 0.5 * 2 / ((1-t^2) P'^2)
+  }
+}
+
+SimplexRule simplex_rule(int dim, int q) {
+  std::vector<double> g, gw;
+  gauss_legendre01(q, g, gw);
+  SimplexRule r;
+  r.dim = dim;
+  if (dim == 2) {
+    for (int i = 0; i < q; ++i)
+      for (int j = 0; j < q; ++j) {
+        double s = g[i], t = g[j];
+        double x = s, y = t * (1.0 - s);
+        r.lam.insert(r.lam.end(), {1.0 - x - y, x, y});
+        r.w.push_back(gw[i] * gw[j] * (1.0 - s));
+      }
+  } else {
+    for (int i = 0; i < q; ++i)
+      for (int j = 0; j < q; ++j)
+        for (int l = 0; l < q; ++l) {
+          double s = g[i], t = g[j], u = g[l];
+          double x = s, y = t * (1.0 - s), z = u * (1.0 - s) * (1.0 - t);
+          r.lam.insert(r.lam.end(), {1.0 - x - y - z, x, y, z});
+          r.w.push_back(gw[i] * gw[j] * gw[l] * (1.0 - s) * (1.0 - s) * (1.0 - t));
+        }
+  }
+  r.npts = (int)r.w.size();
+  return r;
+}
+
+Basis make_basis(int dim, int k) {
+  Basis b;
+  b.dim = dim;
+  b.k = k;
+  // all multi-indices (a_0..a_dim) with sum k
+  std::vector<int> a(dim + 1, 0);
+  if (dim == 2) {
+    for (int a1 = 0; a1 <= k; ++a1)
+      for (int a2 = 0; a1 + a2 <= k; ++a2) b.nodes.push_back({k - a1 - a2, a1, a2});
+  } else {
+    for (int a1 = 0; a1 <= k; ++a1)
+      for (int a2 = 0; a1 + a2 <= k; ++a2)
+        for (int a3 = 0; a1 + a2 + a3 <= k; ++a3) b.nodes.push_back({k - a1 - a2 - a3, a1, a2, a3});
+  }
+  return b;
+}
+
+// L_m(t) with s = k t given: prod_{j<m} (s - j) / (j + 1)
+static inline double lagr(int m, double s) {
+  double v = 1.0;
+  for (int j = 0; j < m; ++j) v *= (s - j) / (j + 1);
+  return v;
+}
+
+// d/dt L_m(t) = sum_j k/(j+1) prod_{j' != j} (s - j')/(j'+1)
+static inline double dlagr(int m, double s, int k) {
+  double d = 0.0;
+  for (int j = 0; j < m; ++j) {
+    double v = (double)k / (j + 1);
+    for (int jj = 0; jj < m; ++jj)
+      if (jj != j) v *= (s - jj) / (jj + 1);
+    d += v;
+  }
+  return d;
+}
+
+void Basis::eval(const double* klam, double* phi) const {
+  for (int j = 0; j < size(); ++j) {
+    double v = 1.0;
+    for (int i = 0; i <= dim; ++i) v *= lagr(nodes[j][i], klam[i]);
+    phi[j] = v;
+  }
+}
+
+void Basis::dlam(const double* lam, double* d) const {
+  double s[4];
+  for (int i = 0; i <= dim; ++i) s[i] = k * lam[i];
+  for (int j = 0; j < size(); ++j) {
+    for (int i = 0; i <= dim; ++i) {
+      double v = dlagr(nodes[j][i], s[i], k);
+      for (int i2 = 0; i2 <= dim; ++i2)
+        if (i2 != i) v *= lagr(nodes[j][i2], s[i2]);
+      d[j * (dim + 1) + i] = v;
+    }
+  }
+}
+
+Csr transpose(const Csr& a) {
+  Csr t;
+  t.nrows = a.ncols;
+  t.ncols = a.nrows;
+  t.rowptr.assign(t.nrows + 1, 0);
+  for (int c : a.col) t.rowptr[c + 1]++;
+  for (int i = 0; i < t.nrows; ++i) t.rowptr[i + 1] += t.rowptr[i];
+  t.col.resize(a.col.size());
+  t.val.resize(a.val.size());
+  std::vector<int> pos(t.rowptr.begin(), t.rowptr.end() - 1);
+  for (int r = 0; r < a.nrows; ++r)
+    for (int q = a.rowptr[r]; q < a.rowptr[r + 1]; ++q) {
+      int c = a.col[q];
+      t.col[pos[c]] = r;
+      t.val[pos[c]] = a.val[q];
+      pos[c]++;
+    }
+  return t;
+}
+
+}  // namespace vk

@@ -1,0 +1,495 @@
+// gfx950 kernels of the matrix-full additive Vanka multigrid path.
+//
+// Wavefronts are 64 lanes.  Every reduction has a fixed order (no floating
+// point atomics), so results are bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace vk {
+
+// ============================================================================
+// CSR products: y = A x, y = b - A x, y += A x.  A group of LANES lanes owns
+// one row; lanes stride over the row's entries (coalesced col/val loads) and
+// the partial sums are combined by an xor butterfly inside the group.
+// ============================================================================
+template <int LANES, int MODE>
+__global__ void __launch_bounds__(256) csr_kernel(int nrows, const int* __restrict__ rowptr,
+                                                  const int* __restrict__ col, const double* __restrict__ val,
+                                                  const double* __restrict__ x, const double* __restrict__ b,
+                                                  double* __restrict__ y) {
+  const int row = (int)((blockIdx.x * 256u + threadIdx.x) / LANES);
+  const int lane = threadIdx.x & (LANES - 1);
+  if (row >= nrows) return;  // uniform over the LANES-group
+  const int s = rowptr[row], e = rowptr[row + 1];
+  double acc = 0.0;
+  for (int q = s + lane; q < e; q += LANES) acc += val[q] * x[col[q]];
+#pragma unroll
+  for (int off = LANES / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LANES);
+  if (lane == 0) {
+    if (MODE == 0) y[row] = acc;
+    else if (MODE == 1) y[row] = b[row] - acc;
+    else y[row] += acc;
+  }
+}
+
+template <int LANES>
+static void csr_dispatch(int mode, int nrows, const int* rp, const int* c, const double* v, const double* x,
+                         const double* b, double* y, hipStream_t s) {
+  const int64_t threads = (int64_t)nrows * LANES;
+  const int grid = (int)((threads + 255) / 256);
+  if (grid == 0) return;
+  if (mode == 0) csr_kernel<LANES, 0><<<grid, 256, 0, s>>>(nrows, rp, c, v, x, b, y);
+  else if (mode == 1) csr_kernel<LANES, 1><<<grid, 256, 0, s>>>(nrows, rp, c, v, x, b, y);
+  else csr_kernel<LANES, 2><<<grid, 256, 0, s>>>(nrows, rp, c, v, x, b, y);
+}
+
+void launch_csr(int mode, int nrows, double mean_row, const int* rp, const int* c, const double* v,
+                const double* x, const double* b, double* y, hipStream_t s) {
+  if (mean_row <= 6) csr_dispatch<4>(mode, nrows, rp, c, v, x, b, y, s);
+  else if (mean_row <= 12) csr_dispatch<8>(mode, nrows, rp, c, v, x, b, y, s);
+  else if (mean_row <= 28) csr_dispatch<16>(mode, nrows, rp, c, v, x, b, y, s);
+  else if (mean_row <= 80) csr_dispatch<32>(mode, nrows, rp, c, v, x, b, y, s);
+  else csr_dispatch<64>(mode, nrows, rp, c, v, x, b, y, s);
+}
+
+// ============================================================================
+// Patch gather: K_i[l, m] = K[I_i[l], I_i[m]] into an LDS tile (column-major,
+// leading dimension n).  Each wave walks whole CSR rows of the patch's DoFs;
+// the column of every entry is located in the (ascending) DoF list by binary
+// search, entries outside the patch are skipped.
+// ============================================================================
+__device__ inline void gather_tile(int n, const int* __restrict__ Ii, const int* __restrict__ rowptr,
+                                   const int* __restrict__ col, const double* __restrict__ val, double* T) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
+  for (int l = wave; l < n; l += nwaves) {
+    const int g = Ii[l];
+    const int s = rowptr[g], e = rowptr[g + 1];
+    for (int q = s + lane; q < e; q += 64) {
+      const int c = col[q];
+      int lo = 0, hi = n;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (Ii[mid] < c) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < n && Ii[lo] == c) T[lo * n + l] = val[q];
+    }
+  }
+}
+
+// ============================================================================
+// Batched Gauss-Jordan inversion with partial pivoting, one 256-thread
+// workgroup per patch, tile resident in LDS (NMAX = 128: 128 KiB of the
+// 160 KiB LDS of a gfx950 CU).  The pivot is the largest |a| in the column
+// (ties -> lowest row), found by a wave-wide xor butterfly.  Row swaps are
+// undone as column swaps at the end.
+// ============================================================================
+template <int NMAX, typename TS>
+__global__ void __launch_bounds__(256) gather_invert_kernel(const int* __restrict__ list, const int* __restrict__ pptr,
+                                                            const int* __restrict__ pdofs,
+                                                            const int* __restrict__ rowptr,
+                                                            const int* __restrict__ col,
+                                                            const double* __restrict__ val,
+                                                            const int64_t* __restrict__ inv_off, TS* __restrict__ inv,
+                                                            int* __restrict__ singular) {
+  __shared__ double T[NMAX * NMAX];
+  __shared__ int Ii[NMAX];
+  __shared__ double colk[NMAX];
+  __shared__ int perm[NMAX];
+  __shared__ int piv_s, sing_s;
+  const int p = list[blockIdx.x];
+  const int base = pptr[p];
+  const int n = pptr[p + 1] - base;
+  const int tid = threadIdx.x;
+  const int nn = n * n;
+  if (n > NMAX || n <= 0) return;  // the host sorts patches into size classes; never taken
+  for (int i = tid; i < n; i += 256) Ii[i] = pdofs[base + i];
+  for (int e = tid; e < nn; e += 256) T[e] = 0.0;
+  if (tid == 0) sing_s = 0;
+  __syncthreads();
+  gather_tile(n, Ii, rowptr, col, val, T);
+  __syncthreads();
+
+  const int wave = tid >> 6, lane = tid & 63;
+  // (i, j) walk of the flattened tile e = tid + 256 t, column-major
+  const int dj = 256 / n, di = 256 - dj * n;
+  for (int k = 0; k < n; ++k) {
+    if (wave == 0) {
+      double best = -1.0;
+      int bi = n;
+      for (int i = k + lane; i < n; i += 64) {
+        const double v = fabs(T[k * n + i]);
+        if (v > best) { best = v; bi = i; }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) {
+        piv_s = bi;
+        if (!(best > 0.0) || bi >= n) sing_s = 1;
+      }
+    }
+    __syncthreads();
+    if (sing_s) break;
+    const int pr = piv_s;
+    if (pr != k)
+      for (int j = tid; j < n; j += 256) {
+        const double a = T[j * n + k];
+        T[j * n + k] = T[j * n + pr];
+        T[j * n + pr] = a;
+      }
+    if (tid == 0) perm[k] = pr;
+    __syncthreads();
+    const double piv = T[k * n + k];
+    for (int i = tid; i < n; i += 256) colk[i] = T[k * n + i];
+    __syncthreads();
+    for (int j = tid; j < n; j += 256) T[j * n + k] = (j == k ? 1.0 : T[j * n + k]) / piv;
+    __syncthreads();
+    int i = tid % n, j = tid / n;
+    for (int e = tid; e < nn; e += 256) {
+      if (i != k) {
+        const double a = (j == k) ? 0.0 : T[e];
+        T[e] = a - colk[i] * T[j * n + k];
+      }
+      i += di;
+      j += dj;
+      if (i >= n) { i -= n; j += 1; }
+    }
+    __syncthreads();
+  }
+  if (sing_s) {
+    if (tid == 0) atomicMin(singular, p);
+    return;
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int pr = perm[k];
+    if (pr != k)
+      for (int i = tid; i < n; i += 256) {
+        const double a = T[k * n + i];
+        T[k * n + i] = T[pr * n + i];
+        T[pr * n + i] = a;
+      }
+    __syncthreads();
+  }
+  constexpr int RPL = 16 / sizeof(TS);
+  const int ld = (n + RPL - 1) / RPL * RPL;
+  TS* out = inv + inv_off[p];
+  for (int e = tid; e < ld * n; e += 256) {
+    const int jj = e / ld, ii = e - jj * ld;
+    out[e] = ii < n ? (TS)T[jj * n + ii] : (TS)0;
+  }
+}
+
+template <int NMAX>
+static void gather_invert_dispatch(bool fp32, int count, const int* list, const int* pptr, const int* pdofs,
+                                   const int* rowptr, const int* col, const double* val, const int64_t* inv_off,
+                                   void* inv, int* singular, hipStream_t s) {
+  if (fp32)
+    gather_invert_kernel<NMAX, float><<<count, 256, 0, s>>>(list, pptr, pdofs, rowptr, col, val, inv_off,
+                                                            (float*)inv, singular);
+  else
+    gather_invert_kernel<NMAX, double><<<count, 256, 0, s>>>(list, pptr, pdofs, rowptr, col, val, inv_off,
+                                                             (double*)inv, singular);
+}
+
+void launch_gather_invert(int nmax, bool fp32, int count, const int* list, const int* pptr, const int* pdofs,
+                          const int* rowptr, const int* col, const double* val, const int64_t* inv_off, void* inv,
+                          int* singular, hipStream_t s) {
+  if (count <= 0) return;
+  if (nmax <= 32) gather_invert_dispatch<32>(fp32, count, list, pptr, pdofs, rowptr, col, val, inv_off, inv, singular, s);
+  else if (nmax <= 64) gather_invert_dispatch<64>(fp32, count, list, pptr, pdofs, rowptr, col, val, inv_off, inv, singular, s);
+  else gather_invert_dispatch<128>(fp32, count, list, pptr, pdofs, rowptr, col, val, inv_off, inv, singular, s);
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(256) gather_dense_kernel(int first, const int* __restrict__ pptr,
+                                                           const int* __restrict__ pdofs,
+                                                           const int* __restrict__ rowptr,
+                                                           const int* __restrict__ col,
+                                                           const double* __restrict__ val,
+                                                           const int64_t* __restrict__ out_off,
+                                                           double* __restrict__ out) {
+  __shared__ double T[NMAX * NMAX];
+  __shared__ int Ii[NMAX];
+  const int p = first + blockIdx.x;
+  const int base = pptr[p], n = pptr[p + 1] - base;
+  if (n > NMAX) return;  // the host picks NMAX >= every size in the range; never taken
+  for (int i = threadIdx.x; i < n; i += 256) Ii[i] = pdofs[base + i];
+  for (int e = threadIdx.x; e < n * n; e += 256) T[e] = 0.0;
+  __syncthreads();
+  gather_tile(n, Ii, rowptr, col, val, T);
+  __syncthreads();
+  double* o = out + out_off[blockIdx.x];
+  for (int e = threadIdx.x; e < n * n; e += 256) o[e] = T[e];
+}
+
+void launch_gather_dense(int nmax, int first, int count, const int* pptr, const int* pdofs, const int* rowptr,
+                         const int* col, const double* val, const int64_t* out_off, double* out, hipStream_t s) {
+  if (count <= 0) return;
+  if (nmax <= 32) gather_dense_kernel<32><<<count, 256, 0, s>>>(first, pptr, pdofs, rowptr, col, val, out_off, out);
+  else if (nmax <= 64) gather_dense_kernel<64><<<count, 256, 0, s>>>(first, pptr, pdofs, rowptr, col, val, out_off, out);
+  else gather_dense_kernel<128><<<count, 256, 0, s>>>(first, pptr, pdofs, rowptr, col, val, out_off, out);
+}
+
+template <typename TS>
+__global__ void copy_inverse_kernel(int n, const TS* __restrict__ inv, int64_t off, double* __restrict__ out) {
+  constexpr int RPL = 16 / sizeof(TS);
+  const int ld = (n + RPL - 1) / RPL * RPL;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n * n; e += gridDim.x * 256) {
+    const int j = e / n, i = e - j * n;
+    out[e] = (double)inv[off + (int64_t)j * ld + i];
+  }
+}
+
+void launch_copy_inverse(bool fp32, int n, const void* inv, int64_t off, double* out, hipStream_t s) {
+  const int grid = (n * n + 255) / 256;
+  if (fp32) copy_inverse_kernel<float><<<grid, 256, 0, s>>>(n, (const float*)inv, off, out);
+  else copy_inverse_kernel<double><<<grid, 256, 0, s>>>(n, (const double*)inv, off, out);
+}
+
+// ============================================================================
+// Additive patch apply: delta_i = K_i^{-1} t[I_i].  One wave per patch.  The
+// gathered residual sits in LDS; the inverse (column-major, ld rounded to
+// RPL rows) streams from HBM in 16-byte loads: lane (c, r) loads rows
+// [RPL r, RPL r + RPL) of columns c, c + C, c + 2C, ... so that one wave
+// instruction covers C consecutive columns contiguously.  The C partial
+// sums per row are combined in LDS in fixed order.
+// ============================================================================
+template <typename T> struct vec16;
+template <> struct vec16<double> { using type = double2; };
+template <> struct vec16<float> { using type = float4; };
+
+template <typename TS>
+__device__ inline void fma_vec(TS* acc, const typename vec16<TS>::type& a, TS x);
+template <>
+__device__ inline void fma_vec<double>(double* acc, const double2& a, double x) {
+  acc[0] += a.x * x;
+  acc[1] += a.y * x;
+}
+template <>
+__device__ inline void fma_vec<float>(float* acc, const float4& a, float x) {
+  acc[0] += a.x * x;
+  acc[1] += a.y * x;
+  acc[2] += a.z * x;
+  acc[3] += a.w * x;
+}
+
+template <typename TS>
+__global__ void __launch_bounds__(64) patch_apply_kernel(const int* __restrict__ order, const int* __restrict__ pptr,
+                                                         const int* __restrict__ pdofs,
+                                                         const int64_t* __restrict__ inv_off,
+                                                         const TS* __restrict__ inv, const double* __restrict__ t,
+                                                         TS* __restrict__ delta) {
+  constexpr int RPL = 16 / sizeof(TS);
+  using V = typename vec16<TS>::type;
+  __shared__ TS xs[256];
+  __shared__ TS red[64 * RPL];
+  const int p = order[blockIdx.x];
+  const int base = pptr[p];
+  const int n = pptr[p + 1] - base;
+  const int lane = threadIdx.x;
+  if (n > 256) return;  // the host rejects patches above 256 DoFs; never taken
+  for (int j = lane; j < n; j += 64) xs[j] = (TS)t[pdofs[base + j]];
+  __syncthreads();
+  const int ld = (n + RPL - 1) / RPL * RPL;
+  const TS* A = inv + inv_off[p];
+  for (int r0 = 0; r0 < ld; r0 += 64 * RPL) {
+    const int rows = min(ld - r0, 64 * RPL);
+    const int R = rows / RPL;
+    const int C = 64 / R;
+    const int r = lane % R, c = lane / R;
+    TS acc[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) acc[u] = (TS)0;
+    if (c < C) {
+      const TS* Ap = A + r0 + r * RPL;
+#pragma unroll 4
+      for (int j = c; j < n; j += C) {
+        const V a = *reinterpret_cast<const V*>(Ap + (int64_t)j * ld);
+        fma_vec<TS>(acc, a, xs[j]);
+      }
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) red[c * rows + r * RPL + u] = acc[u];
+    }
+    __syncthreads();
+    if (lane < R) {
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) {
+        TS s = red[lane * RPL + u];
+        for (int c2 = 1; c2 < C; ++c2) s += red[c2 * rows + lane * RPL + u];
+        const int row = r0 + lane * RPL + u;
+        if (row < n) delta[base + row] = s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+void launch_patch_apply(bool fp32, int J, const int* order, const int* pptr, const int* pdofs,
+                        const int64_t* inv_off, const void* inv, const double* t, void* delta, hipStream_t s) {
+  if (J <= 0) return;
+  if (fp32)
+    patch_apply_kernel<float><<<J, 64, 0, s>>>(order, pptr, pdofs, inv_off, (const float*)inv, t, (float*)delta);
+  else
+    patch_apply_kernel<double><<<J, 64, 0, s>>>(order, pptr, pdofs, inv_off, (const double*)inv, t,
+                                                (double*)delta);
+}
+
+// ============================================================================
+// Deterministic segmented scatter-add of the weighted corrections:
+// x[d] (+)= scale[d] * sum over the slots of d (ascending patch id).
+// ============================================================================
+template <typename TD, bool SET>
+__global__ void __launch_bounds__(256) scatter_kernel(int N, const int* __restrict__ dptr,
+                                                      const int* __restrict__ dslot, const TD* __restrict__ delta,
+                                                      const double* __restrict__ scale, double* __restrict__ x) {
+  const int d = blockIdx.x * 256 + threadIdx.x;
+  if (d >= N) return;
+  double s = 0.0;
+  for (int q = dptr[d]; q < dptr[d + 1]; ++q) s += (double)delta[dslot[q]];
+  if (SET) x[d] = scale[d] * s;
+  else x[d] += scale[d] * s;
+}
+
+void launch_scatter(bool fp32, int N, const int* dptr, const int* dslot, const void* delta, const double* scale,
+                    double* x, hipStream_t s) {
+  const int grid = (N + 255) / 256;
+  if (fp32) scatter_kernel<float, false><<<grid, 256, 0, s>>>(N, dptr, dslot, (const float*)delta, scale, x);
+  else scatter_kernel<double, false><<<grid, 256, 0, s>>>(N, dptr, dslot, (const double*)delta, scale, x);
+}
+
+void launch_scatter_set(bool fp32, int N, const int* dptr, const int* dslot, const void* delta,
+                        const double* scale, double* x, hipStream_t s) {
+  const int grid = (N + 255) / 256;
+  if (fp32) scatter_kernel<float, true><<<grid, 256, 0, s>>>(N, dptr, dslot, (const float*)delta, scale, x);
+  else scatter_kernel<double, true><<<grid, 256, 0, s>>>(N, dptr, dslot, (const double*)delta, scale, x);
+}
+
+// ============================================================================
+// Coarsest level: e = M r with the pre-inverted bordered system; one wave per row.
+// ============================================================================
+__global__ void __launch_bounds__(256) dense_gemv_kernel(int N, const double* __restrict__ M,
+                                                         const double* __restrict__ r, double* __restrict__ e) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= N) return;
+  const double* m = M + (int64_t)row * N;
+  double acc = 0.0;
+  for (int j = lane; j < N; j += 64) acc += m[j] * r[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) e[row] = acc;
+}
+
+void launch_dense_gemv(int N, const double* M, const double* r, double* e, hipStream_t s) {
+  dense_gemv_kernel<<<(N + 3) / 4, 256, 0, s>>>(N, M, r, e);
+}
+
+// ============================================================================
+// Krylov helpers with fixed-order two-stage reductions.
+// ============================================================================
+__device__ inline double block_sum256(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(256) multidot_partial_kernel(int n, const double* __restrict__ V, int64_t ldv,
+                                                               const double* __restrict__ w,
+                                                               double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const int v = blockIdx.y;
+  const double* x = V + (int64_t)v * ldv;
+  double acc = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += kReduceBlocks * 256) acc += x[i] * w[i];
+  const double s = block_sum256(acc, sh);
+  if (threadIdx.x == 0) partial[v * kReduceBlocks + blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) reduce_final_kernel(const double* __restrict__ partial, double* __restrict__ out) {
+  __shared__ double sh[256];
+  const double s = block_sum256(partial[blockIdx.x * kReduceBlocks + threadIdx.x], sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+void launch_multidot(int n, int nv, const double* V, int64_t ldv, const double* w, double* partial, double* out,
+                     hipStream_t s) {
+  static_assert(kReduceBlocks == 256, "final stage sums one partial per thread");
+  multidot_partial_kernel<<<dim3(kReduceBlocks, nv), 256, 0, s>>>(n, V, ldv, w, partial);
+  reduce_final_kernel<<<nv, 256, 0, s>>>(partial, out);
+}
+
+__global__ void __launch_bounds__(256) multiaxpy_kernel(int n, int nv, double sign, const double* __restrict__ V,
+                                                        int64_t ldv, const double* __restrict__ h,
+                                                        double* __restrict__ w) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int v = 0; v < nv; ++v) s += V[(int64_t)v * ldv + i] * h[v];
+  w[i] += sign * s;
+}
+
+void launch_multiaxpy(int n, int nv, double sign, const double* V, int64_t ldv, const double* h, double* w,
+                      hipStream_t s) {
+  multiaxpy_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, nv, sign, V, ldv, h, w);
+}
+
+__global__ void __launch_bounds__(256) div_kernel(int n, const double* x, double a, double* y) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = x[i] / a;
+}
+__global__ void __launch_bounds__(256) copy_kernel(int n, const double* __restrict__ x, double* __restrict__ y) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+__global__ void __launch_bounds__(256) fill_kernel(int n, double v, double* __restrict__ y) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+
+void launch_div(int n, const double* x, double alpha, double* y, hipStream_t s) {
+  div_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, x, alpha, y);
+}
+void launch_copy(int n, const double* x, double* y, hipStream_t s) {
+  copy_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, x, y);
+}
+void launch_fill(int n, double v, double* y, hipStream_t s) {
+  fill_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, v, y);
+}
+
+__global__ void __launch_bounds__(256) project_partial_kernel(int n, int p0, double zv, const double* __restrict__ x,
+                                                              double* __restrict__ partial) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = p0 + blockIdx.x * 256 + threadIdx.x; i < n; i += kReduceBlocks * 256) acc += x[i] * zv;
+  const double s = block_sum256(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) project_apply_kernel(int n, int p0, double zv, const double* __restrict__ zx,
+                                                            double* __restrict__ x) {
+  const int i = p0 + blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] -= zx[0] * zv;
+}
+
+void launch_project(int n, int p0, double zv, double* x, double* partial, hipStream_t s) {
+  project_partial_kernel<<<kReduceBlocks, 256, 0, s>>>(n, p0, zv, x, partial);
+  reduce_final_kernel<<<1, 256, 0, s>>>(partial, partial + kReduceBlocks);
+  project_apply_kernel<<<(n - p0 + 255) / 256, 256, 0, s>>>(n, p0, zv, partial + kReduceBlocks, x);
+}
+
+}  // namespace vk

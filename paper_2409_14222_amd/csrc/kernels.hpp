@@ -1,0 +1,61 @@
+// Launchers of the gfx950 kernels (kernels.hip).  All enqueue on `s`.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace vk {
+
+// y = A x (mode 0), y = b - A x (mode 1), y += A x (mode 2); lanes per row
+// chosen from the mean row length.
+void launch_csr(int mode, int nrows, double mean_row, const int* rowptr, const int* col, const double* val,
+                const double* x, const double* b, double* y, hipStream_t s);
+
+// Matrix-full patch setup: gather K_i = K[I_i, I_i] into LDS, invert it by
+// Gauss-Jordan with partial pivoting (FP64), store the inverse column-major
+// (leading dimension rounded to 2 doubles / 4 floats) as double or float.
+// `list` holds `count` patch ids whose size is <= nmax (32, 64 or 128).
+// `singular` receives the smallest patch id with a zero pivot (initialise to INT_MAX).
+void launch_gather_invert(int nmax, bool fp32, int count, const int* list, const int* pptr, const int* pdofs,
+                          const int* rowptr, const int* col, const double* val, const int64_t* inv_off, void* inv,
+                          int* singular, hipStream_t s);
+
+// Dense K_i tiles (n_i x n_i, column-major, packed) of patches first..first+count-1.
+void launch_gather_dense(int nmax, int first, int count, const int* pptr, const int* pdofs, const int* rowptr,
+                         const int* col, const double* val, const int64_t* out_off, double* out, hipStream_t s);
+
+// Copy one stored inverse (double or float, padded) to a dense n x n double array.
+void launch_copy_inverse(bool fp32, int n, const void* inv, int64_t off, double* out, hipStream_t s);
+
+// delta_i = K_i^{-1} t[I_i] for every patch (one wave per patch, order[] = largest first).
+void launch_patch_apply(bool fp32, int J, const int* order, const int* pptr, const int* pdofs,
+                        const int64_t* inv_off, const void* inv, const double* t, void* delta, hipStream_t s);
+
+// x[d] += scale[d] * sum_{slots of d, ascending patch id} delta[slot]
+void launch_scatter(bool fp32, int N, const int* dptr, const int* dslot, const void* delta, const double* scale,
+                    double* x, hipStream_t s);
+
+// x[d] = scale[d] * sum delta (first sweep from a zero iterate)
+void launch_scatter_set(bool fp32, int N, const int* dptr, const int* dslot, const void* delta,
+                        const double* scale, double* x, hipStream_t s);
+
+// e = M r, M dense row-major N x N
+void launch_dense_gemv(int N, const double* M, const double* r, double* e, hipStream_t s);
+
+// Deterministic reductions.  `partial` holds at least kReduceBlocks * nv doubles.
+constexpr int kReduceBlocks = 256;
+// out[v] = sum_i V[v*ldv + i] * w[i], v < nv  (w may alias none of V)
+void launch_multidot(int n, int nv, const double* V, int64_t ldv, const double* w, double* partial, double* out,
+                     hipStream_t s);
+// w[i] += sign * sum_v V[v*ldv + i] * h[v]
+void launch_multiaxpy(int n, int nv, double sign, const double* V, int64_t ldv, const double* h, double* w,
+                      hipStream_t s);
+// y = x / alpha
+void launch_div(int n, const double* x, double alpha, double* y, hipStream_t s);
+void launch_copy(int n, const double* x, double* y, hipStream_t s);
+void launch_fill(int n, double v, double* y, hipStream_t s);
+// x[p] -= (sum_{q in [p0,n)} x[q] zv) zv for p in [p0, n): removal of the constant pressure
+void launch_project(int n, int p0, double zv, double* x, double* partial, hipStream_t s);
+
+}  // namespace vk
