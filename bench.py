@@ -85,6 +85,9 @@ def main():
     H.setup()
     torch.cuda.synchronize()
     t_dev = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tuning = H.autotune(reps=5)
+    t_tune = time.perf_counter() - t0
     Lf = w["levels"] - 1
     info = H.level_info(Lf)
     b = torch.tensor(H.rhs(), device="cuda")
@@ -133,7 +136,8 @@ def main():
         "iterations": its_mean,
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
         "vanka_dof_sweeps_per_s_finest": info.n_free * 4 * its_mean * solves_per_s,
-        "setup_s": {"host_assembly": t_host, "device_upload_gather_invert": t_dev},
+        "setup_s": {"host_assembly": t_host, "device_upload_gather_invert": t_dev, "autotune": t_tune},
+        "tuning": tuning,
         "roofline": {"kernel": "patch_apply_kernel (finest level)", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": apply_bytes, "avg_launch_us": avg_s * 1e6,

@@ -187,6 +187,25 @@ vk_status vk_vcycle(vk_hierarchy* h, const double* d_r, double* d_e, int nu_pre,
 vk_status vk_solve(vk_hierarchy* h, const double* d_b, double* d_x, const vk_solve_opts* opts,
                    vk_solve_info* info);
 
+/* Launch shapes of one level.  They change only speed, never results: the
+ * CSR products and the patch apply sum in a canonical order that does not
+ * depend on the lanes per row or the waves per patch. */
+typedef struct vk_tuning {
+  int k_lanes;           /* lanes per CSR row of K (4, 8, 16, 32, 64) */
+  int p_lanes;           /* lanes per row of the prolongation from level-1 */
+  int pt_lanes;          /* lanes per row of its transpose (restriction) */
+  int apply_waves_large; /* wavefronts per patch, patches with more than 64 DoFs (1, 2, 4) */
+  int apply_waves_small; /* wavefronts per patch, the others */
+} vk_tuning;
+
+/* Autotuner (batching pattern of the path): times every candidate launch
+ * shape on each level's own data (reps launches each, HIP events) and keeps
+ * the fastest.  Synchronises.  Needs vk_patches_setup first. */
+vk_status vk_autotune(vk_hierarchy* h, int reps);
+vk_status vk_tuning_get(const vk_hierarchy* h, int level, vk_tuning* t);
+/* Pins launch shapes (e.g. a cached autotuner result); VK_EINVAL on unsupported values. */
+vk_status vk_tuning_set(vk_hierarchy* h, int level, const vk_tuning* t);
+
 /* Timing of the finest-level patch-apply kernel (HIP events around every
  * launch while enabled): launches and total milliseconds since the last reset. */
 vk_status vk_kernel_timing(vk_hierarchy* h, int enable, int reset, int64_t* launches, double* total_ms);

@@ -44,6 +44,11 @@ class vk_level_info(ctypes.Structure):
                 ("p_nnz", ctypes.c_int64)]
 
 
+class vk_tuning(ctypes.Structure):
+    _fields_ = [("k_lanes", _c_int), ("p_lanes", _c_int), ("pt_lanes", _c_int), ("apply_waves_large", _c_int),
+                ("apply_waves_small", _c_int)]
+
+
 class vk_solve_opts(ctypes.Structure):
     _fields_ = [("restart", _c_int), ("maxit", _c_int), ("rtol", _c_dbl), ("nu_pre", _c_int), ("nu_post", _c_int)]
 
@@ -76,6 +81,9 @@ _SIGS = {
     "vk_coarse_solve": ([_p, _p, _p], _c_int),
     "vk_vcycle": ([_p, _p, _p, _c_int, _c_int], _c_int),
     "vk_solve": ([_p, _p, _p, _P(vk_solve_opts), _P(vk_solve_info)], _c_int),
+    "vk_autotune": ([_p, _c_int], _c_int),
+    "vk_tuning_get": ([_p, _c_int, _P(vk_tuning)], _c_int),
+    "vk_tuning_set": ([_p, _c_int, _P(vk_tuning)], _c_int),
     "vk_kernel_timing": ([_p, _c_int, _c_int, _P(ctypes.c_int64), _P(_c_dbl)], _c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -225,6 +233,21 @@ class Hierarchy:
         if history:
             out["history"] = hist[: info.iterations + 1].copy()
         return out
+
+    def autotune(self, reps=5):
+        check(lib.vk_autotune(self.h, reps))
+        return [self.tuning(l) for l in range(self.n_levels)]
+
+    def tuning(self, level):
+        t = vk_tuning()
+        check(lib.vk_tuning_get(self.h, level, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in vk_tuning._fields_}
+
+    def set_tuning(self, level, **kw):
+        cur = self.tuning(level)
+        cur.update(kw)
+        t = vk_tuning(**cur)
+        check(lib.vk_tuning_set(self.h, level, ctypes.byref(t)))
 
     def kernel_timing(self, enable=True, reset=False):
         n = ctypes.c_int64()

@@ -39,6 +39,9 @@ struct DevLevel {
   double *b = nullptr, *x = nullptr, *t = nullptr;
   double* M = nullptr;  // coarsest level
   int class_count[3] = {0, 0, 0};  // patches with n <= 32, <= 64, <= 128 (ids in `classes`)
+  // launch shapes (never change results): lanes per CSR row of K, P, P^T;
+  // waves per patch for the large (n > 64, first in `order`) and small patches
+  int k_lanes = 32, p_lanes = 8, pt_lanes = 8, waves_large = 1, waves_small = 1, n_large = 0;
 };
 
 // Sequential carving of one caller buffer into 256-byte aligned pieces.  Run
@@ -97,6 +100,7 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.N = lh.N;
     d.nvel = lh.nvel;
     d.mean_row = (double)lh.K.nnz() / lh.N;
+    d.k_lanes = csr_default_lanes(d.mean_row);
     d.rowptr = cv.take<int>(lh.N + 1);
     d.col = cv.take<int>(lh.K.col.size());
     d.val = cv.take<double>(lh.K.val.size());
@@ -115,6 +119,10 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.ptval = cv.take<double>(lh.PT.val.size());
     d.p_mean = (double)lh.P.nnz() / std::max(1, lh.P.nrows);
     d.pt_mean = (double)lh.PT.nnz() / std::max(1, lh.PT.nrows);
+    d.p_lanes = csr_default_lanes(d.p_mean);
+    d.pt_lanes = csr_default_lanes(d.pt_mean);
+    for (int i = 0; i + 1 < (int)lh.pptr.size(); ++i)
+      if (lh.pptr[i + 1] - lh.pptr[i] > 64) d.n_large++;
     d.J = (int)lh.pptr.size() - 1;
     d.pptr = cv.take<int>(lh.pptr.size());
     d.pdofs = cv.take<int>(lh.pdofs.size());
@@ -171,7 +179,10 @@ void patch_apply(vk_hierarchy* h, int l, const double* t) {
     h->ev_free.pop_back();
     HIPCHECK(hipEventRecord(ev.first, h->stream));
   }
-  launch_patch_apply(h->fp32(), d.J, d.order, d.pptr, d.pdofs, d.inv_off, d.inv, t, d.delta, h->stream);
+  launch_patch_apply(h->fp32(), d.waves_large, d.n_large, d.order, d.pptr, d.pdofs, d.inv_off, d.inv, t, d.delta,
+                     h->stream);
+  launch_patch_apply(h->fp32(), d.waves_small, d.J - d.n_large, d.order + d.n_large, d.pptr, d.pdofs, d.inv_off,
+                     d.inv, t, d.delta, h->stream);
   check_launch();
   if (timed) {
     HIPCHECK(hipEventRecord(ev.second, h->stream));
@@ -188,7 +199,7 @@ void smooth(vk_hierarchy* h, int l, const double* b, double* x, int nsweeps, boo
     const bool first_zero = x_zero && it == 0;
     const double* t = b;
     if (!first_zero) {
-      launch_csr(1, d.N, d.mean_row, d.rowptr, d.col, d.val, x, b, d.t, s);
+      launch_csr(1, d.N, d.k_lanes, d.rowptr, d.col, d.val, x, b, d.t, s);
       t = d.t;
     }
     patch_apply(h, l, t);
@@ -210,11 +221,11 @@ void vcycle(vk_hierarchy* h, int l, const double* r, double* e, int nu_pre, int 
   }
   DevLevel& c = h->D[l - 1];
   smooth(h, l, r, e, nu_pre, true);
-  launch_csr(1, d.N, d.mean_row, d.rowptr, d.col, d.val, e, r, d.t, s);        // t = r - K e
-  launch_csr(0, c.N, d.pt_mean, d.ptrow, d.ptcol, d.ptval, d.t, nullptr, c.b, s);  // r_c = P^T t
+  launch_csr(1, d.N, d.k_lanes, d.rowptr, d.col, d.val, e, r, d.t, s);           // t = r - K e
+  launch_csr(0, c.N, d.pt_lanes, d.ptrow, d.ptcol, d.ptval, d.t, nullptr, c.b, s);  // r_c = P^T t
   check_launch();
   vcycle(h, l - 1, c.b, c.x, nu_pre, nu_post);
-  launch_csr(2, d.N, d.p_mean, d.prow, d.pcol, d.pval, c.x, nullptr, e, s);     // e += P e_c
+  launch_csr(2, d.N, d.p_lanes, d.prow, d.pcol, d.pval, c.x, nullptr, e, s);     // e += P e_c
   check_launch();
   smooth(h, l, r, e, nu_post, false);
 }
@@ -281,7 +292,7 @@ vk_status fgmres(vk_hierarchy* h, const double* b_in, double* x, const vk_solve_
       double* zj = h->Z + (size_t)j * N;
       double* w = h->V + (size_t)(j + 1) * N;
       vcycle(h, Lf, vj, zj, o.nu_pre, o.nu_post);
-      launch_csr(0, N, F.mean_row, F.rowptr, F.col, F.val, zj, nullptr, w, s);
+      launch_csr(0, N, F.k_lanes, F.rowptr, F.col, F.val, zj, nullptr, w, s);
       // CGS2: two classical Gram-Schmidt passes against v_0..v_j
       launch_multidot(N, j + 1, h->V, N, w, h->partial, h->small, s);
       launch_multiaxpy(N, j + 1, -1.0, h->V, N, h->small, w, s);
@@ -324,7 +335,7 @@ vk_status fgmres(vk_hierarchy* h, const double* b_in, double* x, const vk_solve_
     HIPCHECK(hipMemcpyAsync(h->ydev, h->ybuf.data(), nk * sizeof(double), hipMemcpyHostToDevice, s));
     launch_multiaxpy(N, nk, 1.0, h->Z, N, h->ydev, x, s);
     launch_project(N, nvel, zv, x, h->partial, s);
-    launch_csr(1, N, F.mean_row, F.rowptr, F.col, F.val, x, h->bb, h->r, s);
+    launch_csr(1, N, F.k_lanes, F.rowptr, F.col, F.val, x, h->bb, h->r, s);
     check_launch();
   }
   if (info) {
@@ -334,6 +345,69 @@ vk_status fgmres(vk_hierarchy* h, const double* b_in, double* x, const vk_solve_
   }
   if (h->timing) collect_timing(h);
   return converged ? VK_OK : VK_NOT_CONVERGED;
+}
+
+// Times `fn` (enqueued on the stream) `reps` times after one warm-up; returns the mean in ms.
+template <typename Fn>
+float time_ms(hipStream_t s, int reps, Fn&& fn) {
+  hipEvent_t a, b;
+  HIPCHECK(hipEventCreate(&a));
+  HIPCHECK(hipEventCreate(&b));
+  fn();
+  HIPCHECK(hipEventRecord(a, s));
+  for (int i = 0; i < reps; ++i) fn();
+  HIPCHECK(hipEventRecord(b, s));
+  HIPCHECK(hipEventSynchronize(b));
+  float ms = 0.f;
+  HIPCHECK(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
+}
+
+// Autotuner: for every level, the lanes per CSR row of K, P and P^T and the
+// waves per patch of the two apply launches are chosen by timing each
+// candidate on the level's own data.  Launch shapes never change results.
+void autotune(vk_hierarchy* h, int reps) {
+  const hipStream_t s = h->stream;
+  const int lanes[5] = {4, 8, 16, 32, 64};
+  const int waves[3] = {1, 2, 4};
+  for (int l = 0; l < h->L(); ++l) {
+    DevLevel& d = h->D[l];
+    launch_fill(d.N, 1.0, d.b, s);
+    launch_fill(d.N, 1.0, d.x, s);
+    auto best_lanes = [&](auto&& run) {
+      int best = 64;
+      float bt = 1e30f;
+      for (int ln : lanes) {
+        const float t = time_ms(s, reps, [&] { run(ln); });
+        if (t < bt * 0.98f) { bt = t; best = ln; }
+      }
+      return best;
+    };
+    d.k_lanes = best_lanes([&](int ln) { launch_csr(1, d.N, ln, d.rowptr, d.col, d.val, d.x, d.b, d.t, s); });
+    if (l == 0) continue;
+    DevLevel& c = h->D[l - 1];
+    launch_fill(c.N, 1.0, c.x, s);
+    d.p_lanes = best_lanes([&](int ln) { launch_csr(2, d.N, ln, d.prow, d.pcol, d.pval, c.x, nullptr, d.t, s); });
+    d.pt_lanes = best_lanes([&](int ln) { launch_csr(0, c.N, ln, d.ptrow, d.ptcol, d.ptval, d.x, nullptr, c.b, s); });
+    for (int part = 0; part < 2; ++part) {
+      const int first = part == 0 ? 0 : d.n_large;
+      const int count = part == 0 ? d.n_large : d.J - d.n_large;
+      if (count == 0) continue;
+      int best = 1;
+      float bt = 1e30f;
+      for (int w : waves) {
+        const float t = time_ms(s, reps, [&] {
+          launch_patch_apply(h->fp32(), w, count, d.order + first, d.pptr, d.pdofs, d.inv_off, d.inv, d.b,
+                             d.delta, s);
+        });
+        if (t < bt * 0.98f) { bt = t; best = w; }
+      }
+      (part == 0 ? d.waves_large : d.waves_small) = best;
+    }
+  }
+  check_launch();
 }
 
 template <typename F>
@@ -645,7 +719,7 @@ vk_status vk_spmv(vk_hierarchy* h, int level, const double* x, double* y) {
     require(h && h->bound && x && y, VK_ESTATE, "hierarchy not bound or null vector");
     require_level(h, level, 0);
     DevLevel& d = h->D[level];
-    launch_csr(0, d.N, d.mean_row, d.rowptr, d.col, d.val, x, nullptr, y, h->stream);
+    launch_csr(0, d.N, d.k_lanes, d.rowptr, d.col, d.val, x, nullptr, y, h->stream);
     check_launch();
     return VK_OK;
   });
@@ -656,7 +730,7 @@ vk_status vk_restrict(vk_hierarchy* h, int level, const double* rf, double* rc) 
     require(h && h->bound && rf && rc, VK_ESTATE, "hierarchy not bound or null vector");
     require_level(h, level, 1);
     DevLevel& d = h->D[level];
-    launch_csr(0, h->D[level - 1].N, d.pt_mean, d.ptrow, d.ptcol, d.ptval, rf, nullptr, rc, h->stream);
+    launch_csr(0, h->D[level - 1].N, d.pt_lanes, d.ptrow, d.ptcol, d.ptval, rf, nullptr, rc, h->stream);
     check_launch();
     return VK_OK;
   });
@@ -667,7 +741,7 @@ vk_status vk_prolong_add(vk_hierarchy* h, int level, const double* ec, double* e
     require(h && h->bound && ec && ef, VK_ESTATE, "hierarchy not bound or null vector");
     require_level(h, level, 1);
     DevLevel& d = h->D[level];
-    launch_csr(2, d.N, d.p_mean, d.prow, d.pcol, d.pval, ec, nullptr, ef, h->stream);
+    launch_csr(2, d.N, d.p_lanes, d.prow, d.pcol, d.pval, ec, nullptr, ef, h->stream);
     check_launch();
     return VK_OK;
   });
@@ -709,6 +783,49 @@ vk_status vk_solve(vk_hierarchy* h, const double* b, double* x, const vk_solve_o
     require(opts->maxit >= 0 && opts->rtol >= 0 && opts->nu_pre >= 0 && opts->nu_post >= 0, VK_EINVAL,
             "bad solve options");
     return fgmres(h, b, x, *opts, info);
+  });
+}
+
+vk_status vk_autotune(vk_hierarchy* h, int reps) {
+  return guarded([&]() -> vk_status {
+    require_ready(h);
+    require(reps >= 1 && reps <= 1000, VK_EINVAL, "reps out of range");
+    autotune(h, reps);
+    return VK_OK;
+  });
+}
+
+vk_status vk_tuning_get(const vk_hierarchy* h, int level, vk_tuning* t) {
+  return guarded([&]() -> vk_status {
+    require(h && t, VK_EINVAL, "null argument");
+    require(h->bound, VK_ESTATE, "hierarchy is not bound");
+    require_level(h, level, 0);
+    const DevLevel& d = h->D[level];
+    t->k_lanes = d.k_lanes;
+    t->p_lanes = d.p_lanes;
+    t->pt_lanes = d.pt_lanes;
+    t->apply_waves_large = d.waves_large;
+    t->apply_waves_small = d.waves_small;
+    return VK_OK;
+  });
+}
+
+vk_status vk_tuning_set(vk_hierarchy* h, int level, const vk_tuning* t) {
+  return guarded([&]() -> vk_status {
+    require(h && t, VK_EINVAL, "null argument");
+    require(h->bound, VK_ESTATE, "hierarchy is not bound");
+    require_level(h, level, 0);
+    auto okl = [](int v) { return v == 4 || v == 8 || v == 16 || v == 32 || v == 64; };
+    auto okw = [](int v) { return v == 1 || v == 2 || v == 4; };
+    require(okl(t->k_lanes) && okl(t->p_lanes) && okl(t->pt_lanes), VK_EINVAL, "lanes must be 4, 8, 16, 32 or 64");
+    require(okw(t->apply_waves_large) && okw(t->apply_waves_small), VK_EINVAL, "waves must be 1, 2 or 4");
+    DevLevel& d = h->D[level];
+    d.k_lanes = t->k_lanes;
+    d.p_lanes = t->p_lanes;
+    d.pt_lanes = t->pt_lanes;
+    d.waves_large = t->apply_waves_large;
+    d.waves_small = t->apply_waves_small;
+    return VK_OK;
   });
 }
 

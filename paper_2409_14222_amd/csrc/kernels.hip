@@ -13,20 +13,42 @@ namespace vk {
 
 // ============================================================================
 // CSR products: y = A x, y = b - A x, y += A x.  A group of LANES lanes owns
-// one row; lanes stride over the row's entries (coalesced col/val loads) and
-// the partial sums are combined by an xor butterfly inside the group.
+// one row.  The summation order is canonical and independent of LANES: the
+// row's entries are dealt to 64 virtual positions p = (q - rowstart) mod 64,
+// each position accumulates its entries in ascending order, and the 64
+// partial sums are combined by the xor tree with offsets 32, 16, ..., 1.  A
+// lane holds 64/LANES positions, performs the tree levels with offsets
+// >= LANES in registers and the rest with cross-lane shuffles, so every
+// launch shape returns bitwise identical results.
 // ============================================================================
 template <int LANES, int MODE>
 __global__ void __launch_bounds__(256) csr_kernel(int nrows, const int* __restrict__ rowptr,
                                                   const int* __restrict__ col, const double* __restrict__ val,
                                                   const double* __restrict__ x, const double* __restrict__ b,
                                                   double* __restrict__ y) {
+  constexpr int V = 64 / LANES;
   const int row = (int)((blockIdx.x * 256u + threadIdx.x) / LANES);
   const int lane = threadIdx.x & (LANES - 1);
   if (row >= nrows) return;  // uniform over the LANES-group
   const int s = rowptr[row], e = rowptr[row + 1];
-  double acc = 0.0;
-  for (int q = s + lane; q < e; q += LANES) acc += val[q] * x[col[q]];
+  double a[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) a[v] = 0.0;
+  for (int base = s; base < e; base += 64) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int q = base + lane + v * LANES;
+      if (q < e) a[v] += val[q] * x[col[q]];
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= LANES; o >>= 1) {
+    const int vo = o / LANES;
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      if (!(v & vo)) a[v] = a[v] + a[v | vo];
+  }
+  double acc = a[0];
 #pragma unroll
   for (int off = LANES / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LANES);
   if (lane == 0) {
@@ -47,13 +69,23 @@ static void csr_dispatch(int mode, int nrows, const int* rp, const int* c, const
   else csr_kernel<LANES, 2><<<grid, 256, 0, s>>>(nrows, rp, c, v, x, b, y);
 }
 
-void launch_csr(int mode, int nrows, double mean_row, const int* rp, const int* c, const double* v,
-                const double* x, const double* b, double* y, hipStream_t s) {
-  if (mean_row <= 6) csr_dispatch<4>(mode, nrows, rp, c, v, x, b, y, s);
-  else if (mean_row <= 12) csr_dispatch<8>(mode, nrows, rp, c, v, x, b, y, s);
-  else if (mean_row <= 28) csr_dispatch<16>(mode, nrows, rp, c, v, x, b, y, s);
-  else if (mean_row <= 80) csr_dispatch<32>(mode, nrows, rp, c, v, x, b, y, s);
-  else csr_dispatch<64>(mode, nrows, rp, c, v, x, b, y, s);
+int csr_default_lanes(double mean_row) {
+  if (mean_row <= 6) return 4;
+  if (mean_row <= 12) return 8;
+  if (mean_row <= 28) return 16;
+  if (mean_row <= 80) return 32;
+  return 64;
+}
+
+void launch_csr(int mode, int nrows, int lanes, const int* rp, const int* c, const double* v, const double* x,
+                const double* b, double* y, hipStream_t s) {
+  switch (lanes) {
+    case 4: csr_dispatch<4>(mode, nrows, rp, c, v, x, b, y, s); break;
+    case 8: csr_dispatch<8>(mode, nrows, rp, c, v, x, b, y, s); break;
+    case 16: csr_dispatch<16>(mode, nrows, rp, c, v, x, b, y, s); break;
+    case 32: csr_dispatch<32>(mode, nrows, rp, c, v, x, b, y, s); break;
+    default: csr_dispatch<64>(mode, nrows, rp, c, v, x, b, y, s); break;
+  }
 }
 
 // ============================================================================
@@ -255,96 +287,135 @@ void launch_copy_inverse(bool fp32, int n, const void* inv, int64_t off, double*
 }
 
 // ============================================================================
-// Additive patch apply: delta_i = K_i^{-1} t[I_i].  One wave per patch.  The
-// gathered residual sits in LDS; the inverse (column-major, ld rounded to
-// RPL rows) streams from HBM in 16-byte loads: lane (c, r) loads rows
-// [RPL r, RPL r + RPL) of columns c, c + C, c + 2C, ... so that one wave
-// instruction covers C consecutive columns contiguously.  The C partial
-// sums per row are combined in LDS in fixed order.
+// Additive patch apply: delta_i = K_i^{-1} t[I_i].  One workgroup of W waves
+// per patch.  The gathered residual sits in LDS; the inverse (column-major,
+// ld rounded to RPL rows) streams from HBM in 16-byte non-temporal loads.
+//
+// Lane layout: R = ld / RPL lanes cover the rows (RPL rows each), C column
+// slots (a power of two <= 8) cover the columns.  The summation order of
+// every output row is canonical: column j belongs to group j mod 8, each
+// group sums its columns in ascending order, and the 8 group sums are
+// combined by the xor tree with offsets 4, 2, 1.  A slot c owns groups
+// c, c + C, ... and performs the tree levels with offsets >= C in
+// registers; the remaining levels run over LDS.  Results are therefore
+// bitwise independent of W (the autotuned launch shape).
 // ============================================================================
+typedef double dbl2_t __attribute__((ext_vector_type(2)));
+typedef float flt4_t __attribute__((ext_vector_type(4)));
 template <typename T> struct vec16;
-template <> struct vec16<double> { using type = double2; };
-template <> struct vec16<float> { using type = float4; };
+template <> struct vec16<double> { using type = dbl2_t; };
+template <> struct vec16<float> { using type = flt4_t; };
 
-template <typename TS>
-__device__ inline void fma_vec(TS* acc, const typename vec16<TS>::type& a, TS x);
-template <>
-__device__ inline void fma_vec<double>(double* acc, const double2& a, double x) {
-  acc[0] += a.x * x;
-  acc[1] += a.y * x;
-}
-template <>
-__device__ inline void fma_vec<float>(float* acc, const float4& a, float x) {
-  acc[0] += a.x * x;
-  acc[1] += a.y * x;
-  acc[2] += a.z * x;
-  acc[3] += a.w * x;
-}
-
-template <typename TS>
-__global__ void __launch_bounds__(64) patch_apply_kernel(const int* __restrict__ order, const int* __restrict__ pptr,
-                                                         const int* __restrict__ pdofs,
-                                                         const int64_t* __restrict__ inv_off,
-                                                         const TS* __restrict__ inv, const double* __restrict__ t,
-                                                         TS* __restrict__ delta) {
+template <typename TS, int W>
+__global__ void __launch_bounds__(64 * W) patch_apply_kernel(const int* __restrict__ order,
+                                                             const int* __restrict__ pptr,
+                                                             const int* __restrict__ pdofs,
+                                                             const int64_t* __restrict__ inv_off,
+                                                             const TS* __restrict__ inv,
+                                                             const double* __restrict__ t,
+                                                             TS* __restrict__ delta) {
   constexpr int RPL = 16 / sizeof(TS);
+  constexpr int NT = 64 * W;
   using V = typename vec16<TS>::type;
   __shared__ TS xs[256];
-  __shared__ TS red[64 * RPL];
+  __shared__ TS red[8 * 64 * RPL];
   const int p = order[blockIdx.x];
   const int base = pptr[p];
   const int n = pptr[p + 1] - base;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
   if (n > 256) return;  // the host rejects patches above 256 DoFs; never taken
-  for (int j = lane; j < n; j += 64) xs[j] = (TS)t[pdofs[base + j]];
+  for (int j = tid; j < n; j += NT) xs[j] = (TS)t[pdofs[base + j]];
   __syncthreads();
   const int ld = (n + RPL - 1) / RPL * RPL;
   const TS* A = inv + inv_off[p];
   for (int r0 = 0; r0 < ld; r0 += 64 * RPL) {
     const int rows = min(ld - r0, 64 * RPL);
     const int R = rows / RPL;
-    const int C = 64 / R;
-    const int r = lane % R, c = lane / R;
-    TS acc[RPL];
-#pragma unroll
-    for (int u = 0; u < RPL; ++u) acc[u] = (TS)0;
+    int C = NT / R;
+    C = C >= 8 ? 8 : C >= 4 ? 4 : C >= 2 ? 2 : 1;
+    const int r = tid % R, c = tid / R;
     if (c < C) {
+      constexpr int G = 8;
+      const int ng = G / C;  // groups owned by this slot: c, c + C, ...
+      TS acc[G][RPL];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) acc[g][u] = (TS)0;
       const TS* Ap = A + r0 + r * RPL;
-#pragma unroll 4
-      for (int j = c; j < n; j += C) {
-        const V a = *reinterpret_cast<const V*>(Ap + (int64_t)j * ld);
-        fma_vec<TS>(acc, a, xs[j]);
+      // columns j = c + C * m; group of j is j mod 8 = c + C * (m mod ng)
+      for (int j0 = c; j0 < n; j0 += 8) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          if (g < ng) {
+            const int j = j0 + g * C;
+            if (j < n) {
+              const V a = __builtin_nontemporal_load(reinterpret_cast<const V*>(Ap + (int64_t)j * ld));
+              const TS xj = xs[j];
+#pragma unroll
+              for (int u = 0; u < RPL; ++u) acc[g][u] += a[u] * xj;
+            }
+          }
+        }
+      }
+      // in-register tree levels: local group index g <-> global group c + C g;
+      // xor offset o >= C in global index is xor (o / C) in local index
+#pragma unroll
+      for (int o = 4; o >= 1; o >>= 1) {
+        if (o < C) break;
+        const int lo = o / C;
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          if (g < ng && !(g & lo))
+#pragma unroll
+            for (int u = 0; u < RPL; ++u) acc[g][u] = acc[g][u] + acc[g | lo][u];
       }
 #pragma unroll
-      for (int u = 0; u < RPL; ++u) red[c * rows + r * RPL + u] = acc[u];
+      for (int u = 0; u < RPL; ++u) red[c * rows + r * RPL + u] = acc[0][u];
     }
     __syncthreads();
-    if (lane < R) {
+    // cross-slot tree levels (offsets C/2 .. 1) and the store
+    for (int el = tid; el < rows; el += NT) {
+      const int row = r0 + el;
+      TS w[8];
 #pragma unroll
-      for (int u = 0; u < RPL; ++u) {
-        TS s = red[lane * RPL + u];
-        for (int c2 = 1; c2 < C; ++c2) s += red[c2 * rows + lane * RPL + u];
-        const int row = r0 + lane * RPL + u;
-        if (row < n) delta[base + row] = s;
-      }
+      for (int cc = 0; cc < 8; ++cc) w[cc] = cc < C ? red[cc * rows + el] : (TS)0;
+#pragma unroll
+      for (int o = 4; o >= 1; o >>= 1)
+        if (o < C)
+#pragma unroll
+          for (int cc = 0; cc < 8; ++cc)
+            if (cc < C && !(cc & o)) w[cc] = w[cc] + w[cc | o];
+      if (row < n) delta[base + row] = w[0];
     }
     __syncthreads();
   }
 }
 
-void launch_patch_apply(bool fp32, int J, const int* order, const int* pptr, const int* pdofs,
+template <typename TS>
+static void apply_dispatch(int waves, int count, const int* order, const int* pptr, const int* pdofs,
+                           const int64_t* inv_off, const TS* inv, const double* t, TS* delta, hipStream_t s) {
+  if (count <= 0) return;
+  switch (waves) {
+    case 1: patch_apply_kernel<TS, 1><<<count, 64, 0, s>>>(order, pptr, pdofs, inv_off, inv, t, delta); break;
+    case 2: patch_apply_kernel<TS, 2><<<count, 128, 0, s>>>(order, pptr, pdofs, inv_off, inv, t, delta); break;
+    default: patch_apply_kernel<TS, 4><<<count, 256, 0, s>>>(order, pptr, pdofs, inv_off, inv, t, delta); break;
+  }
+}
+
+void launch_patch_apply(bool fp32, int waves, int count, const int* order, const int* pptr, const int* pdofs,
                         const int64_t* inv_off, const void* inv, const double* t, void* delta, hipStream_t s) {
-  if (J <= 0) return;
   if (fp32)
-    patch_apply_kernel<float><<<J, 64, 0, s>>>(order, pptr, pdofs, inv_off, (const float*)inv, t, (float*)delta);
+    apply_dispatch<float>(waves, count, order, pptr, pdofs, inv_off, (const float*)inv, t, (float*)delta, s);
   else
-    patch_apply_kernel<double><<<J, 64, 0, s>>>(order, pptr, pdofs, inv_off, (const double*)inv, t,
-                                                (double*)delta);
+    apply_dispatch<double>(waves, count, order, pptr, pdofs, inv_off, (const double*)inv, t, (double*)delta, s);
 }
 
 // ============================================================================
 // Deterministic segmented scatter-add of the weighted corrections:
-// x[d] (+)= scale[d] * sum over the slots of d (ascending patch id).
+// x[d] (+)= scale[d] * sum over the slots of d (ascending patch id).  The
+// slot indices of a chunk of 8 are loaded first and the corrections after,
+// so the dependent loads overlap; the sum stays in ascending slot order.
 // ============================================================================
 template <typename TD, bool SET>
 __global__ void __launch_bounds__(256) scatter_kernel(int N, const int* __restrict__ dptr,
@@ -352,8 +423,19 @@ __global__ void __launch_bounds__(256) scatter_kernel(int N, const int* __restri
                                                       const double* __restrict__ scale, double* __restrict__ x) {
   const int d = blockIdx.x * 256 + threadIdx.x;
   if (d >= N) return;
+  const int q0 = dptr[d], q1 = dptr[d + 1];
   double s = 0.0;
-  for (int q = dptr[d]; q < dptr[d + 1]; ++q) s += (double)delta[dslot[q]];
+  for (int q = q0; q < q1; q += 8) {
+    int idx[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) idx[u] = q + u < q1 ? dslot[q + u] : -1;
+    TD v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = idx[u] >= 0 ? delta[idx[u]] : (TD)0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (q + u < q1) s += (double)v[u];
+  }
   if (SET) x[d] = scale[d] * s;
   else x[d] += scale[d] * s;
 }

@@ -7,10 +7,11 @@
 
 namespace vk {
 
-// y = A x (mode 0), y = b - A x (mode 1), y += A x (mode 2); lanes per row
-// chosen from the mean row length.
-void launch_csr(int mode, int nrows, double mean_row, const int* rowptr, const int* col, const double* val,
+// y = A x (mode 0), y = b - A x (mode 1), y += A x (mode 2); `lanes` (4..64,
+// a power of two) per row.  Results do not depend on `lanes`.
+void launch_csr(int mode, int nrows, int lanes, const int* rowptr, const int* col, const double* val,
                 const double* x, const double* b, double* y, hipStream_t s);
+int csr_default_lanes(double mean_row);
 
 // Matrix-full patch setup: gather K_i = K[I_i, I_i] into LDS, invert it by
 // Gauss-Jordan with partial pivoting (FP64), store the inverse column-major
@@ -28,8 +29,9 @@ void launch_gather_dense(int nmax, int first, int count, const int* pptr, const 
 // Copy one stored inverse (double or float, padded) to a dense n x n double array.
 void launch_copy_inverse(bool fp32, int n, const void* inv, int64_t off, double* out, hipStream_t s);
 
-// delta_i = K_i^{-1} t[I_i] for every patch (one wave per patch, order[] = largest first).
-void launch_patch_apply(bool fp32, int J, const int* order, const int* pptr, const int* pdofs,
+// delta_i = K_i^{-1} t[I_i] for the `count` patches order[0..count) with
+// `waves` (1, 2 or 4) wavefronts per patch.  Results do not depend on `waves`.
+void launch_patch_apply(bool fp32, int waves, int count, const int* order, const int* pptr, const int* pdofs,
                         const int64_t* inv_off, const void* inv, const double* t, void* delta, hipStream_t s);
 
 // x[d] += scale[d] * sum_{slots of d, ascending patch id} delta[slot]

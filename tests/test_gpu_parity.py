@@ -230,3 +230,27 @@ def test_mixed_precision_solve(p4p3):
     assert res["rel_residual"] <= 1e-10
     assert np.linalg.norm(ob - L.K @ xg) <= 1.05e-10 * np.linalg.norm(ob)
     assert np.linalg.norm(xg - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("fx", ["p2p1", "p4p3"])
+def test_launch_shapes_do_not_change_results(fx, request):
+    """The autotuner may pick any lanes-per-row / waves-per-patch: results stay bitwise equal."""
+    H, OH, OV = request.getfixturevalue(fx)
+    L = OH.finest
+    r = _dev(synth.vector(L.N, 700))
+    saved = [H.tuning(l) for l in range(len(OH.levels))]
+    ref = torch.empty_like(r)
+    H.vcycle(r, ref, 2, 2)
+    for lanes, waves in ((4, 1), (8, 2), (16, 4), (64, 1), (32, 4)):
+        for l in range(len(OH.levels)):
+            H.set_tuning(l, k_lanes=lanes, p_lanes=lanes, pt_lanes=lanes, apply_waves_large=waves,
+                         apply_waves_small=waves)
+        e = torch.empty_like(r)
+        H.vcycle(r, e, 2, 2)
+        assert torch.equal(e, ref), (lanes, waves)
+    H.autotune(reps=2)
+    e = torch.empty_like(r)
+    H.vcycle(r, e, 2, 2)
+    assert torch.equal(e, ref)
+    for l, t in enumerate(saved):
+        H.set_tuning(l, **t)
