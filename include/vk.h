@@ -196,6 +196,8 @@ typedef struct vk_tuning {
   int pt_lanes;          /* lanes per row of its transpose (restriction) */
   int apply_waves_large; /* wavefronts per patch, patches with more than 64 DoFs (1, 2, 4) */
   int apply_waves_small; /* wavefronts per patch, the others */
+  int apply_nontemporal_large; /* 1: stream the large patches' inverses with non-temporal loads */
+  int apply_nontemporal_small; /* same for the small patches */
 } vk_tuning;
 
 /* Autotuner (batching pattern of the path): times every candidate launch

@@ -46,7 +46,8 @@ class vk_level_info(ctypes.Structure):
 
 class vk_tuning(ctypes.Structure):
     _fields_ = [("k_lanes", _c_int), ("p_lanes", _c_int), ("pt_lanes", _c_int), ("apply_waves_large", _c_int),
-                ("apply_waves_small", _c_int)]
+                ("apply_waves_small", _c_int), ("apply_nontemporal_large", _c_int),
+                ("apply_nontemporal_small", _c_int)]
 
 
 class vk_solve_opts(ctypes.Structure):
@@ -136,10 +137,10 @@ class Hierarchy:
         self.ws = None
         self.stream = None
 
-    def __del__(self):
+    def __del__(self, _destroy=lib.vk_hierarchy_destroy):
         h = getattr(self, "h", None)
         if h is not None and h.value:
-            lib.vk_hierarchy_destroy(h)
+            _destroy(h)
             self.h = None
 
     # ------------------------------------------------------------ host data

@@ -42,6 +42,8 @@ struct DevLevel {
   // launch shapes (never change results): lanes per CSR row of K, P, P^T;
   // waves per patch for the large (n > 64, first in `order`) and small patches
   int k_lanes = 32, p_lanes = 8, pt_lanes = 8, waves_large = 1, waves_small = 1, n_large = 0;
+  int nt_large = 1, nt_small = 1;  // non-temporal (streaming) loads of the inverses
+  int4* meta = nullptr;            // per patch in processing order: {first slot, n, inverse offset}
 };
 
 // Sequential carving of one caller buffer into 256-byte aligned pieces.  Run
@@ -74,6 +76,7 @@ struct vk_hierarchy {
   double *V = nullptr, *Z = nullptr, *bb = nullptr, *r = nullptr, *partial = nullptr, *small = nullptr, *ydev = nullptr;
   int* singular = nullptr;
   std::vector<double> ybuf;
+  std::vector<std::vector<int4>> meta_host;  // staging of the per-patch metadata uploads
   // kernel timing of the finest-level patch apply
   bool timing = false;
   int64_t t_launches = 0;
@@ -131,6 +134,7 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.order = cv.take<int>(lh.order.size());
     d.classes = cv.take<int>(lh.order.size());
     d.inv_off = cv.take<int64_t>(lh.inv_off.size());
+    d.meta = cv.take<int4>(lh.order.size());
     d.scale = cv.take<double>(lh.scale.size());
     d.inv = cv.take<char>((size_t)lh.inv_elems * es);
     d.delta = cv.take<char>(lh.pdofs.size() * es);
@@ -179,10 +183,10 @@ void patch_apply(vk_hierarchy* h, int l, const double* t) {
     h->ev_free.pop_back();
     HIPCHECK(hipEventRecord(ev.first, h->stream));
   }
-  launch_patch_apply(h->fp32(), d.waves_large, d.n_large, d.order, d.pptr, d.pdofs, d.inv_off, d.inv, t, d.delta,
+  launch_patch_apply(h->fp32(), d.waves_large, d.nt_large != 0, d.n_large, d.meta, d.pdofs, d.inv, t, d.delta,
                      h->stream);
-  launch_patch_apply(h->fp32(), d.waves_small, d.J - d.n_large, d.order + d.n_large, d.pptr, d.pdofs, d.inv_off,
-                     d.inv, t, d.delta, h->stream);
+  launch_patch_apply(h->fp32(), d.waves_small, d.nt_small != 0, d.J - d.n_large, d.meta + d.n_large, d.pdofs, d.inv,
+                     t, d.delta, h->stream);
   check_launch();
   if (timed) {
     HIPCHECK(hipEventRecord(ev.second, h->stream));
@@ -395,16 +399,17 @@ void autotune(vk_hierarchy* h, int reps) {
       const int first = part == 0 ? 0 : d.n_large;
       const int count = part == 0 ? d.n_large : d.J - d.n_large;
       if (count == 0) continue;
-      int best = 1;
+      int best = 1, best_nt = 1;
       float bt = 1e30f;
-      for (int w : waves) {
-        const float t = time_ms(s, reps, [&] {
-          launch_patch_apply(h->fp32(), w, count, d.order + first, d.pptr, d.pdofs, d.inv_off, d.inv, d.b,
-                             d.delta, s);
-        });
-        if (t < bt * 0.98f) { bt = t; best = w; }
-      }
+      for (int nt = 1; nt >= 0; --nt)
+        for (int w : waves) {
+          const float t = time_ms(s, reps, [&] {
+            launch_patch_apply(h->fp32(), w, nt != 0, count, d.meta + first, d.pdofs, d.inv, d.b, d.delta, s);
+          });
+          if (t < bt * 0.98f) { bt = t; best = w; best_nt = nt; }
+        }
       (part == 0 ? d.waves_large : d.waves_small) = best;
+      (part == 0 ? d.nt_large : d.nt_small) = best_nt;
     }
   }
   check_launch();
@@ -527,6 +532,7 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_r
     h->max_restart = max_restart;
     Carver cv(d_ws);
     carve(h->H, h->fp32(), h, cv, max_restart);
+    h->meta_host.clear();
     const hipStream_t s = h->stream;
     for (int l = 0; l < h->L(); ++l) {
       const LevelHost& L = h->H[l];
@@ -551,6 +557,17 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_r
       up(d.order, L.order, s);
       up(d.classes, h->class_lists[l], s);
       up(d.inv_off, L.inv_off, s);
+      {
+        std::vector<int4> meta(L.order.size());
+        for (size_t i = 0; i < L.order.size(); ++i) {
+          const int p = L.order[i];
+          const int64_t o = L.inv_off[p];
+          meta[i] = make_int4(L.pptr[p], L.pptr[p + 1] - L.pptr[p], (int)(uint32_t)(o & 0xffffffffLL),
+                              (int)(o >> 32));
+        }
+        h->meta_host.push_back(std::move(meta));
+        up(d.meta, h->meta_host.back(), s);
+      }
       up(d.scale, L.scale, s);
       const int lim[3] = {32, 64, 128};
       for (int c = 0; c < 3; ++c) {
@@ -806,6 +823,8 @@ vk_status vk_tuning_get(const vk_hierarchy* h, int level, vk_tuning* t) {
     t->pt_lanes = d.pt_lanes;
     t->apply_waves_large = d.waves_large;
     t->apply_waves_small = d.waves_small;
+    t->apply_nontemporal_large = d.nt_large;
+    t->apply_nontemporal_small = d.nt_small;
     return VK_OK;
   });
 }
@@ -825,6 +844,8 @@ vk_status vk_tuning_set(vk_hierarchy* h, int level, const vk_tuning* t) {
     d.pt_lanes = t->pt_lanes;
     d.waves_large = t->apply_waves_large;
     d.waves_small = t->apply_waves_small;
+    d.nt_large = t->apply_nontemporal_large != 0;
+    d.nt_small = t->apply_nontemporal_small != 0;
     return VK_OK;
   });
 }

@@ -306,109 +306,144 @@ template <typename T> struct vec16;
 template <> struct vec16<double> { using type = dbl2_t; };
 template <> struct vec16<float> { using type = flt4_t; };
 
-template <typename TS, int W>
-__global__ void __launch_bounds__(64 * W) patch_apply_kernel(const int* __restrict__ order,
-                                                             const int* __restrict__ pptr,
+template <typename TS, bool NT>
+__device__ inline typename vec16<TS>::type load16(const TS* p) {
+  using V = typename vec16<TS>::type;
+  if (NT) return __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  return *reinterpret_cast<const V*>(p);
+}
+
+// One row pass of the apply with C column slots (compile-time, so every
+// accumulator index is static).  Slot c owns the columns c, c + C, ... whose
+// canonical groups are c, c + C, ... (ng = 8 / C of them).
+template <typename TS, int NTH, bool NT, int C>
+__device__ inline void apply_pass(const TS* __restrict__ A, int n, int ld, int r0, int rows, bool gather,
+                                  const int* __restrict__ dofs, const double* __restrict__ t, TS* xs, TS* red,
+                                  TS* __restrict__ dout) {  // dout: the patch's first slot
+  constexpr int RPL = 16 / sizeof(TS);
+  constexpr int U = 16;       // column loads in flight per lane
+  constexpr int ng = 8 / C;   // canonical groups per slot
+  using V = typename vec16<TS>::type;
+  const int tid = threadIdx.x;
+  const int R = rows / RPL;
+  const int r = tid % R, c = tid / R;
+  const bool active = c < C;
+  const int mcount = active ? (n - c + C - 1) / C : 0;
+  const TS* Ap = A + r0 + r * RPL + (int64_t)c * ld;
+  const int64_t cstride = (int64_t)C * ld;
+  V a[U];
+  // the first batch of column loads goes out before the residual gather completes
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (u < mcount) a[u] = load16<TS, NT>(Ap + u * cstride);
+  if (gather) {
+    for (int j = tid; j < n; j += NTH) xs[j] = (TS)t[dofs[j]];
+    __syncthreads();
+  }
+  TS acc[ng][RPL];
+#pragma unroll
+  for (int g = 0; g < ng; ++g)
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) acc[g][q] = (TS)0;
+  for (int m = 0; m < mcount; m += U) {
+    if (m > 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (m + u < mcount) a[u] = load16<TS, NT>(Ap + (int64_t)(m + u) * cstride);
+    }
+    // column c + C (m + u) is in local group (m + u) mod ng = u mod ng (U is a multiple of 8)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (m + u < mcount) {
+        const TS xj = xs[c + C * (m + u)];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) acc[u % ng][q] += a[u][q] * xj;
+      }
+    }
+  }
+  if (active) {
+    // in-register tree levels: global group c + C g; xor offset o >= C is local xor o / C
+#pragma unroll
+    for (int o = 4; o >= C; o >>= 1) {
+      const int lo = o / C;
+#pragma unroll
+      for (int g = 0; g < ng; ++g)
+        if (!(g & lo))
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) acc[g][q] = acc[g][q] + acc[g | lo][q];
+    }
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) red[c * rows + r * RPL + q] = acc[0][q];
+  }
+  __syncthreads();
+  // cross-slot tree levels (offsets C/2 .. 1) and the store
+  for (int el = tid; el < rows; el += NTH) {
+    const int row = r0 + el;
+    TS w[C];
+#pragma unroll
+    for (int cc = 0; cc < C; ++cc) w[cc] = red[cc * rows + el];
+#pragma unroll
+    for (int o = C / 2; o >= 1; o >>= 1)
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc)
+        if (!(cc & o)) w[cc] = w[cc] + w[cc | o];
+    if (row < n) dout[row] = w[0];
+  }
+  __syncthreads();
+}
+
+// meta[i] = {first slot, n, inverse offset (low, high 32 bits)} of the i-th
+// patch in processing order.
+template <typename TS, int W, bool NT>
+__global__ void __launch_bounds__(64 * W) patch_apply_kernel(const int4* __restrict__ meta,
                                                              const int* __restrict__ pdofs,
-                                                             const int64_t* __restrict__ inv_off,
                                                              const TS* __restrict__ inv,
                                                              const double* __restrict__ t,
                                                              TS* __restrict__ delta) {
   constexpr int RPL = 16 / sizeof(TS);
-  constexpr int NT = 64 * W;
-  using V = typename vec16<TS>::type;
+  constexpr int NTH = 64 * W;
   __shared__ TS xs[256];
   __shared__ TS red[8 * 64 * RPL];
-  const int p = order[blockIdx.x];
-  const int base = pptr[p];
-  const int n = pptr[p + 1] - base;
-  const int tid = threadIdx.x;
-  if (n > 256) return;  // the host rejects patches above 256 DoFs; never taken
-  for (int j = tid; j < n; j += NT) xs[j] = (TS)t[pdofs[base + j]];
-  __syncthreads();
+  const int4 m4 = meta[blockIdx.x];
+  const int base = m4.x, n = m4.y;
+  const int64_t off = (int64_t)(uint32_t)m4.z | ((int64_t)m4.w << 32);
+  if (n > 256 || n <= 0) return;  // the host rejects patches above 256 DoFs; never taken
   const int ld = (n + RPL - 1) / RPL * RPL;
-  const TS* A = inv + inv_off[p];
+  const TS* A = inv + off;
   for (int r0 = 0; r0 < ld; r0 += 64 * RPL) {
     const int rows = min(ld - r0, 64 * RPL);
     const int R = rows / RPL;
-    int C = NT / R;
-    C = C >= 8 ? 8 : C >= 4 ? 4 : C >= 2 ? 2 : 1;
-    const int r = tid % R, c = tid / R;
-    if (c < C) {
-      constexpr int G = 8;
-      const int ng = G / C;  // groups owned by this slot: c, c + C, ...
-      TS acc[G][RPL];
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int u = 0; u < RPL; ++u) acc[g][u] = (TS)0;
-      const TS* Ap = A + r0 + r * RPL;
-      // columns j = c + C * m; group of j is j mod 8 = c + C * (m mod ng)
-      for (int j0 = c; j0 < n; j0 += 8) {
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-          if (g < ng) {
-            const int j = j0 + g * C;
-            if (j < n) {
-              const V a = __builtin_nontemporal_load(reinterpret_cast<const V*>(Ap + (int64_t)j * ld));
-              const TS xj = xs[j];
-#pragma unroll
-              for (int u = 0; u < RPL; ++u) acc[g][u] += a[u] * xj;
-            }
-          }
-        }
-      }
-      // in-register tree levels: local group index g <-> global group c + C g;
-      // xor offset o >= C in global index is xor (o / C) in local index
-#pragma unroll
-      for (int o = 4; o >= 1; o >>= 1) {
-        if (o < C) break;
-        const int lo = o / C;
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-          if (g < ng && !(g & lo))
-#pragma unroll
-            for (int u = 0; u < RPL; ++u) acc[g][u] = acc[g][u] + acc[g | lo][u];
-      }
-#pragma unroll
-      for (int u = 0; u < RPL; ++u) red[c * rows + r * RPL + u] = acc[0][u];
-    }
-    __syncthreads();
-    // cross-slot tree levels (offsets C/2 .. 1) and the store
-    for (int el = tid; el < rows; el += NT) {
-      const int row = r0 + el;
-      TS w[8];
-#pragma unroll
-      for (int cc = 0; cc < 8; ++cc) w[cc] = cc < C ? red[cc * rows + el] : (TS)0;
-#pragma unroll
-      for (int o = 4; o >= 1; o >>= 1)
-        if (o < C)
-#pragma unroll
-          for (int cc = 0; cc < 8; ++cc)
-            if (cc < C && !(cc & o)) w[cc] = w[cc] + w[cc | o];
-      if (row < n) delta[base + row] = w[0];
-    }
-    __syncthreads();
+    const int Cm = NTH / R;
+    const bool g = r0 == 0;
+    const int* dofs = pdofs + base;
+    TS* dout = delta + base;
+    if (Cm >= 8) apply_pass<TS, NTH, NT, 8>(A, n, ld, r0, rows, g, dofs, t, xs, red, dout);
+    else if (Cm >= 4) apply_pass<TS, NTH, NT, 4>(A, n, ld, r0, rows, g, dofs, t, xs, red, dout);
+    else if (Cm >= 2) apply_pass<TS, NTH, NT, 2>(A, n, ld, r0, rows, g, dofs, t, xs, red, dout);
+    else apply_pass<TS, NTH, NT, 1>(A, n, ld, r0, rows, g, dofs, t, xs, red, dout);
   }
 }
 
-template <typename TS>
-static void apply_dispatch(int waves, int count, const int* order, const int* pptr, const int* pdofs,
-                           const int64_t* inv_off, const TS* inv, const double* t, TS* delta, hipStream_t s) {
+template <typename TS, bool NT>
+static void apply_dispatch(int waves, int count, const int4* meta, const int* pdofs, const TS* inv, const double* t,
+                           TS* delta, hipStream_t s) {
   if (count <= 0) return;
   switch (waves) {
-    case 1: patch_apply_kernel<TS, 1><<<count, 64, 0, s>>>(order, pptr, pdofs, inv_off, inv, t, delta); break;
-    case 2: patch_apply_kernel<TS, 2><<<count, 128, 0, s>>>(order, pptr, pdofs, inv_off, inv, t, delta); break;
-    default: patch_apply_kernel<TS, 4><<<count, 256, 0, s>>>(order, pptr, pdofs, inv_off, inv, t, delta); break;
+    case 1: patch_apply_kernel<TS, 1, NT><<<count, 64, 0, s>>>(meta, pdofs, inv, t, delta); break;
+    case 2: patch_apply_kernel<TS, 2, NT><<<count, 128, 0, s>>>(meta, pdofs, inv, t, delta); break;
+    default: patch_apply_kernel<TS, 4, NT><<<count, 256, 0, s>>>(meta, pdofs, inv, t, delta); break;
   }
 }
 
-void launch_patch_apply(bool fp32, int waves, int count, const int* order, const int* pptr, const int* pdofs,
-                        const int64_t* inv_off, const void* inv, const double* t, void* delta, hipStream_t s) {
-  if (fp32)
-    apply_dispatch<float>(waves, count, order, pptr, pdofs, inv_off, (const float*)inv, t, (float*)delta, s);
-  else
-    apply_dispatch<double>(waves, count, order, pptr, pdofs, inv_off, (const double*)inv, t, (double*)delta, s);
+void launch_patch_apply(bool fp32, int waves, bool nontemporal, int count, const int4* meta, const int* pdofs,
+                        const void* inv, const double* t, void* delta, hipStream_t s) {
+  if (fp32) {
+    if (nontemporal) apply_dispatch<float, true>(waves, count, meta, pdofs, (const float*)inv, t, (float*)delta, s);
+    else apply_dispatch<float, false>(waves, count, meta, pdofs, (const float*)inv, t, (float*)delta, s);
+  } else {
+    if (nontemporal) apply_dispatch<double, true>(waves, count, meta, pdofs, (const double*)inv, t, (double*)delta, s);
+    else apply_dispatch<double, false>(waves, count, meta, pdofs, (const double*)inv, t, (double*)delta, s);
+  }
 }
 
 // ============================================================================

@@ -29,10 +29,12 @@ void launch_gather_dense(int nmax, int first, int count, const int* pptr, const 
 // Copy one stored inverse (double or float, padded) to a dense n x n double array.
 void launch_copy_inverse(bool fp32, int n, const void* inv, int64_t off, double* out, hipStream_t s);
 
-// delta_i = K_i^{-1} t[I_i] for the `count` patches order[0..count) with
-// `waves` (1, 2 or 4) wavefronts per patch.  Results do not depend on `waves`.
-void launch_patch_apply(bool fp32, int waves, int count, const int* order, const int* pptr, const int* pdofs,
-                        const int64_t* inv_off, const void* inv, const double* t, void* delta, hipStream_t s);
+// delta_i = K_i^{-1} t[I_i] for `count` patches described by meta[0..count)
+// ({first slot, n, inverse offset low, high}) with `waves` (1, 2 or 4)
+// wavefronts per patch; `nontemporal` streams the inverses past the caches.
+// Results depend on neither.
+void launch_patch_apply(bool fp32, int waves, bool nontemporal, int count, const int4* meta, const int* pdofs,
+                        const void* inv, const double* t, void* delta, hipStream_t s);
 
 // x[d] += scale[d] * sum_{slots of d, ascending patch id} delta[slot]
 void launch_scatter(bool fp32, int N, const int* dptr, const int* dslot, const void* delta, const double* scale,
