@@ -71,6 +71,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="p4p3-64", choices=sorted(WORKLOADS))
     ap.add_argument("--store", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay every Arnoldi step from a captured HIP graph (the apply kernel is then not "
+                         "event-timed; the roofline entry is omitted)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy (y = x), the reference for HBM counter scaling")
@@ -103,6 +106,8 @@ def main():
     w = WORKLOADS[args.workload]
     store = vk.VK_STORE_FP32 if args.store == "fp32" else vk.VK_STORE_FP64
     torch.cuda.init()
+    stream = torch.cuda.Stream()  # a non-default stream (needed for graph capture)
+    torch.cuda.set_stream(stream)
     t0 = time.perf_counter()
     H = vk.Hierarchy(w["k"], w["n0"], w["levels"], store=store)
     t_host = time.perf_counter() - t0
@@ -119,16 +124,16 @@ def main():
     b = torch.tensor(H.rhs(), device="cuda")
     x = torch.empty_like(b)
     for _ in range(args.warmup):
-        res = H.solve(b, x)
+        res = H.solve(b, x, graphs=args.graphs)
     torch.cuda.synchronize()
-    H.kernel_timing(enable=True, reset=True)
+    H.kernel_timing(enable=not args.graphs, reset=True)
     lat = []
     its = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
-        res = H.solve(b, x)
+        res = H.solve(b, x, graphs=args.graphs)
         lat.append(time.perf_counter() - s0)
         its.append(res["iterations"])
         if not res["converged"]:
@@ -143,7 +148,7 @@ def main():
     s = 4 if store == vk.VK_STORE_FP32 else 8
     apply_bytes = info.sum_n2 * s + info.sum_n * (4 + 8 + s)
     avg_s = kms / 1e3 / max(launches, 1)
-    achieved = apply_bytes / avg_s / 1e9
+    achieved = apply_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
     out = {
         "metric": "Stokes solves/s to 1e-10 rel. residual",
         "value": solves_per_s,
@@ -158,7 +163,8 @@ def main():
         "dtype": "f64" if store == vk.VK_STORE_FP64 else "f64 (patch inverses stored/applied in f32)",
         "data": "synthetic (manufactured solution)",
         "config": {"workload": w["desc"], "dofs_free": info.n_free, "nnz": info.nnz, "patches": info.n_patches,
-                   "patch_dofs_sum": info.sum_n, "max_patch": info.max_n, "store": args.store},
+                   "patch_dofs_sum": info.sum_n, "max_patch": info.max_n, "store": args.store,
+                   "graphs": args.graphs},
         "iterations": its_mean,
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
         "vanka_dof_sweeps_per_s_finest": info.n_free * 4 * its_mean * solves_per_s,
@@ -170,6 +176,8 @@ def main():
                      "algorithmic_bytes_per_launch": apply_bytes, "avg_launch_us": avg_s * 1e6,
                      "launches": launches},
     }
+    if args.graphs:
+        out.pop("roofline")
     if not args.no_cpu_baseline:
         env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
                    HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")

@@ -108,6 +108,8 @@ typedef struct vk_solve_opts {
   double rtol;  /* stop when ||b - K x||_2 <= rtol ||b||_2 (1e-10) */
   int nu_pre;   /* pre-smoothing sweeps per level (2) */
   int nu_post;  /* post-smoothing sweeps per level (2) */
+  int use_graphs; /* 1: replay each Arnoldi step (V-cycle, SpMV, CGS2) from a HIP graph
+                     captured on first use; needs a non-default bound stream */
 } vk_solve_opts;
 
 typedef struct vk_solve_info {

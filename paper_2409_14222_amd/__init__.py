@@ -51,7 +51,8 @@ class vk_tuning(ctypes.Structure):
 
 
 class vk_solve_opts(ctypes.Structure):
-    _fields_ = [("restart", _c_int), ("maxit", _c_int), ("rtol", _c_dbl), ("nu_pre", _c_int), ("nu_post", _c_int)]
+    _fields_ = [("restart", _c_int), ("maxit", _c_int), ("rtol", _c_dbl), ("nu_pre", _c_int), ("nu_post", _c_int),
+                ("use_graphs", _c_int)]
 
 
 class vk_solve_info(ctypes.Structure):
@@ -224,8 +225,8 @@ class Hierarchy:
     def vcycle(self, r, e, nu_pre=2, nu_post=2):
         check(lib.vk_vcycle(self.h, _ptr(r), _ptr(e), nu_pre, nu_post))
 
-    def solve(self, b, x, restart=30, maxit=100, rtol=1e-10, nu_pre=2, nu_post=2, history=False):
-        opts = vk_solve_opts(restart, maxit, rtol, nu_pre, nu_post)
+    def solve(self, b, x, restart=30, maxit=100, rtol=1e-10, nu_pre=2, nu_post=2, history=False, graphs=False):
+        opts = vk_solve_opts(restart, maxit, rtol, nu_pre, nu_post, int(graphs))
         hist = np.zeros(maxit + 1) if history else None
         info = vk_solve_info(0, 0, 0.0, hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if history else None)
         status = check(lib.vk_solve(self.h, _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(info)))

@@ -7,7 +7,9 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -77,6 +79,9 @@ struct vk_hierarchy {
   int* singular = nullptr;
   std::vector<double> ybuf;
   std::vector<std::vector<int4>> meta_host;  // staging of the per-patch metadata uploads
+  // captured FGMRES iterations, keyed by (j, restart, nu_pre, nu_post)
+  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
+  bool capturing = false;
   // kernel timing of the finest-level patch apply
   bool timing = false;
   int64_t t_launches = 0;
@@ -168,9 +173,14 @@ void require_level(const vk_hierarchy* h, int level, int lo) {
 }
 
 // ---------------------------------------------------------------- smoother
+void drop_graphs(vk_hierarchy* h) {
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
+  h->graphs.clear();
+}
+
 void patch_apply(vk_hierarchy* h, int l, const double* t) {
   DevLevel& d = h->D[l];
-  const bool timed = h->timing && l == h->L() - 1;
+  const bool timed = h->timing && !h->capturing && l == h->L() - 1;
   std::pair<hipEvent_t, hipEvent_t> ev;
   if (timed) {
     if (h->ev_free.empty()) {
@@ -255,6 +265,58 @@ void collect_timing(vk_hierarchy* h) {
   h->ev_pending.clear();
 }
 
+// One Arnoldi step of FGMRES: z_j = V-cycle(v_j), w = K z_j, two classical
+// Gram-Schmidt passes against v_0..v_j (coefficients and |w|^2 left in
+// `small`), v_{j+1} = w / |w|.  Everything stays on the device.
+void arnoldi_step(vk_hierarchy* h, int j, const vk_solve_opts& o) {
+  const int N = h->H.back().N;
+  const int m = o.restart;
+  const hipStream_t s = h->stream;
+  DevLevel& F = h->D[h->L() - 1];
+  double* vj = h->V + (size_t)j * N;
+  double* zj = h->Z + (size_t)j * N;
+  double* w = h->V + (size_t)(j + 1) * N;
+  vcycle(h, h->L() - 1, vj, zj, o.nu_pre, o.nu_post);
+  launch_csr(0, N, F.k_lanes, F.rowptr, F.col, F.val, zj, nullptr, w, s);
+  launch_multidot(N, j + 1, h->V, N, w, h->partial, h->small, s);
+  launch_multiaxpy(N, j + 1, -1.0, h->V, N, h->small, w, s);
+  launch_multidot(N, j + 1, h->V, N, w, h->partial, h->small + (m + 2), s);
+  launch_multiaxpy(N, j + 1, -1.0, h->V, N, h->small + (m + 2), w, s);
+  launch_multidot(N, 1, w, 0, w, h->partial, h->small + 2 * (m + 2), s);
+  launch_div_norm(N, w, h->small + 2 * (m + 2), s);
+  check_launch();
+}
+
+// The same step replayed from a HIP graph captured on first use (one graph
+// per (j, restart, nu_pre, nu_post); dropped when launch shapes change).
+void arnoldi_step_graph(vk_hierarchy* h, int j, const vk_solve_opts& o) {
+  const auto key = std::make_tuple(j, o.restart, o.nu_pre, o.nu_post);
+  auto it = h->graphs.find(key);
+  if (it == h->graphs.end()) {
+    const hipStream_t s = h->stream;
+    require(s != nullptr, VK_EINVAL, "graph capture needs a non-default stream");
+    hipGraph_t g = nullptr;
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    h->capturing = true;
+    try {
+      arnoldi_step(h, j, o);
+    } catch (...) {
+      h->capturing = false;
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    h->capturing = false;
+    HIPCHECK(hipStreamEndCapture(s, &g));
+    hipGraphExec_t ge = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHECK(e);
+    it = h->graphs.emplace(key, ge).first;
+  }
+  HIPCHECK(hipGraphLaunch(it->second, h->stream));
+}
+
 // FGMRES(m) preconditioned by one V-cycle (right preconditioning, stored Z).
 vk_status fgmres(vk_hierarchy* h, const double* b_in, double* x, const vk_solve_opts& o, vk_solve_info* info) {
   const int N = h->H.back().N;
@@ -292,25 +354,14 @@ vk_status fgmres(vk_hierarchy* h, const double* b_in, double* x, const vk_solve_
     launch_div(N, h->r, beta, h->V, s);
     int jlast = -1;
     for (int j = 0; j < m; ++j) {
-      double* vj = h->V + (size_t)j * N;
-      double* zj = h->Z + (size_t)j * N;
-      double* w = h->V + (size_t)(j + 1) * N;
-      vcycle(h, Lf, vj, zj, o.nu_pre, o.nu_post);
-      launch_csr(0, N, F.k_lanes, F.rowptr, F.col, F.val, zj, nullptr, w, s);
-      // CGS2: two classical Gram-Schmidt passes against v_0..v_j
-      launch_multidot(N, j + 1, h->V, N, w, h->partial, h->small, s);
-      launch_multiaxpy(N, j + 1, -1.0, h->V, N, h->small, w, s);
-      launch_multidot(N, j + 1, h->V, N, w, h->partial, h->small + (m + 2), s);
-      launch_multiaxpy(N, j + 1, -1.0, h->V, N, h->small + (m + 2), w, s);
-      launch_multidot(N, 1, w, 0, w, h->partial, h->small + 2 * (m + 2), s);
-      check_launch();
+      if (o.use_graphs) arnoldi_step_graph(h, j, o);
+      else arnoldi_step(h, j, o);
       HIPCHECK(hipMemcpyAsync(hh.data(), h->small, 3 * (m + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHECK(hipStreamSynchronize(s));
       const double hn = std::sqrt(hh[2 * (m + 2)]);
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[(m + 2) + i];
       H[(size_t)(j + 1) * m + j] = hn;
       require(std::isfinite(hn), VK_ENAN, "Arnoldi breakdown to a non-finite value");
-      if (hn > 0.0) launch_div(N, w, hn, w, s);
       for (int i = 0; i < j; ++i) {
         const double a = H[(size_t)i * m + j], c2 = H[(size_t)(i + 1) * m + j];
         H[(size_t)i * m + j] = cs[i] * a + sn[i] * c2;
@@ -498,6 +549,7 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
 vk_status vk_hierarchy_destroy(vk_hierarchy* h) {
   return guarded([&]() -> vk_status {
     if (!h) return VK_OK;
+    drop_graphs(h);
     for (auto& e : h->ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (auto& e : h->ev_pending) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     delete h;
@@ -530,6 +582,7 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_r
     require(bytes >= dry.off, VK_ENOMEM, "workspace too small");
     h->stream = (hipStream_t)stream;
     h->max_restart = max_restart;
+    drop_graphs(h);
     Carver cv(d_ws);
     carve(h->H, h->fp32(), h, cv, max_restart);
     h->meta_host.clear();
@@ -807,6 +860,7 @@ vk_status vk_autotune(vk_hierarchy* h, int reps) {
   return guarded([&]() -> vk_status {
     require_ready(h);
     require(reps >= 1 && reps <= 1000, VK_EINVAL, "reps out of range");
+    drop_graphs(h);
     autotune(h, reps);
     return VK_OK;
   });
@@ -838,6 +892,7 @@ vk_status vk_tuning_set(vk_hierarchy* h, int level, const vk_tuning* t) {
     auto okw = [](int v) { return v == 1 || v == 2 || v == 4; };
     require(okl(t->k_lanes) && okl(t->p_lanes) && okl(t->pt_lanes), VK_EINVAL, "lanes must be 4, 8, 16, 32 or 64");
     require(okw(t->apply_waves_large) && okw(t->apply_waves_small), VK_EINVAL, "waves must be 1, 2 or 4");
+    drop_graphs(h);
     DevLevel& d = h->D[level];
     d.k_lanes = t->k_lanes;
     d.p_lanes = t->p_lanes;

@@ -578,6 +578,15 @@ __global__ void __launch_bounds__(256) fill_kernel(int n, double v, double* __re
   if (i < n) y[i] = v;
 }
 
+__global__ void __launch_bounds__(256) div_norm_kernel(int n, double* y, const double* __restrict__ nn) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = y[i] / sqrt(nn[0]);
+}
+
+void launch_div_norm(int n, double* y, const double* nn, hipStream_t s) {
+  div_norm_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, y, nn);
+}
+
 void launch_div(int n, const double* x, double alpha, double* y, hipStream_t s) {
   div_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, x, alpha, y);
 }

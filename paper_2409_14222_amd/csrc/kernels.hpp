@@ -57,6 +57,8 @@ void launch_multiaxpy(int n, int nv, double sign, const double* V, int64_t ldv, 
                       hipStream_t s);
 // y = x / alpha
 void launch_div(int n, const double* x, double alpha, double* y, hipStream_t s);
+// y = y / sqrt(nn[0]), nn a device scalar (squared norm)
+void launch_div_norm(int n, double* y, const double* nn, hipStream_t s);
 void launch_copy(int n, const double* x, double* y, hipStream_t s);
 void launch_fill(int n, double v, double* y, hipStream_t s);
 // x[p] -= (sum_{q in [p0,n)} x[q] zv) zv for p in [p0, n): removal of the constant pressure
