@@ -26,6 +26,9 @@ WORKLOADS = {
                                            "5-level hierarchy, composite Vanka, V(2,2), omega 0.5, FGMRES(30) to 1e-10"),
     "p2p1-16": dict(k=2, n0=4, levels=3, desc="P2-P1 Taylor-Hood, 16x16 two-triangle mesh of the unit square, "
                                            "3-level hierarchy, vertex Vanka, V(2,2), omega 0.5, FGMRES(30) to 1e-10"),
+    "p2p1-3d-16": dict(k=2, n0=4, levels=3, dim=3,
+                       desc="3D P2-P1 Taylor-Hood, 16^3 cubes each split into 6 Kuhn tetrahedra, 3-level hierarchy "
+                            "(4^3, 8^3, 16^3), vertex Vanka (up to 196 DoFs), V(2,2), omega 0.5, FGMRES(30) to 1e-10"),
 }
 HBM_PEAK_GBS = 8000.0
 
@@ -51,7 +54,8 @@ def cpu_sample(workload, iterations):
     import synth
     from oracle import fields, solve
     w = WORKLOADS[workload]
-    H, V = solve.setup(2, w["k"], w["n0"], w["levels"], 1.0, fields.baseline_mms)
+    dim = w.get("dim", 2)
+    H, V = solve.setup(dim, w["k"], w["n0"], w["levels"], 1.0, fields.cube_mms if dim == 3 else fields.baseline_mms)
     L = H.finest
     v = synth.vector(L.N, 1)
     v /= np.linalg.norm(v)
@@ -109,7 +113,9 @@ def main():
     stream = torch.cuda.Stream()  # a non-default stream (needed for graph capture)
     torch.cuda.set_stream(stream)
     t0 = time.perf_counter()
-    H = vk.Hierarchy(w["k"], w["n0"], w["levels"], store=store)
+    dim = w.get("dim", 2)
+    H = vk.Hierarchy(w["k"], w["n0"], w["levels"], dim=dim, store=store,
+                     forcing=vk.VK_F_CUBE_MMS if dim == 3 else vk.VK_F_BASELINE_MMS)
     t_host = time.perf_counter() - t0
     t0 = time.perf_counter()
     H.bind()

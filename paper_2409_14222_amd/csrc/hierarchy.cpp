@@ -40,7 +40,7 @@ struct DevLevel {
   void* delta = nullptr;
   double *b = nullptr, *x = nullptr, *t = nullptr;
   double* M = nullptr;  // coarsest level
-  int class_count[3] = {0, 0, 0};  // patches with n <= 32, <= 64, <= 128 (ids in `classes`)
+  int class_count[4] = {0, 0, 0, 0};  // patches with n <= 32, <= 64, <= 128, <= 224 (ids in `classes`)
   // launch shapes (never change results): lanes per CSR row of K, P, P^T;
   // waves per patch for the large (n > 64, first in `order`) and small patches
   int k_lanes = 32, p_lanes = 8, pt_lanes = 8, waves_large = 1, waves_small = 1, n_large = 0;
@@ -526,7 +526,7 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
       if (l > 0) {
         build_prolongation(h->H[l - 1], L);
         build_patches(L, opts->construct, opts->omega, opts->store);
-        require(L.max_n <= 128, VK_EINVAL, "patches above 128 DoFs are not supported");
+        require(L.max_n <= 224, VK_EINVAL, "patches above 224 DoFs are not supported");
       }
     }
     h->coarse_M = bordered_inverse(h->H[0]);
@@ -534,8 +534,8 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
     for (int l = 1; l < p.n_levels; ++l) {
       const LevelHost& L = h->H[l];
       std::vector<int>& cl = h->class_lists[l];
-      const int lim[3] = {32, 64, 128};
-      for (int c = 0; c < 3; ++c)
+      const int lim[4] = {32, 64, 128, 224};
+      for (int c = 0; c < 4; ++c)
         for (int i = 0; i + 1 < (int)L.pptr.size(); ++i) {
           const int n = L.pptr[i + 1] - L.pptr[i];
           if (n <= lim[c] && (c == 0 || n > lim[c - 1])) cl.push_back(i);
@@ -622,8 +622,8 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_r
         up(d.meta, h->meta_host.back(), s);
       }
       up(d.scale, L.scale, s);
-      const int lim[3] = {32, 64, 128};
-      for (int c = 0; c < 3; ++c) {
+      const int lim[4] = {32, 64, 128, 224};
+      for (int c = 0; c < 4; ++c) {
         d.class_count[c] = 0;
         for (int i = 0; i + 1 < (int)L.pptr.size(); ++i) {
           const int n = L.pptr[i + 1] - L.pptr[i];
@@ -647,8 +647,8 @@ vk_status vk_patches_setup(vk_hierarchy* h) {
       std::vector<int> init(1, INT_MAX);
       HIPCHECK(hipMemcpyAsync(h->singular, init.data(), sizeof(int), hipMemcpyHostToDevice, s));
       int first = 0;
-      const int lim[3] = {32, 64, 128};
-      for (int c = 0; c < 3; ++c) {
+      const int lim[4] = {32, 64, 128, 224};
+      for (int c = 0; c < 4; ++c) {
         launch_gather_invert(lim[c], h->fp32(), d.class_count[c], d.classes + first, d.pptr, d.pdofs, d.rowptr,
                              d.col, d.val, d.inv_off, d.inv, h->singular, s);
         check_launch();

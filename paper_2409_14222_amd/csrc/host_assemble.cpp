@@ -462,7 +462,12 @@ std::vector<double> bordered_inverse(const LevelHost& L) {
     A[(size_t)N * M + r] = zv;
   }
   // Gauss-Jordan inversion with partial pivoting (row swaps undone as column
-  // swaps at the end)
+  // swaps at the end).  A pivot below M * eps * max|a| means the coarsest
+  // system is singular beyond the constant pressure (e.g. spurious pressure
+  // modes on a too coarse mesh) and is reported instead of inverted.
+  double amax = 0.0;
+  for (double v : A) amax = std::max(amax, std::fabs(v));
+  const double tiny = M * 2.220446049250313e-16 * amax;
   std::vector<int> perm(M);
   for (int c = 0; c < M; ++c) {
     int p = c;
@@ -471,7 +476,7 @@ std::vector<double> bordered_inverse(const LevelHost& L) {
       double v = std::fabs(A[(size_t)r * M + c]);
       if (v > best) { best = v; p = r; }
     }
-    require(best > 0.0, VK_ESINGULAR, "coarsest bordered matrix is singular");
+    require(best > tiny, VK_ESINGULAR, "coarsest bordered matrix is singular (refine the coarsest mesh)");
     perm[c] = p;
     if (p != c)
       for (int j = 0; j < M; ++j) std::swap(A[(size_t)c * M + j], A[(size_t)p * M + j]);

@@ -219,6 +219,207 @@ __global__ void __launch_bounds__(256) gather_invert_kernel(const int* __restric
   }
 }
 
+// ============================================================================
+// Gauss-Jordan for patches with 128 < n <= 224 (3D vertex stars reach 196):
+// the FP64 tile (up to 392 KiB) does not fit in LDS, so it lives in registers.
+// 512 threads form a 32 x 16 grid; thread (ti, tj) owns the elements
+// (ti + 32 x, tj + 16 y), x < 7, y < 14, of the tile padded with the identity
+// to 224 x 224 (the padding never pivots and stays the identity).  Per step
+// only the pivot column and the normalised pivot row pass through LDS.  The
+// tile is gathered from the CSR matrix in slabs of 32 rows.
+// ============================================================================
+template <typename TS>
+__global__ void __launch_bounds__(1024) gather_invert_big_kernel(const int* __restrict__ list,
+                                                                const int* __restrict__ pptr,
+                                                                const int* __restrict__ pdofs,
+                                                                const int* __restrict__ rowptr,
+                                                                const int* __restrict__ col,
+                                                                const double* __restrict__ val,
+                                                                const int64_t* __restrict__ inv_off,
+                                                                TS* __restrict__ inv, int* __restrict__ singular) {
+  constexpr int TX = 32, TY = 32, NX = 7, NY = 7, T = 224, NT = 1024;
+  __shared__ double slab[TX * T];
+  __shared__ int Ii[T];
+  __shared__ double colk[T], prow[T], qrow[T], nrow[T];
+  __shared__ int perm[T];
+  __shared__ int piv_s, sing_s;
+  const int tid = threadIdx.x, ti = tid & (TX - 1), tj = tid >> 5;
+  const int p = list[blockIdx.x];
+  const int base = pptr[p];
+  const int n = pptr[p + 1] - base;
+  if (n > T || n <= 0) return;  // the host sorts patches into size classes; never taken
+  for (int i = tid; i < n; i += NT) Ii[i] = pdofs[base + i];
+  if (tid == 0) sing_s = 0;
+  double a[NX][NY];
+  const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll 1
+  for (int x = 0; x < NX; ++x) {
+    __syncthreads();
+    for (int e = tid; e < TX * T; e += NT) slab[e] = 0.0;
+    __syncthreads();
+    for (int r = wave; r < TX; r += NT / 64) {
+      const int l = TX * x + r;
+      if (l >= n) continue;
+      const int g = Ii[l];
+      for (int q = rowptr[g] + lane; q < rowptr[g + 1]; q += 64) {
+        const int c = col[q];
+        int lo = 0, hi = n;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (Ii[mid] < c) lo = mid + 1;
+          else hi = mid;
+        }
+        if (lo < n && Ii[lo] == c) slab[r * T + lo] = val[q];
+      }
+    }
+    __syncthreads();
+    const int i = ti + TX * x;
+#pragma unroll
+    for (int xx = 0; xx < NX; ++xx)
+      if (xx == x)
+#pragma unroll
+        for (int y = 0; y < NY; ++y) {
+          const int j = tj + TY * y;
+          a[xx][y] = (i < n && j < n) ? slab[ti * T + j] : (i == j ? 1.0 : 0.0);
+        }
+  }
+  __syncthreads();
+
+  // k = 32 kb + kr with the block index kb unrolled, so that row block and
+  // column block of k (TX == TY) are compile-time register indices
+  static_assert(TX == TY && NX == NY, "square thread grid");
+#pragma unroll
+  for (int kb = 0; kb < NX; ++kb) {
+    for (int kr = 0; kr < TX; ++kr) {
+      const int k = TX * kb + kr;
+      if (k >= n) break;
+      if (tj == kr) {  // the 32 owners of column k: one half-wave
+        double best = -1.0;
+        int bi = T;
+#pragma unroll
+        for (int x = 0; x < NX; ++x) {
+          const int i = ti + TX * x;
+          const double v = fabs(a[x][kb]);
+          if (i >= k && i < n && v > best) { best = v; bi = i; }
+        }
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off, 32);
+          const int oi = __shfl_xor(bi, off, 32);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (ti == 0) {
+          piv_s = bi;
+          if (!(best > 0.0) || bi >= n) sing_s = 1;
+        }
+      }
+      __syncthreads();
+      if (sing_s) break;
+      const int pr = piv_s, px = pr / TX, prr = pr % TX;
+      // rows pr (the new row k) and k to LDS
+      if (ti == prr) {
+#pragma unroll
+        for (int x = 0; x < NX; ++x)
+          if (x == px)
+#pragma unroll
+            for (int y = 0; y < NY; ++y) prow[tj + TY * y] = a[x][y];
+      }
+      if (pr != k && ti == kr) {
+#pragma unroll
+        for (int y = 0; y < NY; ++y) qrow[tj + TY * y] = a[kb][y];
+      }
+      if (tid == 0) perm[k] = pr;
+      __syncthreads();
+      if (pr != k) {
+        if (ti == kr) {
+#pragma unroll
+          for (int y = 0; y < NY; ++y) a[kb][y] = prow[tj + TY * y];
+        }
+        if (ti == prr) {
+#pragma unroll
+          for (int x = 0; x < NX; ++x)
+            if (x == px)
+#pragma unroll
+              for (int y = 0; y < NY; ++y) a[x][y] = qrow[tj + TY * y];
+        }
+      }
+      // post-swap column k and the normalised pivot row
+      if (tj == kr) {
+#pragma unroll
+        for (int x = 0; x < NX; ++x) colk[ti + TX * x] = a[x][kb];
+      }
+      const double piv = prow[k];
+      for (int j = tid; j < T; j += NT) nrow[j] = (j == k ? 1.0 : prow[j]) / piv;
+      __syncthreads();
+#pragma unroll
+      for (int x = 0; x < NX; ++x) {
+        const int i = ti + TX * x;
+        const double ci = colk[i];
+#pragma unroll
+        for (int y = 0; y < NY; ++y) {
+          const int j = tj + TY * y;
+          if (i == k) a[x][y] = nrow[j];
+          else a[x][y] = (j == k ? 0.0 : a[x][y]) - ci * nrow[j];
+        }
+      }
+      __syncthreads();
+    }
+    if (sing_s) break;
+  }
+  if (sing_s) {
+    if (tid == 0) atomicMin(singular, p);
+    return;
+  }
+  // undo the row interchanges as column interchanges, last first
+#pragma unroll
+  for (int kb = NX - 1; kb >= 0; --kb) {
+    for (int kr = TX - 1; kr >= 0; --kr) {
+      const int k = TX * kb + kr;
+      if (k >= n) continue;
+      const int pr = perm[k];
+      if (pr == k) continue;  // uniform: perm is in LDS
+      const int py = pr / TY, pc = pr % TY;
+      if (tj == kr) {
+#pragma unroll
+        for (int x = 0; x < NX; ++x) colk[ti + TX * x] = a[x][kb];
+      }
+      if (tj == pc) {
+#pragma unroll
+        for (int y = 0; y < NY; ++y)
+          if (y == py)
+#pragma unroll
+            for (int x = 0; x < NX; ++x) qrow[ti + TX * x] = a[x][y];
+      }
+      __syncthreads();
+      if (tj == kr) {
+#pragma unroll
+        for (int x = 0; x < NX; ++x) a[x][kb] = qrow[ti + TX * x];
+      }
+      if (tj == pc) {
+#pragma unroll
+        for (int y = 0; y < NY; ++y)
+          if (y == py)
+#pragma unroll
+            for (int x = 0; x < NX; ++x) a[x][y] = colk[ti + TX * x];
+      }
+      __syncthreads();
+    }
+  }
+  constexpr int RPL = 16 / sizeof(TS);
+  const int ld = (n + RPL - 1) / RPL * RPL;
+  TS* out = inv + inv_off[p];
+#pragma unroll
+  for (int y = 0; y < NY; ++y) {
+    const int j = tj + TY * y;
+    if (j >= n) continue;
+#pragma unroll
+    for (int x = 0; x < NX; ++x) {
+      const int i = ti + TX * x;
+      if (i < ld) out[(int64_t)j * ld + i] = (TS)a[x][y];
+    }
+  }
+}
+
 template <int NMAX>
 static void gather_invert_dispatch(bool fp32, int count, const int* list, const int* pptr, const int* pdofs,
                                    const int* rowptr, const int* col, const double* val, const int64_t* inv_off,
@@ -237,7 +438,13 @@ void launch_gather_invert(int nmax, bool fp32, int count, const int* list, const
   if (count <= 0) return;
   if (nmax <= 32) gather_invert_dispatch<32>(fp32, count, list, pptr, pdofs, rowptr, col, val, inv_off, inv, singular, s);
   else if (nmax <= 64) gather_invert_dispatch<64>(fp32, count, list, pptr, pdofs, rowptr, col, val, inv_off, inv, singular, s);
-  else gather_invert_dispatch<128>(fp32, count, list, pptr, pdofs, rowptr, col, val, inv_off, inv, singular, s);
+  else if (nmax <= 128) gather_invert_dispatch<128>(fp32, count, list, pptr, pdofs, rowptr, col, val, inv_off, inv, singular, s);
+  else if (fp32)
+    gather_invert_big_kernel<float><<<count, 1024, 0, s>>>(list, pptr, pdofs, rowptr, col, val, inv_off, (float*)inv,
+                                                          singular);
+  else
+    gather_invert_big_kernel<double><<<count, 1024, 0, s>>>(list, pptr, pdofs, rowptr, col, val, inv_off,
+                                                           (double*)inv, singular);
 }
 
 template <int NMAX>
@@ -262,9 +469,30 @@ __global__ void __launch_bounds__(256) gather_dense_kernel(int first, const int*
   for (int e = threadIdx.x; e < n * n; e += 256) o[e] = T[e];
 }
 
+// Big patches: the dense tile is zeroed and filled directly in the output.
+__global__ void __launch_bounds__(256) gather_dense_global_kernel(int first, const int* __restrict__ pptr,
+                                                                  const int* __restrict__ pdofs,
+                                                                  const int* __restrict__ rowptr,
+                                                                  const int* __restrict__ col,
+                                                                  const double* __restrict__ val,
+                                                                  const int64_t* __restrict__ out_off,
+                                                                  double* __restrict__ out) {
+  const int p = first + blockIdx.x;
+  const int base = pptr[p], n = pptr[p + 1] - base;
+  const int* Ii = pdofs + base;
+  double* o = out + out_off[blockIdx.x];
+  for (int e = threadIdx.x; e < n * n; e += 256) o[e] = 0.0;
+  __syncthreads();
+  gather_tile(n, Ii, rowptr, col, val, o);
+}
+
 void launch_gather_dense(int nmax, int first, int count, const int* pptr, const int* pdofs, const int* rowptr,
                          const int* col, const double* val, const int64_t* out_off, double* out, hipStream_t s) {
   if (count <= 0) return;
+  if (nmax > 128) {
+    gather_dense_global_kernel<<<count, 256, 0, s>>>(first, pptr, pdofs, rowptr, col, val, out_off, out);
+    return;
+  }
   if (nmax <= 32) gather_dense_kernel<32><<<count, 256, 0, s>>>(first, pptr, pdofs, rowptr, col, val, out_off, out);
   else if (nmax <= 64) gather_dense_kernel<64><<<count, 256, 0, s>>>(first, pptr, pdofs, rowptr, col, val, out_off, out);
   else gather_dense_kernel<128><<<count, 256, 0, s>>>(first, pptr, pdofs, rowptr, col, val, out_off, out);

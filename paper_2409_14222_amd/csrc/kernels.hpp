@@ -16,7 +16,7 @@ int csr_default_lanes(double mean_row);
 // Matrix-full patch setup: gather K_i = K[I_i, I_i] into LDS, invert it by
 // Gauss-Jordan with partial pivoting (FP64), store the inverse column-major
 // (leading dimension rounded to 2 doubles / 4 floats) as double or float.
-// `list` holds `count` patch ids whose size is <= nmax (32, 64 or 128).
+// `list` holds `count` patch ids whose size is <= nmax (32, 64, 128 or 224).
 // `singular` receives the smallest patch id with a zero pivot (initialise to INT_MAX).
 void launch_gather_invert(int nmax, bool fp32, int count, const int* list, const int* pptr, const int* pdofs,
                           const int* rowptr, const int* col, const double* val, const int64_t* inv_off, void* inv,

@@ -54,12 +54,23 @@ def p4p3():
     return H, OH, OV
 
 
+@pytest.fixture(scope="module")
+def p2p1_3d():
+    """3D P2-P1 on Kuhn tetrahedra, levels 2/4/8 cubes per direction (vertex patches up to 196)."""
+    import paper_2409_14222_amd as vk
+    from oracle import fields, solve
+    print("[gpu] building 3D P2-P1 8^3 hierarchy", flush=True)
+    H = vk.Hierarchy(2, 2, 3, dim=3, forcing=vk.VK_F_CUBE_MMS).bind().setup()
+    OH, OV = solve.setup(3, 2, 2, 3, 1.0, fields.cube_mms)
+    return H, OH, OV
+
+
 def _cond_bound(S):
     """max_i n_i * cond(K_i): scale of the explicit-inverse vs LU-solve difference."""
     return max(len(I) * np.linalg.cond(S.patch_matrix(i)) for i, I in enumerate(S.patches))
 
 
-@pytest.mark.parametrize("fx", ["p2p1", "p4p3"])
+@pytest.mark.parametrize("fx", ["p2p1", "p4p3", "p2p1_3d"])
 def test_spmv_and_transfers(fx, request):
     H, OH, OV = request.getfixturevalue(fx)
     for l in range(len(OH.levels)):
@@ -86,7 +97,7 @@ def test_spmv_and_transfers(fx, request):
             assert np.all(np.abs(_host(rc) - P.T @ x) <= 1e-13 * (abs(P.T) @ np.abs(x)))
 
 
-@pytest.mark.parametrize("fx", ["p2p1", "p4p3"])
+@pytest.mark.parametrize("fx", ["p2p1", "p4p3", "p2p1_3d"])
 def test_patch_gather_matches_csr_and_oracle(fx, request):
     H, OH, OV = request.getfixturevalue(fx)
     l = len(OH.levels) - 1
@@ -111,7 +122,7 @@ def test_patch_gather_matches_csr_and_oracle(fx, request):
         assert np.abs(Ki - Ko).max() <= 1e-12 * np.abs(Ko).max()  # oracle: within assembly roundoff
 
 
-@pytest.mark.parametrize("fx", ["p2p1", "p4p3"])
+@pytest.mark.parametrize("fx", ["p2p1", "p4p3", "p2p1_3d"])
 def test_patch_inverses(fx, request):
     H, OH, OV = request.getfixturevalue(fx)
     l = len(OH.levels) - 1
@@ -130,7 +141,7 @@ def test_patch_inverses(fx, request):
         assert np.abs(X - Xo).max() <= 8 * n * EPS * c * np.abs(Xo).max()
 
 
-@pytest.mark.parametrize("fx", ["p2p1", "p4p3"])
+@pytest.mark.parametrize("fx", ["p2p1", "p4p3", "p2p1_3d"])
 def test_one_sweep(fx, request):
     H, OH, OV = request.getfixturevalue(fx)
     for l in range(1, len(OH.levels)):
@@ -164,7 +175,7 @@ def test_coarse_solve(p4p3):
     assert err <= tol
 
 
-@pytest.mark.parametrize("fx", ["p2p1", "p4p3"])
+@pytest.mark.parametrize("fx", ["p2p1", "p4p3", "p2p1_3d"])
 def test_vcycle(fx, request):
     H, OH, OV = request.getfixturevalue(fx)
     L = OH.finest
@@ -182,7 +193,7 @@ def test_vcycle(fx, request):
     assert torch.equal(e, e2)
 
 
-@pytest.mark.parametrize("fx", ["p2p1", "p4p3"])
+@pytest.mark.parametrize("fx", ["p2p1", "p4p3", "p2p1_3d"])
 def test_solve_matches_oracle(fx, request):
     from oracle import solve
     H, OH, OV = request.getfixturevalue(fx)
@@ -232,7 +243,7 @@ def test_mixed_precision_solve(p4p3):
     assert np.linalg.norm(xg - xo) <= 1e-8 * np.linalg.norm(xo)
 
 
-@pytest.mark.parametrize("fx", ["p2p1", "p4p3"])
+@pytest.mark.parametrize("fx", ["p2p1", "p4p3", "p2p1_3d"])
 def test_launch_shapes_do_not_change_results(fx, request):
     """The autotuner may pick any lanes-per-row / waves-per-patch: results stay bitwise equal."""
     H, OH, OV = request.getfixturevalue(fx)
@@ -277,3 +288,21 @@ def test_graph_replays_match_eager(k, n0, nl):
             H.solve(b, x2)                      # eager work between replays
             side.synchronize()
             assert torch.equal(x2, x_eager)
+
+
+def test_mixed_precision_solve_3d(p2p1_3d):
+    """3D workload pattern: FP64 factorisation, FP32 inverses, FP64 FGMRES reaches 1e-10."""
+    import paper_2409_14222_amd as vk
+    from oracle import solve
+    H64, OH, OV = p2p1_3d
+    H = vk.Hierarchy(2, 2, 3, dim=3, forcing=vk.VK_F_CUBE_MMS, store=vk.VK_STORE_FP32).bind().setup()
+    L = OH.finest
+    x = torch.empty(L.N, dtype=torch.float64, device="cuda")
+    res = H.solve(_dev(H.rhs()), x)
+    xo, its, _, _ = solve.solve(OH, OV)
+    xg = _host(x)
+    ob = solve.consistent_rhs(L)
+    print(f"[gpu] 3D mixed: its {res['iterations']} (fp64 oracle {its}), diff {np.linalg.norm(xg - xo) / np.linalg.norm(xo):.2e}")
+    assert res["converged"] and abs(res["iterations"] - its) <= 2
+    assert res["rel_residual"] <= 1e-10
+    assert np.linalg.norm(ob - L.K @ xg) <= 1.05e-10 * np.linalg.norm(ob)

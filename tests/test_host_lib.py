@@ -107,3 +107,49 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(vk.VkError) as e:
         vk.check(vk.lib.vk_patches_setup(H.h))
     assert e.value.code == vk.VK_ESTATE
+
+
+def test_host_assembly_3d_matches_oracle():
+    """3D P2-P1 on Kuhn tetrahedra (levels 2, 4 cubes per direction)."""
+    H = vk.Hierarchy(2, 2, 2, dim=3, forcing=vk.VK_F_CUBE_MMS)
+    OH = th.THHierarchy(3, 2, 2, 2, 1.0, fields.cube_mms)
+    for l in range(2):
+        ol = OH.levels[l]
+        inf = H.level_info(l)
+        assert (inf.n_free, inf.nnz) == (ol.N, ol.K.nnz)
+        X, kind = H.dof_coords(l)
+        OX, okind = ol.dof_coords()
+        assert np.array_equal(kind, okind) and np.abs(X - OX).max() < 1e-15
+        rp, col, val = H.csr(l)
+        assert np.array_equal(rp, ol.K.indptr) and np.array_equal(col, ol.K.indices)
+        B = ol.vb
+        cV = np.linalg.cond(B._mono(B.nodes))
+        rowmax = np.maximum.reduceat(np.abs(ol.K.data), ol.K.indptr[:-1])
+        assert np.all(np.abs(val - ol.K.data) <= cV * np.finfo(float).eps * np.repeat(rowmax, np.diff(ol.K.indptr)))
+        if l > 0:
+            prp, pcol, pval = H.prolongation(l)
+            P = OH.P[l]
+            assert np.array_equal(prp, P.indptr) and np.array_equal(pcol, P.indices)
+            assert np.abs(pval - P.data).max() <= 1e-14
+            ptr, dofs = H.patches(l)
+            op = patches.build_patches(ol)
+            assert [list(dofs[ptr[i]:ptr[i + 1]]) for i in range(len(op))] == [list(I) for I in op]
+    assert np.abs(H.rhs() - solve.consistent_rhs(OH.finest)).max() <= 1e-13 * np.abs(OH.finest.b).max()
+
+
+def test_3d_counts_of_the_16_cube_hierarchy():
+    """Free DoFs and patch statistics of P2-P1 on 4^3 / 8^3 / 16^3 Kuhn meshes."""
+    H = vk.Hierarchy(2, 4, 3, dim=3, forcing=vk.VK_F_CUBE_MMS)
+    for l, n in enumerate((4, 8, 16)):
+        inf = H.level_info(l)
+        assert inf.n_free == 3 * (2 * n - 1) ** 3 + (n + 1) ** 3
+    inf = H.level_info(2)
+    assert (inf.n_patches, inf.max_n) == (17 ** 3, 196)     # interior vertex star: 65 P2 nodes x 3 + 1
+
+
+def test_singular_coarsest_level_is_reported():
+    """A single Kuhn cube has spurious P1 pressure modes: the bordered coarsest system is
+    singular beyond the constant and the library must refuse it."""
+    with pytest.raises(vk.VkError) as e:
+        vk.Hierarchy(2, 1, 2, dim=3, forcing=vk.VK_F_CUBE_MMS)
+    assert e.value.code == vk.VK_ESINGULAR
