@@ -137,13 +137,14 @@ vk_status vk_hierarchy_destroy(vk_hierarchy* h);
 
 /* Bytes of device workspace needed by vk_hierarchy_bind (all levels, the
  * patch inverses in the chosen precision, the V-cycle vectors and an FGMRES
- * basis of max_restart vectors). */
-vk_status vk_hierarchy_workspace_bytes(const vk_hierarchy* h, int max_restart, size_t* bytes);
+ * basis of max_restart vectors, each for up to max_rhs (1..64) right-hand
+ * sides solved together). */
+vk_status vk_hierarchy_workspace_bytes(const vk_hierarchy* h, int max_restart, int max_rhs, size_t* bytes);
 
 /* Carves the caller's buffer d_workspace (>= the reported bytes, 256-byte
  * aligned) and enqueues the upload of every level on hip_stream (a
  * hipStream_t; NULL = default stream).  VK_ENOMEM if bytes is too small. */
-vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_workspace, size_t bytes, int max_restart,
+vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_workspace, size_t bytes, int max_restart, int max_rhs,
                             void* hip_stream);
 
 /* Matrix-full patch setup on the device: gathers every K_i = K[I_i, I_i]
@@ -189,6 +190,24 @@ vk_status vk_vcycle(vk_hierarchy* h, const double* d_r, double* d_e, int nu_pre,
 vk_status vk_solve(vk_hierarchy* h, const double* d_b, double* d_x, const vk_solve_opts* opts,
                    vk_solve_info* info);
 
+/* Many right-hand sides in lockstep.  Multivectors are row-major [N][nrhs]
+ * (the nrhs values of one DoF are contiguous), 1 <= nrhs <= max_rhs of the
+ * bind.  Each column runs the single-vector algorithm (its own Krylov basis,
+ * Hessenberg matrix and stopping test); the kernels process all columns at
+ * once and never mix them, so a column's result does not depend on the other
+ * columns.  With FP32 inverses the patch applies are FP32 matrix-core GEMMs
+ * (Delta_i = K_i^{-1} T[I_i, :]); FP64 inverses use vector FMAs and need
+ * patches of at most 128 DoFs. */
+vk_status vk_smooth_multi(vk_hierarchy* h, int level, const double* d_B, double* d_X, int nrhs, int nsweeps);
+vk_status vk_vcycle_multi(vk_hierarchy* h, const double* d_R, double* d_E, int nrhs, int nu_pre, int nu_post);
+/* info: nrhs entries (caller-owned), one per column.  VK_NOT_CONVERGED if any column missed rtol. */
+vk_status vk_solve_multi(vk_hierarchy* h, const double* d_B, double* d_X, int nrhs, const vk_solve_opts* opts,
+                         vk_solve_info* info);
+/* Finest-level right-hand side (consistent) of the smooth random forcing
+ * sum_{a,b=1..M} g[c][a-1][b-1] sin(a pi x) sin(b pi y) / (a^2 + b^2) with zero
+ * boundary velocity; coeffs: 2 * M * M values, host. */
+vk_status vk_rhs_random(const vk_hierarchy* h, int n_modes, const double* h_coeffs, double* h_b);
+
 /* Launch shapes of one level.  They change only speed, never results: the
  * CSR products and the patch apply sum in a canonical order that does not
  * depend on the lanes per row or the waves per patch. */
@@ -210,8 +229,9 @@ vk_status vk_tuning_get(const vk_hierarchy* h, int level, vk_tuning* t);
 /* Pins launch shapes (e.g. a cached autotuner result); VK_EINVAL on unsupported values. */
 vk_status vk_tuning_set(vk_hierarchy* h, int level, const vk_tuning* t);
 
-/* Timing of the finest-level patch-apply kernel (HIP events around every
- * launch while enabled): launches and total milliseconds since the last reset. */
+/* Timing of the finest-level patch apply (single vector: the two size-class
+ * dispatches; many right-hand sides: the patch GEMM), HIP events around every
+ * launch while enabled: launches and total milliseconds since the last reset. */
 vk_status vk_kernel_timing(vk_hierarchy* h, int enable, int reset, int64_t* launches, double* total_ms);
 
 #ifdef __cplusplus

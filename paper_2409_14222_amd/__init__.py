@@ -65,8 +65,8 @@ _SIGS = {
     "vk_last_error": ([], ctypes.c_char_p),
     "vk_hierarchy_create": ([_P(vk_problem), _P(vk_patch_opts), _P(_p)], _c_int),
     "vk_hierarchy_destroy": ([_p], _c_int),
-    "vk_hierarchy_workspace_bytes": ([_p, _c_int, _P(ctypes.c_size_t)], _c_int),
-    "vk_hierarchy_bind": ([_p, _p, ctypes.c_size_t, _c_int, _p], _c_int),
+    "vk_hierarchy_workspace_bytes": ([_p, _c_int, _c_int, _P(ctypes.c_size_t)], _c_int),
+    "vk_hierarchy_bind": ([_p, _p, ctypes.c_size_t, _c_int, _c_int, _p], _c_int),
     "vk_patches_setup": ([_p], _c_int),
     "vk_level_info_get": ([_p, _c_int, _P(vk_level_info)], _c_int),
     "vk_level_csr": ([_p, _c_int, _p, _p, _p], _c_int),
@@ -83,6 +83,10 @@ _SIGS = {
     "vk_coarse_solve": ([_p, _p, _p], _c_int),
     "vk_vcycle": ([_p, _p, _p, _c_int, _c_int], _c_int),
     "vk_solve": ([_p, _p, _p, _P(vk_solve_opts), _P(vk_solve_info)], _c_int),
+    "vk_smooth_multi": ([_p, _c_int, _p, _p, _c_int, _c_int], _c_int),
+    "vk_vcycle_multi": ([_p, _p, _p, _c_int, _c_int, _c_int], _c_int),
+    "vk_solve_multi": ([_p, _p, _p, _c_int, _P(vk_solve_opts), _p], _c_int),
+    "vk_rhs_random": ([_p, _c_int, _p, _p], _c_int),
     "vk_autotune": ([_p, _c_int], _c_int),
     "vk_tuning_get": ([_p, _c_int, _P(vk_tuning)], _c_int),
     "vk_tuning_set": ([_p, _c_int, _P(vk_tuning)], _c_int),
@@ -180,21 +184,22 @@ class Hierarchy:
         return b
 
     # ------------------------------------------------------------ device
-    def workspace_bytes(self, max_restart=30):
+    def workspace_bytes(self, max_restart=30, max_rhs=1):
         nb = ctypes.c_size_t()
-        check(lib.vk_hierarchy_workspace_bytes(self.h, max_restart, ctypes.byref(nb)))
+        check(lib.vk_hierarchy_workspace_bytes(self.h, max_restart, max_rhs, ctypes.byref(nb)))
         return nb.value
 
-    def bind(self, max_restart=30, device="cuda"):
+    def bind(self, max_restart=30, device="cuda", max_rhs=1):
         import torch
-        nbytes = self.workspace_bytes(max_restart)
+        nbytes = self.workspace_bytes(max_restart, max_rhs)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         base = self.ws.data_ptr()
         aligned = (base + 255) // 256 * 256
         self.stream = torch.cuda.current_stream(self.ws.device)
-        check(lib.vk_hierarchy_bind(self.h, aligned, nbytes + 256 - (aligned - base), max_restart,
+        check(lib.vk_hierarchy_bind(self.h, aligned, nbytes + 256 - (aligned - base), max_restart, max_rhs,
                                     self.stream.cuda_stream))
         self.max_restart = max_restart
+        self.max_rhs = max_rhs
         return self
 
     def setup(self):
@@ -235,6 +240,26 @@ class Hierarchy:
         if history:
             out["history"] = hist[: info.iterations + 1].copy()
         return out
+
+    def rhs_random(self, coeffs):
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+        b = np.empty(self.level_info(self.n_levels - 1).n_free)
+        check(lib.vk_rhs_random(self.h, coeffs.shape[-1], _ptr(coeffs), _ptr(b)))
+        return b
+
+    def smooth_multi(self, level, B, X, nrhs, nsweeps):
+        check(lib.vk_smooth_multi(self.h, level, _ptr(B), _ptr(X), nrhs, nsweeps))
+
+    def vcycle_multi(self, R, E, nrhs, nu_pre=2, nu_post=2):
+        check(lib.vk_vcycle_multi(self.h, _ptr(R), _ptr(E), nrhs, nu_pre, nu_post))
+
+    def solve_multi(self, B, X, nrhs, restart=30, maxit=100, rtol=1e-10, nu_pre=2, nu_post=2):
+        """B, X: row-major [N][nrhs] device tensors.  Returns one result dict per column."""
+        opts = vk_solve_opts(restart, maxit, rtol, nu_pre, nu_post, 0)
+        infos = (vk_solve_info * nrhs)()
+        status = check(lib.vk_solve_multi(self.h, _ptr(B), _ptr(X), nrhs, ctypes.byref(opts), infos))
+        return status, [{"iterations": i.iterations, "converged": bool(i.converged), "rel_residual": i.rel_residual}
+                        for i in infos]
 
     def autotune(self, reps=5):
         check(lib.vk_autotune(self.h, reps))

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "kernels_multi.hpp"
 #include "vk_internal.hpp"
 
 using namespace vk;
@@ -45,6 +46,7 @@ struct DevLevel {
   // waves per patch for the large (n > 64, first in `order`) and small patches
   int k_lanes = 32, p_lanes = 8, pt_lanes = 8, waves_large = 1, waves_small = 1, n_large = 0;
   int nt_large = 1, nt_small = 1;  // non-temporal (streaming) loads of the inverses
+  int max_n = 0;
   int4* meta = nullptr;            // per patch in processing order: {first slot, n, inverse offset}
 };
 
@@ -74,6 +76,8 @@ struct vk_hierarchy {
   bool bound = false, ready = false;
   hipStream_t stream = nullptr;
   int max_restart = 0;
+  int max_rhs = 1;
+  int *nvc = nullptr, *mask = nullptr;  // per-column iteration counts / active flags (multi-RHS)
   std::vector<DevLevel> D;
   double *V = nullptr, *Z = nullptr, *bb = nullptr, *r = nullptr, *partial = nullptr, *small = nullptr, *ydev = nullptr;
   int* singular = nullptr;
@@ -98,7 +102,7 @@ thread_local std::string g_err;
 
 // Lays out every device array of the hierarchy `Hs` in the carver; pointers go
 // to `h` (a scratch object when only sizing).
-void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver& cv, int max_restart) {
+void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver& cv, int max_restart, int R) {
   const int L = (int)Hs.size();
   h->D.assign(L, DevLevel());
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
@@ -112,9 +116,9 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.rowptr = cv.take<int>(lh.N + 1);
     d.col = cv.take<int>(lh.K.col.size());
     d.val = cv.take<double>(lh.K.val.size());
-    d.b = cv.take<double>(lh.N);
-    d.x = cv.take<double>(lh.N);
-    d.t = cv.take<double>(lh.N);
+    d.b = cv.take<double>((size_t)lh.N * R);
+    d.x = cv.take<double>((size_t)lh.N * R);
+    d.t = cv.take<double>((size_t)lh.N * R);
     if (l == 0) {
       d.M = cv.take<double>((size_t)lh.N * lh.N);
       continue;
@@ -131,6 +135,7 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.pt_lanes = csr_default_lanes(d.pt_mean);
     for (int i = 0; i + 1 < (int)lh.pptr.size(); ++i)
       if (lh.pptr[i + 1] - lh.pptr[i] > 64) d.n_large++;
+    d.max_n = lh.max_n;
     d.J = (int)lh.pptr.size() - 1;
     d.pptr = cv.take<int>(lh.pptr.size());
     d.pdofs = cv.take<int>(lh.pdofs.size());
@@ -142,17 +147,20 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.meta = cv.take<int4>(lh.order.size());
     d.scale = cv.take<double>(lh.scale.size());
     d.inv = cv.take<char>((size_t)lh.inv_elems * es);
-    d.delta = cv.take<char>(lh.pdofs.size() * es);
+    d.delta = cv.take<char>(lh.pdofs.size() * es * R);
   }
   const int N = Hs.back().N;
-  h->V = cv.take<double>((size_t)(max_restart + 1) * N);
-  h->Z = cv.take<double>((size_t)max_restart * N);
-  h->bb = cv.take<double>(N);
-  h->r = cv.take<double>(N);
-  h->partial = cv.take<double>((size_t)kReduceBlocks * 2 * (max_restart + 2) + 512);
-  h->small = cv.take<double>(4 * (max_restart + 2) + 16);
-  h->ydev = cv.take<double>(max_restart + 2);
+  h->V = cv.take<double>((size_t)(max_restart + 1) * N * R);
+  h->Z = cv.take<double>((size_t)max_restart * N * R);
+  h->bb = cv.take<double>((size_t)N * R);
+  h->r = cv.take<double>((size_t)N * R);
+  h->partial = cv.take<double>(std::max<size_t>((size_t)kReduceBlocks * 2 * (max_restart + 2) + 512,
+                                                (size_t)(max_restart + 2) * 64 * 64 + 64 * 64 + 64));
+  h->small = cv.take<double>((size_t)4 * (max_restart + 2) * R + 16);
+  h->ydev = cv.take<double>((size_t)(max_restart + 2) * R);
   h->singular = cv.take<int>(64);
+  h->nvc = cv.take<int>(64);
+  h->mask = cv.take<int>(64);
 }
 
 template <typename T>
@@ -466,6 +474,215 @@ void autotune(vk_hierarchy* h, int reps) {
   check_launch();
 }
 
+// ============================================================================ many right-hand sides
+// The same smoother, V-cycle and FGMRES as above on multivectors [N][R]; each
+// column follows the single-vector algorithm, columns never interact.
+void smooth_multi(vk_hierarchy* h, int l, int R, const double* B, double* X, int nsweeps, bool x_zero) {
+  DevLevel& d = h->D[l];
+  const hipStream_t s = h->stream;
+  for (int it = 0; it < nsweeps; ++it) {
+    const bool first_zero = x_zero && it == 0;
+    const double* T = B;
+    if (!first_zero) {
+      launch_spmm(1, d.N, R, d.rowptr, d.col, d.val, X, B, d.t, s);
+      T = d.t;
+    }
+    const bool timed = h->timing && !h->capturing && l == h->L() - 1;
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (timed) {
+      if (h->ev_free.empty()) {
+        hipEvent_t a, b;
+        HIPCHECK(hipEventCreate(&a));
+        HIPCHECK(hipEventCreate(&b));
+        h->ev_free.push_back({a, b});
+      }
+      ev = h->ev_free.back();
+      h->ev_free.pop_back();
+      HIPCHECK(hipEventRecord(ev.first, s));
+    }
+    launch_patch_gemm(h->fp32(), d.n_large, d.max_n, d.meta, d.pdofs, d.inv, T, R, d.delta, s);
+    launch_patch_gemm(h->fp32(), d.J - d.n_large, std::min(d.max_n, 64), d.meta + d.n_large, d.pdofs, d.inv, T, R,
+                      d.delta, s);
+    if (timed) {
+      HIPCHECK(hipEventRecord(ev.second, s));
+      h->ev_pending.push_back(ev);
+    }
+    launch_scatter_multi(h->fp32(), first_zero, d.N, R, d.dptr, d.dslot, d.delta, d.scale, X, s);
+    check_launch();
+  }
+  if (x_zero && nsweeps == 0) launch_fill(d.N * R, 0.0, X, s);
+}
+
+void vcycle_multi(vk_hierarchy* h, int l, int R, const double* Rv, double* E, int nu_pre, int nu_post) {
+  DevLevel& d = h->D[l];
+  const hipStream_t s = h->stream;
+  if (l == 0) {
+    launch_dense_gemm(d.N, R, d.M, Rv, E, s);
+    check_launch();
+    return;
+  }
+  DevLevel& c = h->D[l - 1];
+  smooth_multi(h, l, R, Rv, E, nu_pre, true);
+  launch_spmm(1, d.N, R, d.rowptr, d.col, d.val, E, Rv, d.t, s);
+  launch_spmm(0, c.N, R, d.ptrow, d.ptcol, d.ptval, d.t, nullptr, c.b, s);
+  check_launch();
+  vcycle_multi(h, l - 1, R, c.b, c.x, nu_pre, nu_post);
+  launch_spmm(2, d.N, R, d.prow, d.pcol, d.pval, c.x, nullptr, E, s);
+  check_launch();
+  smooth_multi(h, l, R, Rv, E, nu_post, false);
+}
+
+void require_multi(const vk_hierarchy* h, int R) {
+  require(R >= 1 && R <= h->max_rhs, VK_EINVAL, "nrhs exceeds the max_rhs the workspace was bound for");
+  if (!h->fp32())
+    for (int l = 1; l < h->L(); ++l)
+      require(h->H[l].max_n <= 128, VK_EINVAL, "FP64 inverses with many right-hand sides need patches <= 128 DoFs");
+}
+
+// sqrt of the column dot products <A_c, B_c> on the host
+std::vector<double> col_norms(vk_hierarchy* h, int n, int R, const double* A, const double* B) {
+  launch_dots_cols(n, R, 1, A, 0, B, h->partial, h->small, h->stream);
+  check_launch();
+  std::vector<double> v(R);
+  HIPCHECK(hipMemcpyAsync(v.data(), h->small, R * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  for (double& x : v) x = std::sqrt(x);
+  return v;
+}
+
+vk_status fgmres_multi(vk_hierarchy* h, int R, const double* B, double* X, const vk_solve_opts& o,
+                       vk_solve_info* info) {
+  const int N = h->H.back().N;
+  const int Lf = h->L() - 1;
+  const int nvel = h->H.back().nvel;
+  const double zv = 1.0 / std::sqrt((double)h->H.back().npres);
+  const hipStream_t s = h->stream;
+  DevLevel& F = h->D[Lf];
+  const int m = o.restart;
+  std::vector<int> ones(R, 1);
+  HIPCHECK(hipMemcpyAsync(h->mask, ones.data(), R * sizeof(int), hipMemcpyHostToDevice, s));
+  launch_copy(N * R, B, h->bb, s);
+  launch_project_cols(N, nvel, R, zv, h->mask, h->bb, h->partial, s);
+  check_launch();
+  const std::vector<double> bnorm = col_norms(h, N, R, h->bb, h->bb);
+  for (double v : bnorm) require(std::isfinite(v), VK_ENAN, "right-hand side is not finite");
+  launch_fill(N * R, 0.0, X, s);
+  launch_copy(N * R, h->bb, h->r, s);
+  std::vector<int> conv(R, 0), its_c(R, 0);
+  for (int c = 0; c < R; ++c) {
+    conv[c] = bnorm[c] == 0.0;
+    if (info && info[c].h_history) info[c].h_history[0] = bnorm[c];
+  }
+  std::vector<double> beta(R, 0.0);
+  std::vector<double> Hs((size_t)R * (m + 1) * m), cs((size_t)R * m), sn((size_t)R * m), g((size_t)R * (m + 1));
+  std::vector<double> hh((size_t)3 * (m + 2) * R), ybuf((size_t)(m + 2) * R), nn(R);
+  std::vector<int> nk(R), running(R), mask(R);
+  while (true) {
+    beta = col_norms(h, N, R, h->r, h->r);
+    // a column takes part in the next cycle if it has not converged and has
+    // iterations left (its own count, so a batch never changes its course)
+    bool any = false;
+    std::vector<int> go(R, 0);
+    for (int c = 0; c < R; ++c) {
+      require(std::isfinite(beta[c]), VK_ENAN, "residual is not finite");
+      if (!conv[c] && beta[c] <= o.rtol * bnorm[c]) conv[c] = 1;
+      go[c] = !conv[c] && its_c[c] < o.maxit;
+      any = any || go[c];
+    }
+    if (!any) break;
+    for (int c = 0; c < R; ++c) nn[c] = go[c] ? beta[c] * beta[c] : 0.0;
+    HIPCHECK(hipMemcpyAsync(h->small, nn.data(), R * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_div_sqrt_cols(N, R, h->r, h->small, h->V, s);
+    std::fill(Hs.begin(), Hs.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    for (int c = 0; c < R; ++c) {
+      g[(size_t)c * (m + 1)] = beta[c];
+      running[c] = go[c];
+      nk[c] = 0;
+    }
+    for (int j = 0; j < m; ++j) {
+      const size_t NR = (size_t)N * R;
+      double* vj = h->V + j * NR;
+      double* zj = h->Z + j * NR;
+      double* w = h->V + (j + 1) * NR;
+      vcycle_multi(h, Lf, R, vj, zj, o.nu_pre, o.nu_post);
+      launch_spmm(0, N, R, F.rowptr, F.col, F.val, zj, nullptr, w, s);
+      launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h->small, s);
+      launch_axpy_cols(N, R, j + 1, nullptr, -1.0, h->V, NR, h->small, w, s);
+      launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h->small + (size_t)(m + 2) * R, s);
+      launch_axpy_cols(N, R, j + 1, nullptr, -1.0, h->V, NR, h->small + (size_t)(m + 2) * R, w, s);
+      launch_dots_cols(N, R, 1, w, 0, w, h->partial, h->small + (size_t)2 * (m + 2) * R, s);
+      launch_div_sqrt_cols(N, R, w, h->small + (size_t)2 * (m + 2) * R, w, s);
+      check_launch();
+      HIPCHECK(hipMemcpyAsync(hh.data(), h->small, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      bool still = false;
+      for (int c = 0; c < R; ++c) {
+        if (!running[c]) continue;
+        double* Hc = &Hs[(size_t)c * (m + 1) * m];
+        double* gc = &g[(size_t)c * (m + 1)];
+        double* csc = &cs[(size_t)c * m];
+        double* snc = &sn[(size_t)c * m];
+        const double hn = std::sqrt(hh[(size_t)2 * (m + 2) * R + c]);
+        require(std::isfinite(hn), VK_ENAN, "Arnoldi breakdown to a non-finite value");
+        for (int i = 0; i <= j; ++i) Hc[(size_t)i * m + j] = hh[(size_t)i * R + c] + hh[(size_t)(m + 2) * R + (size_t)i * R + c];
+        Hc[(size_t)(j + 1) * m + j] = hn;
+        for (int i = 0; i < j; ++i) {
+          const double a = Hc[(size_t)i * m + j], b2 = Hc[(size_t)(i + 1) * m + j];
+          Hc[(size_t)i * m + j] = csc[i] * a + snc[i] * b2;
+          Hc[(size_t)(i + 1) * m + j] = -snc[i] * a + csc[i] * b2;
+        }
+        const double a = Hc[(size_t)j * m + j], b2 = Hc[(size_t)(j + 1) * m + j];
+        const double den = std::hypot(a, b2);
+        csc[j] = a / den;
+        snc[j] = b2 / den;
+        Hc[(size_t)j * m + j] = den;
+        Hc[(size_t)(j + 1) * m + j] = 0.0;
+        gc[j + 1] = -snc[j] * gc[j];
+        gc[j] = csc[j] * gc[j];
+        its_c[c] += 1;
+        nk[c] = j + 1;
+        if (info && info[c].h_history) info[c].h_history[its_c[c]] = std::fabs(gc[j + 1]);
+        if (std::fabs(gc[j + 1]) <= o.rtol * bnorm[c] || hn == 0.0 || its_c[c] >= o.maxit) running[c] = 0;
+        still = still || running[c];
+      }
+      if (!still) break;
+    }
+    std::fill(ybuf.begin(), ybuf.end(), 0.0);
+    for (int c = 0; c < R; ++c) {
+      mask[c] = go[c];
+      if (!go[c]) { nk[c] = 0; continue; }
+      const double* Hc = &Hs[(size_t)c * (m + 1) * m];
+      const double* gc = &g[(size_t)c * (m + 1)];
+      std::vector<double> y(nk[c]);
+      for (int i = nk[c] - 1; i >= 0; --i) {
+        double acc = gc[i];
+        for (int q = i + 1; q < nk[c]; ++q) acc -= Hc[(size_t)i * m + q] * y[q];
+        y[i] = acc / Hc[(size_t)i * m + i];
+      }
+      for (int i = 0; i < nk[c]; ++i) ybuf[(size_t)i * R + c] = y[i];
+    }
+    HIPCHECK(hipMemcpyAsync(h->ydev, ybuf.data(), (size_t)(m + 2) * R * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(h->nvc, nk.data(), R * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(h->mask, mask.data(), R * sizeof(int), hipMemcpyHostToDevice, s));
+    launch_axpy_cols(N, R, m, h->nvc, 1.0, h->Z, (int64_t)N * R, h->ydev, X, s);
+    launch_project_cols(N, nvel, R, zv, h->mask, X, h->partial, s);
+    launch_spmm(1, N, R, F.rowptr, F.col, F.val, X, h->bb, h->r, s);
+    check_launch();
+  }
+  if (h->timing) collect_timing(h);
+  bool all = true;
+  for (int c = 0; c < R; ++c) {
+    all = all && conv[c];
+    if (info) {
+      info[c].iterations = its_c[c];
+      info[c].converged = conv[c];
+      info[c].rel_residual = bnorm[c] > 0 ? beta[c] / bnorm[c] : 0.0;
+    }
+  }
+  return all ? VK_OK : VK_NOT_CONVERGED;
+}
+
 template <typename F>
 vk_status guarded(F&& f) {
   try {
@@ -557,34 +774,38 @@ vk_status vk_hierarchy_destroy(vk_hierarchy* h) {
   });
 }
 
-vk_status vk_hierarchy_workspace_bytes(const vk_hierarchy* h, int max_restart, size_t* bytes) {
+vk_status vk_hierarchy_workspace_bytes(const vk_hierarchy* h, int max_restart, int max_rhs, size_t* bytes) {
   return guarded([&]() -> vk_status {
     require(h && bytes, VK_EINVAL, "null argument");
     require(max_restart >= 1 && max_restart <= 200, VK_EINVAL, "max_restart out of range");
+    require(max_rhs >= 1 && max_rhs <= 64, VK_EINVAL, "max_rhs must be in 1..64");
     vk_hierarchy tmp;  // sizing pass: pointers land in a scratch object
     Carver cv(nullptr);
-    carve(h->H, h->fp32(), &tmp, cv, max_restart);
+    carve(h->H, h->fp32(), &tmp, cv, max_restart, max_rhs);
     *bytes = cv.off + 256;
     return VK_OK;
   });
 }
 
-vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_restart, void* stream) {
+vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_restart, int max_rhs,
+                            void* stream) {
   return guarded([&]() -> vk_status {
     require(h && d_ws, VK_EINVAL, "null argument");
     require(((uintptr_t)d_ws & 255) == 0, VK_EINVAL, "workspace must be 256-byte aligned");
     require(max_restart >= 1 && max_restart <= 200, VK_EINVAL, "max_restart out of range");
+    require(max_rhs >= 1 && max_rhs <= 64, VK_EINVAL, "max_rhs must be in 1..64");
     Carver dry(nullptr);
     {
       vk_hierarchy tmp;
-      carve(h->H, h->fp32(), &tmp, dry, max_restart);
+      carve(h->H, h->fp32(), &tmp, dry, max_restart, max_rhs);
     }
     require(bytes >= dry.off, VK_ENOMEM, "workspace too small");
     h->stream = (hipStream_t)stream;
     h->max_restart = max_restart;
+    h->max_rhs = max_rhs;
     drop_graphs(h);
     Carver cv(d_ws);
-    carve(h->H, h->fp32(), h, cv, max_restart);
+    carve(h->H, h->fp32(), h, cv, max_restart, max_rhs);
     h->meta_host.clear();
     const hipStream_t s = h->stream;
     for (int l = 0; l < h->L(); ++l) {
@@ -853,6 +1074,64 @@ vk_status vk_solve(vk_hierarchy* h, const double* b, double* x, const vk_solve_o
     require(opts->maxit >= 0 && opts->rtol >= 0 && opts->nu_pre >= 0 && opts->nu_post >= 0, VK_EINVAL,
             "bad solve options");
     return fgmres(h, b, x, *opts, info);
+  });
+}
+
+
+vk_status vk_smooth_multi(vk_hierarchy* h, int level, const double* B, double* X, int nrhs, int nsweeps) {
+  return guarded([&]() -> vk_status {
+    require_ready(h);
+    require(B && X && nsweeps >= 0, VK_EINVAL, "bad argument");
+    require_level(h, level, 1);
+    require_multi(h, nrhs);
+    smooth_multi(h, level, nrhs, B, X, nsweeps, false);
+    return VK_OK;
+  });
+}
+
+vk_status vk_vcycle_multi(vk_hierarchy* h, const double* Rv, double* E, int nrhs, int nu_pre, int nu_post) {
+  return guarded([&]() -> vk_status {
+    require_ready(h);
+    require(Rv && E && nu_pre >= 0 && nu_post >= 0, VK_EINVAL, "bad argument");
+    require_multi(h, nrhs);
+    vcycle_multi(h, h->L() - 1, nrhs, Rv, E, nu_pre, nu_post);
+    return VK_OK;
+  });
+}
+
+vk_status vk_solve_multi(vk_hierarchy* h, const double* B, double* X, int nrhs, const vk_solve_opts* opts,
+                         vk_solve_info* info) {
+  return guarded([&]() -> vk_status {
+    require_ready(h);
+    require(B && X && opts, VK_EINVAL, "null argument");
+    require_multi(h, nrhs);
+    require(opts->restart >= 1 && opts->restart <= h->max_restart, VK_EINVAL, "restart exceeds the bound basis");
+    require(opts->maxit >= 0 && opts->rtol >= 0 && opts->nu_pre >= 0 && opts->nu_post >= 0, VK_EINVAL,
+            "bad solve options");
+    require(!opts->use_graphs, VK_EINVAL, "graph replay is implemented for the single-vector solve");
+    return fgmres_multi(h, nrhs, B, X, *opts, info);
+  });
+}
+
+vk_status vk_rhs_random(const vk_hierarchy* h, int n_modes, const double* coeffs, double* hb) {
+  return guarded([&]() -> vk_status {
+    require(h && coeffs && hb, VK_EINVAL, "null argument");
+    require(h->H.back().dim == 2, VK_EINVAL, "random forcing is defined on the unit square");
+    require(n_modes >= 1 && n_modes <= 64, VK_EINVAL, "n_modes out of range");
+    Problem pr = h->pr;
+    pr.p.forcing = VK_F_RANDOM;
+    pr.p.n_modes = n_modes;
+    pr.coeffs.assign(coeffs, coeffs + 2 * n_modes * n_modes);
+    LevelHost L;
+    L.dim = h->H.back().dim;
+    L.k = h->H.back().k;
+    L.n = h->H.back().n;
+    build_level(L, pr, true);
+    const double zv = 1.0 / std::sqrt((double)L.npres);
+    double zb = 0.0;
+    for (int i = L.nvel; i < L.N; ++i) zb += L.b[i] * zv;
+    for (int i = 0; i < L.N; ++i) hb[i] = i < L.nvel ? L.b[i] : L.b[i] - zb * zv;
+    return VK_OK;
   });
 }
 

@@ -1,0 +1,346 @@
+// gfx950 kernels for many right-hand sides solved in lockstep.
+//
+// Multivectors are row-major [N][R]: the R values of one DoF are contiguous,
+// so a wave reading one DoF for all right-hand sides is one coalesced access.
+// No kernel mixes columns: column c of every output depends only on column c
+// of the inputs, so a right-hand side gets the same bits whatever else is in
+// the batch.  Reductions have a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels_multi.hpp"
+
+namespace vk {
+
+static inline int pow2_at_least(int r) {
+  int p = 1;
+  while (p < r) p <<= 1;
+  return p;
+}
+
+// ============================================================================
+// SpMM: Y = A X (mode 0), Y = B - A X (mode 1), Y += A X (mode 2).  One lane
+// per right-hand side, 256 / Rp rows per block; each lane sums its row in
+// ascending entry order.
+// ============================================================================
+template <int MODE>
+__global__ void __launch_bounds__(256) spmm_kernel(int nrows, int R, int Rp, const int* __restrict__ rowptr,
+                                                   const int* __restrict__ col, const double* __restrict__ val,
+                                                   const double* __restrict__ X, const double* __restrict__ B,
+                                                   double* __restrict__ Y) {
+  const int rpb = 256 / Rp;
+  const int row = blockIdx.x * rpb + threadIdx.x / Rp;
+  const int c = threadIdx.x % Rp;
+  if (row >= nrows || c >= R) return;
+  double acc = 0.0;
+  for (int q = rowptr[row]; q < rowptr[row + 1]; ++q) acc += val[q] * X[(int64_t)col[q] * R + c];
+  const int64_t o = (int64_t)row * R + c;
+  if (MODE == 0) Y[o] = acc;
+  else if (MODE == 1) Y[o] = B[o] - acc;
+  else Y[o] += acc;
+}
+
+void launch_spmm(int mode, int nrows, int R, const int* rp, const int* col, const double* val, const double* X,
+                 const double* B, double* Y, hipStream_t s) {
+  const int Rp = pow2_at_least(R);
+  const int rpb = 256 / Rp;
+  const int grid = (nrows + rpb - 1) / rpb;
+  if (grid == 0) return;
+  if (mode == 0) spmm_kernel<0><<<grid, 256, 0, s>>>(nrows, R, Rp, rp, col, val, X, B, Y);
+  else if (mode == 1) spmm_kernel<1><<<grid, 256, 0, s>>>(nrows, R, Rp, rp, col, val, X, B, Y);
+  else spmm_kernel<2><<<grid, 256, 0, s>>>(nrows, R, Rp, rp, col, val, X, B, Y);
+}
+
+// ============================================================================
+// Patch GEMM on the matrix cores: Delta_i = K_i^{-1} T[I_i, 0:R] with FP32
+// inverses, FP32 inputs and FP32 accumulation (v_mfma_f32_16x16x4_f32).  One
+// 256-thread workgroup per patch.  The residual block T[I_i, :] is gathered
+// once into LDS as FP32 (zero-padded to 64 columns and to a multiple of 4
+// rows); the inverse streams from HBM as the A operand.  Wave w computes the
+// 16-row tiles w, w + 4, ..., each against the four 16-column tiles.
+// Operand layout of the instruction (lane l): A[l % 16][l / 16],
+// B[l / 16][l % 16], result rows 4 (l / 16) + i, column l % 16.
+// ============================================================================
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+// NW waves per patch; wave w computes the 16-row tiles w, w + NW, ...  The
+// residual block lives in dynamic LDS sized by the launch's largest patch.
+// The A operand is prefetched 8 MFMA steps (32 columns of K_i^{-1}) ahead.
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) patch_gemm_mfma_kernel(const int4* __restrict__ meta,
+                                                                  const int* __restrict__ pdofs,
+                                                                  const float* __restrict__ inv,
+                                                                  const double* __restrict__ T, int R, int nmax,
+                                                                  float* __restrict__ delta) {
+  extern __shared__ float Bs[];  // [nk][64]
+  const int4 m4 = meta[blockIdx.x];
+  const int base = m4.x, n = m4.y;
+  const int64_t off = (int64_t)(uint32_t)m4.z | ((int64_t)m4.w << 32);
+  if (n > nmax || n <= 0) return;  // the launch sizes LDS for nmax >= every n; never taken
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int ld = (n + 3) / 4 * 4;  // FP32 inverses: leading dimension rounded to 4
+  const int nk = ld;               // depth padded to the MFMA depth 4
+  for (int e = tid; e < nk * 64; e += 64 * NW) {
+    const int j = e >> 6, c = e & 63;
+    Bs[e] = (j < n && c < R) ? (float)T[(int64_t)pdofs[base + j] * R + c] : 0.f;
+  }
+  __syncthreads();
+  const float* A = inv + off;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int ntiles = (n + 15) / 16;
+  for (int rt = wave; rt < ntiles; rt += NW) {
+    floatx4_t acc[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
+    const int row = rt * 16 + lr;
+    const bool rok = row < ld;
+    for (int k0 = 0; k0 < nk; k0 += 32) {
+      float a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + 4 * u + lk;
+        a[u] = (rok && k < n) ? A[(int64_t)k * ld + row] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + 4 * u + lk;
+        if (k0 + 4 * u < nk) {
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) {
+            const float b = Bs[k * 64 + ct * 16 + lr];
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b, acc[ct], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int c = ct * 16 + lr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = rt * 16 + 4 * lk + i;
+        if (r < n && c < R) delta[(int64_t)(base + r) * R + c] = acc[ct][i];
+      }
+    }
+  }
+}
+
+// FP64 inverses: vector FMAs.  Thread (r, g) of a 64 x 4 grid computes rows
+// r, r + 64, ... for the 16 columns 16 g .. 16 g + 15; the columns of the
+// inverse stream from HBM, the residual block sits in LDS.
+__global__ void __launch_bounds__(256) patch_gemm_f64_kernel(const int4* __restrict__ meta,
+                                                             const int* __restrict__ pdofs,
+                                                             const double* __restrict__ inv,
+                                                             const double* __restrict__ T, int R,
+                                                             double* __restrict__ delta) {
+  __shared__ double Bs[128 * 64];
+  const int4 m4 = meta[blockIdx.x];
+  const int base = m4.x, n = m4.y;
+  const int64_t off = (int64_t)(uint32_t)m4.z | ((int64_t)m4.w << 32);
+  if (n > 128 || n <= 0) return;  // the host limits FP64 multi-RHS patches to 128 DoFs; never taken
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * 64; e += 256) {
+    const int j = e >> 6, c = e & 63;
+    Bs[e] = c < R ? T[(int64_t)pdofs[base + j] * R + c] : 0.0;
+  }
+  __syncthreads();
+  const int ld = (n + 1) / 2 * 2;
+  const double* A = inv + off;
+  const int r0 = tid & 63, g = tid >> 6;
+  for (int r = r0; r < n; r += 64) {
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double a = A[(int64_t)j * ld + r];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u] += a * Bs[j * 64 + 16 * g + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int c = 16 * g + u;
+      if (c < R) delta[(int64_t)(base + r) * R + c] = acc[u];
+    }
+  }
+}
+
+void launch_patch_gemm(bool fp32, int count, int nmax, const int4* meta, const int* pdofs, const void* inv,
+                       const double* T, int R, void* delta, hipStream_t s) {
+  if (count <= 0) return;
+  if (fp32) {
+    const int nk = (nmax + 3) / 4 * 4;
+    const size_t lds = (size_t)nk * 64 * sizeof(float);
+    if (nmax > 64)
+      patch_gemm_mfma_kernel<4><<<count, 256, lds, s>>>(meta, pdofs, (const float*)inv, T, R, nmax, (float*)delta);
+    else
+      patch_gemm_mfma_kernel<1><<<count, 64, lds, s>>>(meta, pdofs, (const float*)inv, T, R, nmax, (float*)delta);
+  } else {
+    patch_gemm_f64_kernel<<<count, 256, 0, s>>>(meta, pdofs, (const double*)inv, T, R, (double*)delta);
+  }
+}
+
+// ============================================================================
+// Column-wise scatter: X[d][c] (+)= scale[d] * sum over the slots of d (ascending patch id).
+// ============================================================================
+template <typename TD, bool SET>
+__global__ void __launch_bounds__(256) scatter_multi_kernel(int N, int R, int Rp, const int* __restrict__ dptr,
+                                                            const int* __restrict__ dslot,
+                                                            const TD* __restrict__ delta,
+                                                            const double* __restrict__ scale, double* __restrict__ X) {
+  const int rpb = 256 / Rp;
+  const int d = blockIdx.x * rpb + threadIdx.x / Rp;
+  const int c = threadIdx.x % Rp;
+  if (d >= N || c >= R) return;
+  double s = 0.0;
+  for (int q = dptr[d]; q < dptr[d + 1]; ++q) s += (double)delta[(int64_t)dslot[q] * R + c];
+  const int64_t o = (int64_t)d * R + c;
+  if (SET) X[o] = scale[d] * s;
+  else X[o] += scale[d] * s;
+}
+
+void launch_scatter_multi(bool fp32, bool set, int N, int R, const int* dptr, const int* dslot, const void* delta,
+                          const double* scale, double* X, hipStream_t s) {
+  const int Rp = pow2_at_least(R);
+  const int rpb = 256 / Rp;
+  const int grid = (N + rpb - 1) / rpb;
+  if (fp32) {
+    if (set) scatter_multi_kernel<float, true><<<grid, 256, 0, s>>>(N, R, Rp, dptr, dslot, (const float*)delta, scale, X);
+    else scatter_multi_kernel<float, false><<<grid, 256, 0, s>>>(N, R, Rp, dptr, dslot, (const float*)delta, scale, X);
+  } else {
+    if (set) scatter_multi_kernel<double, true><<<grid, 256, 0, s>>>(N, R, Rp, dptr, dslot, (const double*)delta, scale, X);
+    else scatter_multi_kernel<double, false><<<grid, 256, 0, s>>>(N, R, Rp, dptr, dslot, (const double*)delta, scale, X);
+  }
+}
+
+// ============================================================================
+// Coarsest level: E = M Rv, M dense row-major N0 x N0; one block per row,
+// one lane per right-hand side, ascending j.
+// ============================================================================
+__global__ void __launch_bounds__(64) dense_gemm_kernel(int N, int R, const double* __restrict__ M,
+                                                        const double* __restrict__ Rv, double* __restrict__ E) {
+  const int row = blockIdx.x, c = threadIdx.x;
+  if (c >= R) return;
+  const double* m = M + (int64_t)row * N;
+  double acc = 0.0;
+  for (int j = 0; j < N; ++j) acc += m[j] * Rv[(int64_t)j * R + c];
+  E[(int64_t)row * R + c] = acc;
+}
+
+void launch_dense_gemm(int N, int R, const double* M, const double* Rv, double* E, hipStream_t s) {
+  dense_gemm_kernel<<<N, 64, 0, s>>>(N, R, M, Rv, E);
+}
+
+// ============================================================================
+// Column-wise Krylov helpers.  Reductions: each block sums a contiguous row
+// chunk for every column (4 row lanes x 64 columns, fixed tree), then one
+// final pass sums the block partials in block order.
+// ============================================================================
+constexpr int kColBlocks = 64;
+
+__global__ void __launch_bounds__(256) dots_partial_kernel(int n, int R, const double* __restrict__ V, int64_t ldv,
+                                                           const double* __restrict__ W, double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const int v = blockIdx.y, c = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const double* x = V + (int64_t)v * ldv;
+  const int chunk = (n + kColBlocks - 1) / kColBlocks;
+  const int i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  double acc = 0.0;
+  if (c < R)
+    for (int i = i0 + rl; i < i1; i += 4) acc += x[(int64_t)i * R + c] * W[(int64_t)i * R + c];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  if (rl == 0) {
+    const double s = (sh[c] + sh[64 + c]) + (sh[128 + c] + sh[192 + c]);
+    partial[((int64_t)v * kColBlocks + blockIdx.x) * 64 + c] = s;
+  }
+}
+
+__global__ void __launch_bounds__(64) dots_final_kernel(int R, const double* __restrict__ partial,
+                                                        double* __restrict__ out) {
+  const int v = blockIdx.x, c = threadIdx.x;
+  if (c >= R) return;
+  double s = 0.0;
+  for (int b = 0; b < kColBlocks; ++b) s += partial[((int64_t)v * kColBlocks + b) * 64 + c];
+  out[(int64_t)v * R + c] = s;
+}
+
+void launch_dots_cols(int n, int R, int nv, const double* V, int64_t ldv, const double* W, double* partial,
+                      double* out, hipStream_t s) {
+  dots_partial_kernel<<<dim3(kColBlocks, nv), 256, 0, s>>>(n, R, V, ldv, W, partial);
+  dots_final_kernel<<<nv, 64, 0, s>>>(R, partial, out);
+}
+
+// W[i][c] += sign * sum_{v < nvc[c]} V_v[i][c] h[v][c]  (nvc == nullptr: nv for every column)
+__global__ void __launch_bounds__(256) axpy_cols_kernel(int n, int R, int Rp, int nv, const int* __restrict__ nvc,
+                                                        double sign, const double* __restrict__ V, int64_t ldv,
+                                                        const double* __restrict__ h, double* __restrict__ W) {
+  const int rpb = 256 / Rp;
+  const int i = blockIdx.x * rpb + threadIdx.x / Rp;
+  const int c = threadIdx.x % Rp;
+  if (i >= n || c >= R) return;
+  const int m = nvc ? nvc[c] : nv;
+  double s = 0.0;
+  for (int v = 0; v < m; ++v) s += V[(int64_t)v * ldv + (int64_t)i * R + c] * h[(int64_t)v * R + c];
+  W[(int64_t)i * R + c] += sign * s;
+}
+
+void launch_axpy_cols(int n, int R, int nv, const int* nvc, double sign, const double* V, int64_t ldv,
+                      const double* h, double* W, hipStream_t s) {
+  const int Rp = pow2_at_least(R);
+  const int rpb = 256 / Rp;
+  axpy_cols_kernel<<<(n + rpb - 1) / rpb, 256, 0, s>>>(n, R, Rp, nv, nvc, sign, V, ldv, h, W);
+}
+
+// Y[i][c] = X[i][c] / sqrt(nn[c]) (nn[c] <= 0 gives 0: a finished or empty column)
+__global__ void __launch_bounds__(256) div_sqrt_cols_kernel(int64_t total, int R, const double* X,
+                                                            const double* __restrict__ nn, double* Y) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const double q = nn[e % R];
+  Y[e] = q > 0.0 ? X[e] / sqrt(q) : 0.0;
+}
+
+void launch_div_sqrt_cols(int n, int R, const double* X, const double* nn, double* Y, hipStream_t s) {
+  const int64_t total = (int64_t)n * R;
+  div_sqrt_cols_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(total, R, X, nn, Y);
+}
+
+// per-column removal of the constant pressure, for columns with mask[c] != 0
+__global__ void __launch_bounds__(256) project_cols_partial_kernel(int n, int p0, int R, double zv,
+                                                                   const double* __restrict__ X,
+                                                                   double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const int c = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int np = n - p0;
+  const int chunk = (np + kColBlocks - 1) / kColBlocks;
+  const int i0 = p0 + blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  double acc = 0.0;
+  if (c < R)
+    for (int i = i0 + rl; i < i1; i += 4) acc += X[(int64_t)i * R + c] * zv;
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  if (rl == 0) partial[(int64_t)blockIdx.x * 64 + c] = (sh[c] + sh[64 + c]) + (sh[128 + c] + sh[192 + c]);
+}
+
+__global__ void __launch_bounds__(256) project_cols_apply_kernel(int n, int p0, int R, int Rp, double zv,
+                                                                 const double* __restrict__ zx,
+                                                                 const int* __restrict__ mask, double* __restrict__ X) {
+  const int rpb = 256 / Rp;
+  const int i = p0 + blockIdx.x * rpb + threadIdx.x / Rp;
+  const int c = threadIdx.x % Rp;
+  if (i >= n || c >= R || !mask[c]) return;
+  X[(int64_t)i * R + c] -= zx[c] * zv;
+}
+
+void launch_project_cols(int n, int p0, int R, double zv, const int* mask, double* X, double* partial,
+                         hipStream_t s) {
+  project_cols_partial_kernel<<<kColBlocks, 256, 0, s>>>(n, p0, R, zv, X, partial);
+  dots_final_kernel<<<1, 64, 0, s>>>(R, partial, partial + kColBlocks * 64);
+  const int Rp = pow2_at_least(R);
+  const int rpb = 256 / Rp;
+  project_cols_apply_kernel<<<(n - p0 + rpb - 1) / rpb, 256, 0, s>>>(n, p0, R, Rp, zv, partial + kColBlocks * 64,
+                                                                      mask, X);
+}
+
+}  // namespace vk

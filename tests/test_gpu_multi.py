@@ -1,0 +1,163 @@
+"""GPU parity of the many-right-hand-side path (lockstep FGMRES, SpMM, patch GEMMs).
+
+Every column is compared with the oracle run on that column alone.  The FP32
+matrix-core patch GEMM is checked against an elementwise bound computed by
+the oracle from FP32 rounding of the inverse, the inputs and the
+accumulation.  Columns must not interact: a right-hand side solved alone, or
+at another position of the batch, gives the same bits.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(float).eps
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def hier():
+    import paper_2409_14222_amd as vk
+    from oracle import fields, solve
+    print("[gpu-multi] building P2-P1 and P4-P3 16x16 hierarchies (FP64 and FP32 inverses)", flush=True)
+    out = {}
+    for k in (2, 4):
+        OH, OV = solve.setup(2, k, 4, 3, 1.0, fields.baseline_mms)
+        H64 = vk.Hierarchy(k, 4, 3).bind(max_rhs=16).setup()
+        H32 = vk.Hierarchy(k, 4, 3, store=vk.VK_STORE_FP32).bind(max_rhs=16).setup()
+        out[k] = (H64, H32, OH, OV)
+    return out
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_smooth_multi_fp64(hier, k):
+    H64, _, OH, OV = hier[k]
+    R = 7
+    for l in (1, 2):
+        L, S = OH.levels[l], OV.smoothers[l]
+        B = synth.vector(L.N * R, 800 + l).reshape(L.N, R)
+        X0 = synth.vector(L.N * R, 900 + l).reshape(L.N, R)
+        X = _dev(X0)
+        H64.smooth_multi(l, _dev(B), X, R, 1)
+        got = _host(X)
+        cb = max(len(I) * np.linalg.cond(S.patch_matrix(i)) for i, I in enumerate(S.patches))
+        for c in range(R):
+            ref = S.sweep(B[:, c], X0[:, c])
+            assert np.abs(got[:, c] - ref).max() <= 8 * EPS * cb * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_smooth_multi_fp32_matrix_cores(hier, k):
+    """FP32 inverses on the matrix cores: error within the FP32 rounding bound."""
+    _, H32, OH, OV = hier[k]
+    R = 16
+    l = 2
+    L, S = OH.levels[l], OV.smoothers[l]
+    B = synth.vector(L.N * R, 1000).reshape(L.N, R)
+    X = _dev(np.zeros((L.N, R)))
+    H32.smooth_multi(l, _dev(B), X, R, 1)    # x = 0 + omega W sum_i R_i^T K_i^{-1} R_i b
+    got = _host(X)
+    # elementwise bound: |delta_i - K_i^{-1} b_i| <= (n_i + 2) eps32 |K_i^{-1}| |b_i| per patch,
+    # then the weighted scatter of those bounds
+    bound = np.zeros((L.N, R))
+    ref = np.zeros((L.N, R))
+    for i, I in enumerate(S.patches):
+        Ainv = sla.lu_solve(S.lu[i], np.eye(len(I)))
+        ref[I] += Ainv @ B[I]
+        bound[I] += (len(I) + 2) * EPS32 * (np.abs(Ainv) @ np.abs(B[I]))
+    w = (S.omega * S.weight)[:, None]
+    ref *= w
+    bound = bound * w + 16 * EPS * np.abs(ref)
+    assert np.all(np.abs(got - ref) <= bound)
+    # and the FP32 path is not just FP64 in disguise (it should differ at FP32 level somewhere)
+    assert np.abs(got - ref).max() > 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_vcycle_multi_fp64(hier, k):
+    H64, _, OH, OV = hier[k]
+    R = 5
+    L = OH.finest
+    Rv = synth.vector(L.N * R, 1100).reshape(L.N, R)
+    E = torch.empty((L.N, R), dtype=torch.float64, device="cuda")
+    H64.vcycle_multi(_dev(Rv), E, R)
+    got = _host(E)
+    cb = max(max(len(I) * np.linalg.cond(S.patch_matrix(i)) for i, I in enumerate(S.patches))
+             for S in OV.smoothers[1:])
+    for c in range(R):
+        ref = OV.apply(Rv[:, c])
+        assert np.abs(got[:, c] - ref).max() <= 32 * EPS * cb * np.abs(ref).max()
+
+
+def _oracle_random_solve(k, g):
+    from oracle import fields, solve
+    OH, OV = solve.setup(2, k, 4, 3, 1.0, lambda nu: fields.random_sine_field(g, nu))
+    x, its, _, conv = solve.solve(OH, OV)
+    return OH, x, its, conv
+
+
+@pytest.mark.parametrize("k,store", [(2, "fp64"), (4, "fp64"), (2, "fp32"), (4, "fp32")])
+def test_solve_multi_matches_single_oracle_solves(hier, k, store):
+    from oracle import solve
+    H64, H32, OH, OV = hier[k]
+    H = H64 if store == "fp64" else H32
+    R = 6
+    gs = [synth.forcing_coeffs(20240922 + j) for j in range(R)]
+    N = OH.finest.N
+    B = np.stack([H.rhs_random(g) for g in gs], axis=1)
+    X = torch.empty((N, R), dtype=torch.float64, device="cuda")
+    status, infos = H.solve_multi(_dev(B), X, R)
+    got = _host(X)
+    for c in range(R):
+        OHc, xo, its, conv = _oracle_random_solve(k, gs[c])
+        Lc = OHc.finest
+        bo = solve.consistent_rhs(Lc)
+        assert np.abs(B[:, c] - bo).max() <= 1e-13 * np.abs(bo).max()
+        res = np.linalg.norm(bo - Lc.K @ got[:, c]) / np.linalg.norm(bo)
+        diff = np.linalg.norm(got[:, c] - xo) / np.linalg.norm(xo)
+        print(f"[gpu-multi] k={k} {store} col {c}: its {infos[c]['iterations']} oracle {its} res {res:.2e} diff {diff:.2e}")
+        assert infos[c]["converged"] and conv
+        assert infos[c]["rel_residual"] <= 1e-10 and res <= 1.05e-10
+        if store == "fp64":
+            assert infos[c]["iterations"] == its
+        else:
+            assert abs(infos[c]["iterations"] - its) <= 2
+        assert diff <= 1e-8
+
+
+@pytest.mark.parametrize("store", ["fp64", "fp32"])
+def test_columns_are_independent(hier, store):
+    """A right-hand side gives bitwise the same solution alone and at any position in a batch."""
+    H64, H32, OH, OV = hier[4]
+    H = H64 if store == "fp64" else H32
+    R = 8
+    N = OH.finest.N
+    B = np.stack([H.rhs_random(synth.forcing_coeffs(77 + j)) for j in range(R)], axis=1)
+    X = torch.empty((N, R), dtype=torch.float64, device="cuda")
+    _, infos = H.solve_multi(_dev(B), X, R)
+    batch = _host(X)
+    perm = np.array([5, 2, 7, 0, 3, 6, 1, 4])
+    Xp = torch.empty((N, R), dtype=torch.float64, device="cuda")
+    _, infos_p = H.solve_multi(_dev(B[:, perm]), Xp, R)
+    shuffled = _host(Xp)
+    for c in (0, 3, 7):
+        x1 = torch.empty((N, 1), dtype=torch.float64, device="cuda")
+        _, i1 = H.solve_multi(_dev(B[:, c:c + 1]), x1, 1)
+        alone = _host(x1)[:, 0]
+        assert np.array_equal(alone, batch[:, c])
+        assert i1[0]["iterations"] == infos[c]["iterations"]
+    for pos, c in enumerate(perm):
+        assert np.array_equal(shuffled[:, pos], batch[:, c])
