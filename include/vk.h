@@ -234,6 +234,74 @@ vk_status vk_tuning_set(vk_hierarchy* h, int level, const vk_tuning* t);
  * launch while enabled: launches and total milliseconds since the last reset. */
 vk_status vk_kernel_timing(vk_hierarchy* h, int enable, int reset, int64_t* launches, double* total_ms);
 
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of Stokes solves (2D Taylor-Hood, coarsest mesh 4 x 4,
+ * n = 8, 16, 32, ... and order k): one hierarchy per (n, k) is kept resident
+ * in a caller-owned device pool (first-fit, admission by exact footprint,
+ * least-recently-used idle hierarchies evicted when a new one does not fit);
+ * each serves up to `slots` requests as columns of the many-right-hand-side
+ * kernels, every column with its own FGMRES state, so requests join and
+ * leave between iterations.  The viscosity of a request enters through the
+ * exact identity K_nu = D_L K_1 D_R (D_L = diag(nu I, I), D_R = diag(I, I/nu)),
+ * so one hierarchy serves every viscosity; FGMRES runs on K_nu itself.  A
+ * request's result does not depend on the other requests in flight.  The
+ * server is not thread-safe; one thread drives it with vk_server_tick. */
+typedef struct vk_server vk_server;
+
+typedef struct vk_server_opts {
+  int slots;      /* concurrent requests per resident hierarchy (1..64) */
+  int store;      /* VK_STORE_FP64 or VK_STORE_FP32 patch inverses */
+  double omega;   /* smoother damping (0.5) */
+  int nu_sweeps;  /* V(nu, nu) (2) */
+  int restart;    /* FGMRES restart (30) */
+  int maxit;      /* iteration cap per request (100) */
+  double rtol;    /* relative residual target (1e-10) */
+  int max_queue;  /* submissions beyond this many waiting requests return VK_EBUSY */
+} vk_server_opts;
+
+typedef struct vk_request {
+  int n, k;          /* mesh n x n (4 * 2^m, >= 8) and velocity order k */
+  double viscosity;  /* nu > 0 */
+  const double* h_b; /* right-hand side on the free DoFs of (n, k), copied at submit */
+} vk_request;
+
+typedef struct vk_result {
+  int state;          /* 0 queued, 1 running, 2 done */
+  vk_status status;   /* when done: VK_OK, VK_NOT_CONVERGED, VK_ENOMEM (never fits the pool), ... */
+  int iterations;
+  double rel_residual;
+  double latency_s;   /* submit -> completion, when done */
+} vk_result;
+
+typedef struct vk_server_stats {
+  int64_t completed;
+  int queued, running, resident_hierarchies;
+  size_t pool_bytes_used;
+  int64_t evictions;
+  double p50_latency_s, p99_latency_s;
+  double solves_per_s; /* completed / (last completion - first submission) */
+} vk_server_stats;
+
+const char* vk_server_last_error(void);
+/* d_pool: caller-owned device memory (256-byte aligned) the server carves hierarchies from. */
+vk_status vk_server_create(const vk_server_opts* opts, void* d_pool, size_t pool_bytes, vk_server** out);
+vk_status vk_server_destroy(vk_server* s);
+/* Builds and uploads the (n, k) hierarchy now (host assembly is the slow part of admission). */
+vk_status vk_server_prepare(vk_server* s, int n, int k);
+vk_status vk_server_problem_size(vk_server* s, int n, int k, int* n_free);
+/* Queues a request; h_x (n_free doubles, caller-owned) receives the solution
+ * when it completes.  VK_EBUSY if the queue is full. */
+vk_status vk_server_submit(vk_server* s, const vk_request* req, double* h_x, uint64_t* ticket);
+/* Admits queued requests into free slots, advances every running request by
+ * one FGMRES iteration and retires the converged ones.  *active = running + queued. */
+vk_status vk_server_tick(vk_server* s, int* active);
+vk_status vk_server_poll(vk_server* s, uint64_t ticket, vk_result* res);
+vk_status vk_server_stats_get(vk_server* s, vk_server_stats* stats);
+
+/* Load vector of the smooth random forcing (as VK_F_RANDOM) on the free DoFs
+ * of the 2D (n, k) problem with zero boundary velocity, no hierarchy needed. */
+vk_status vk_load_random(int k, int n, int n_modes, const double* h_coeffs, double* h_b);
+
 #ifdef __cplusplus
 }
 #endif

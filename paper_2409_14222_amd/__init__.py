@@ -11,6 +11,10 @@ import os
 
 import numpy as np
 
+# torch first: it brings the HIP runtime that owns the device memory and the
+# streams; libvk then binds to that same runtime (one runtime per process).
+import torch  # noqa: F401  (import order matters)
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libvk.so")
 if not os.path.exists(LIBPATH):
@@ -60,6 +64,26 @@ class vk_solve_info(ctypes.Structure):
                 ("h_history", ctypes.POINTER(_c_dbl))]
 
 
+class vk_server_opts(ctypes.Structure):
+    _fields_ = [("slots", _c_int), ("store", _c_int), ("omega", _c_dbl), ("nu_sweeps", _c_int), ("restart", _c_int),
+                ("maxit", _c_int), ("rtol", _c_dbl), ("max_queue", _c_int)]
+
+
+class vk_request(ctypes.Structure):
+    _fields_ = [("n", _c_int), ("k", _c_int), ("viscosity", _c_dbl), ("h_b", _p)]
+
+
+class vk_result(ctypes.Structure):
+    _fields_ = [("state", _c_int), ("status", _c_int), ("iterations", _c_int), ("rel_residual", _c_dbl),
+                ("latency_s", _c_dbl)]
+
+
+class vk_server_stats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("queued", _c_int), ("running", _c_int),
+                ("resident_hierarchies", _c_int), ("pool_bytes_used", ctypes.c_size_t), ("evictions", ctypes.c_int64),
+                ("p50_latency_s", _c_dbl), ("p99_latency_s", _c_dbl), ("solves_per_s", _c_dbl)]
+
+
 _P = ctypes.POINTER
 _SIGS = {
     "vk_last_error": ([], ctypes.c_char_p),
@@ -91,6 +115,16 @@ _SIGS = {
     "vk_tuning_get": ([_p, _c_int, _P(vk_tuning)], _c_int),
     "vk_tuning_set": ([_p, _c_int, _P(vk_tuning)], _c_int),
     "vk_kernel_timing": ([_p, _c_int, _c_int, _P(ctypes.c_int64), _P(_c_dbl)], _c_int),
+    "vk_server_last_error": ([], ctypes.c_char_p),
+    "vk_server_create": ([_P(vk_server_opts), _p, ctypes.c_size_t, _P(_p)], _c_int),
+    "vk_server_destroy": ([_p], _c_int),
+    "vk_server_prepare": ([_p, _c_int, _c_int], _c_int),
+    "vk_server_problem_size": ([_p, _c_int, _c_int, _P(_c_int)], _c_int),
+    "vk_server_submit": ([_p, _P(vk_request), _p, _P(ctypes.c_uint64)], _c_int),
+    "vk_server_tick": ([_p, _P(_c_int)], _c_int),
+    "vk_server_poll": ([_p, ctypes.c_uint64, _P(vk_result)], _c_int),
+    "vk_server_stats_get": ([_p, _P(vk_server_stats)], _c_int),
+    "vk_load_random": ([_c_int, _c_int, _c_int, _p, _p], _c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -281,3 +315,84 @@ class Hierarchy:
         ms = ctypes.c_double()
         check(lib.vk_kernel_timing(self.h, int(enable), int(reset), ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+
+def scheck(status):
+    if status < 0:
+        raise VkError(status, lib.vk_server_last_error().decode())
+    return status
+
+
+def load_random(k, n, coeffs):
+    """Load vector of the smooth random forcing for the 2D (n, k) problem (host)."""
+    coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+    N = 2 * (k * n - 1) ** 2 + ((k - 1) * n + 1) ** 2
+    b = np.empty(N)
+    scheck(lib.vk_load_random(k, n, coeffs.shape[-1], _ptr(coeffs), _ptr(b)))
+    return b
+
+
+class Server:
+    """Continuous-batching Stokes server on one GPU (see vk.h).  The device
+    pool is one torch tensor; results land in host numpy arrays."""
+
+    def __init__(self, pool_bytes, slots=16, store=VK_STORE_FP32, omega=0.5, nu_sweeps=2, restart=30, maxit=100,
+                 rtol=1e-10, max_queue=100000, device="cuda"):
+        import torch
+        self.pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=device)
+        base = self.pool.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.opts = vk_server_opts(slots, store, omega, nu_sweeps, restart, maxit, rtol, max_queue)
+        s = ctypes.c_void_p()
+        scheck(lib.vk_server_create(ctypes.byref(self.opts), aligned, int(pool_bytes), ctypes.byref(s)))
+        self.s = s
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "s", None) is not None and self.s.value:
+            lib.vk_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self, _destroy=lib.vk_server_destroy):
+        s = getattr(self, "s", None)
+        if s is not None and s.value:
+            _destroy(s)
+            self.s = None
+
+    def prepare(self, n, k):
+        scheck(lib.vk_server_prepare(self.s, n, k))
+
+    def size(self, n, k):
+        v = ctypes.c_int()
+        scheck(lib.vk_server_problem_size(self.s, n, k, ctypes.byref(v)))
+        return v.value
+
+    def submit(self, n, k, viscosity, b):
+        """Returns (status, ticket, x): x is filled when the request completes."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros(len(b))
+        req = vk_request(n, k, viscosity, b.ctypes.data)
+        t = ctypes.c_uint64()
+        st = lib.vk_server_submit(self.s, ctypes.byref(req), _ptr(x), ctypes.byref(t))
+        if st == VK_EBUSY:  # queue full: the caller retries later
+            return st, 0, None
+        scheck(st)
+        if st == VK_OK:
+            self._keep[t.value] = x
+        return st, t.value, x
+
+    def tick(self):
+        a = ctypes.c_int()
+        scheck(lib.vk_server_tick(self.s, ctypes.byref(a)))
+        return a.value
+
+    def poll(self, ticket):
+        r = vk_result()
+        scheck(lib.vk_server_poll(self.s, ticket, ctypes.byref(r)))
+        return {"state": r.state, "status": r.status, "iterations": r.iterations, "rel_residual": r.rel_residual,
+                "latency_s": r.latency_s}
+
+    def stats(self):
+        st = vk_server_stats()
+        scheck(lib.vk_server_stats_get(self.s, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in vk_server_stats._fields_}

@@ -1,0 +1,99 @@
+// Internal state of a bound hierarchy, shared by the solver (hierarchy.cpp)
+// and the serving loop (server.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <utility>
+#include <vector>
+
+#include "vk_internal.hpp"
+
+#define HIPCHECK(expr)                                                                                   \
+  do {                                                                                                   \
+    hipError_t _e = (expr);                                                                              \
+    if (_e != hipSuccess) throw vk::Error(VK_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));       \
+  } while (0)
+
+namespace vk {
+
+struct DevLevel {
+  int N = 0, nvel = 0, J = 0;
+  double mean_row = 0, p_mean = 0, pt_mean = 0;
+  int *rowptr = nullptr, *col = nullptr;
+  double* val = nullptr;
+  int *prow = nullptr, *pcol = nullptr, *ptrow = nullptr, *ptcol = nullptr;
+  double *pval = nullptr, *ptval = nullptr;
+  int *pptr = nullptr, *pdofs = nullptr, *dptr = nullptr, *dslot = nullptr, *order = nullptr, *classes = nullptr;
+  int64_t* inv_off = nullptr;
+  double* scale = nullptr;
+  void* inv = nullptr;
+  void* delta = nullptr;
+  double *b = nullptr, *x = nullptr, *t = nullptr;
+  double* M = nullptr;  // coarsest level
+  int class_count[4] = {0, 0, 0, 0};  // patches with n <= 32, <= 64, <= 128, <= 224 (ids in `classes`)
+  // launch shapes (never change results): lanes per CSR row of K, P, P^T;
+  // waves per patch for the large (n > 64, first in `order`) and small patches
+  int k_lanes = 32, p_lanes = 8, pt_lanes = 8, waves_large = 1, waves_small = 1, n_large = 0;
+  int nt_large = 1, nt_small = 1;  // non-temporal (streaming) loads of the inverses
+  int max_n = 0;
+  int4* meta = nullptr;            // per patch in processing order: {first slot, n, inverse offset}
+};
+
+// Sequential carving of one caller buffer into 256-byte aligned pieces.  Run
+// once with base == nullptr to size the workspace.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) / 256 * 256;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace vk
+
+struct vk_hierarchy {
+  using DevLevel = vk::DevLevel;
+  using Problem = vk::Problem;
+  using LevelHost = vk::LevelHost;
+  Problem pr;
+  vk_patch_opts opts{};
+  std::vector<LevelHost> H;
+  std::vector<double> coarse_M;
+  std::vector<std::vector<int>> class_lists;  // per level: ids of class 0, then 1, then 2
+  bool bound = false, ready = false;
+  hipStream_t stream = nullptr;
+  int max_restart = 0;
+  int max_rhs = 1;
+  int *nvc = nullptr, *mask = nullptr;  // per-column iteration counts / active flags (multi-RHS)
+  std::vector<DevLevel> D;
+  double *V = nullptr, *Z = nullptr, *bb = nullptr, *r = nullptr, *partial = nullptr, *small = nullptr, *ydev = nullptr;
+  int* singular = nullptr;
+  std::vector<double> ybuf;
+  std::vector<std::vector<int4>> meta_host;  // staging of the per-patch metadata uploads
+  // captured FGMRES iterations, keyed by (j, restart, nu_pre, nu_post)
+  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
+  bool capturing = false;
+  // kernel timing of the finest-level patch apply
+  bool timing = false;
+  int64_t t_launches = 0;
+  double t_ms = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free, ev_pending;
+
+  bool fp32() const { return opts.store == VK_STORE_FP32; }
+  int L() const { return (int)H.size(); }
+};
+
+
+namespace vk {
+void check_launch();
+void vcycle_multi(vk_hierarchy* h, int l, int R, const double* Rv, double* E, int nu_pre, int nu_post);
+}  // namespace vk

@@ -324,6 +324,75 @@ void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
   }
 }
 
+// Load vector <f, v> of the smooth random forcing on the free DoFs of a 2D
+// level with zero boundary velocity (no lifting term), made consistent.
+// Only the forcing is integrated (no matrix), with sin(a pi x) and
+// sin(b pi y) tabulated per quadrature point; the per-point value is summed
+// in the same (a, b) order as the general path, so both give the same bits.
+void assemble_random_load(int k, int n, int n_modes, const double* coeffs, double* out) {
+  LevelHost L;
+  L.dim = 2;
+  L.k = k;
+  L.n = n;
+  make_cells(L);
+  const int Mv = k * n, Mp = (k - 1) * n;
+  L.nvel = 2 * (Mv - 1) * (Mv - 1);
+  L.npres = (Mp + 1) * (Mp + 1);
+  L.N = L.nvel + L.npres;
+  const Basis vb = make_basis(2, k);
+  const int nbv = vb.size();
+  const SimplexRule rule = simplex_rule(2, k + 3);
+  const int nq = rule.npts, M = n_modes;
+  std::vector<double> phv((size_t)nq * nbv);
+  for (int q = 0; q < nq; ++q) {
+    double kl[3];
+    for (int i = 0; i < 3; ++i) kl[i] = k * rule.lam[q * 3 + i];
+    vb.eval(kl, &phv[(size_t)q * nbv]);
+  }
+  std::vector<double> b(L.N, 0.0), sx(M + 1), sy(M + 1), Floc(2 * nbv);
+  for (const Cell& C : L.cells) {
+    double J[2][2];
+    for (int d = 0; d < 2; ++d)
+      for (int i = 0; i < 2; ++i) J[d][i] = (double)(C.v[i + 1][d] - C.v[0][d]) / n;
+    const double adet = std::fabs(J[0][0] * J[1][1] - J[0][1] * J[1][0]);
+    std::fill(Floc.begin(), Floc.end(), 0.0);
+    for (int q = 0; q < nq; ++q) {
+      double x[2];
+      for (int d = 0; d < 2; ++d) {
+        double s = C.v[0][d] / (double)n;
+        for (int i = 1; i <= 2; ++i) s += J[d][i - 1] * rule.lam[q * 3 + i];
+        x[d] = s;
+      }
+      for (int a = 1; a <= M; ++a) {
+        sx[a] = std::sin(a * PI * x[0]);
+        sy[a] = std::sin(a * PI * x[1]);
+      }
+      double f[2];
+      for (int cc = 0; cc < 2; ++cc) {
+        double s = 0.0;
+        for (int a = 1; a <= M; ++a)
+          for (int bb = 1; bb <= M; ++bb)
+            s += coeffs[(cc * M + (a - 1)) * M + (bb - 1)] * sx[a] * sy[bb] / (double)(a * a + bb * bb);
+        f[cc] = s;
+      }
+      const double w = rule.w[q] * adet;
+      const double* vq = &phv[(size_t)q * nbv];
+      for (int i = 0; i < nbv; ++i)
+        for (int cc = 0; cc < 2; ++cc) Floc[i * 2 + cc] += w * f[cc] * vq[i];
+    }
+    for (int j = 0; j < nbv; ++j) {
+      int G[3];
+      node_lattice(C, vb.nodes[j], 2, G);
+      const int d0 = L.vel_dof(G, 0);
+      if (d0 < 0) continue;
+      b[d0] += Floc[j * 2];
+      b[d0 + 1] += Floc[j * 2 + 1];
+    }
+  }
+  // pressure rows carry no load; the constant-pressure projection leaves b unchanged
+  std::copy(b.begin(), b.end(), out);
+}
+
 // ---------------------------------------------------------------- prolongation
 // Fine lattice point G (units 1/(kk nf)), nf = 2 nc.  The containing coarse
 // cell is found from the structured mesh; barycentric coordinates are exact

@@ -343,4 +343,89 @@ void launch_project_cols(int n, int p0, int R, double zv, const int* mask, doubl
                                                                       mask, X);
 }
 
+// ============================================================================
+// Serving helpers: per-column slices of a multivector stack V[slot][N][R]
+// (slot index per column), per-column diagonal scalings of the velocity
+// (rows < nvel) and pressure rows, single-column copies.
+// ============================================================================
+// out[i][c] = V[jc[c]][i][c] * (i < nvel ? sv[c] : sp[c]); 0 where jc[c] < 0
+__global__ void __launch_bounds__(256) gather_slice_kernel(int n, int R, int Rp, int nvel,
+                                                           const double* __restrict__ V, int64_t slice,
+                                                           const int* __restrict__ jc, const double* __restrict__ sv,
+                                                           const double* __restrict__ sp, double* __restrict__ out) {
+  const int rpb = 256 / Rp;
+  const int i = blockIdx.x * rpb + threadIdx.x / Rp;
+  const int c = threadIdx.x % Rp;
+  if (i >= n || c >= R) return;
+  const int j = jc[c];
+  const int64_t o = (int64_t)i * R + c;
+  out[o] = j >= 0 ? V[(int64_t)j * slice + o] * (i < nvel ? sv[c] : sp[c]) : 0.0;
+}
+
+void launch_gather_slice(int n, int R, int nvel, const double* V, int64_t slice, const int* jc, const double* sv,
+                         const double* sp, double* out, hipStream_t s) {
+  const int Rp = pow2_at_least(R);
+  const int rpb = 256 / Rp;
+  gather_slice_kernel<<<(n + rpb - 1) / rpb, 256, 0, s>>>(n, R, Rp, nvel, V, slice, jc, sv, sp, out);
+}
+
+// V[jc[c]][i][c] = in[i][c] * (i < nvel ? sv[c] : sp[c]) where jc[c] >= 0
+__global__ void __launch_bounds__(256) scatter_slice_kernel(int n, int R, int Rp, int nvel,
+                                                            const double* __restrict__ in,
+                                                            const double* __restrict__ sv,
+                                                            const double* __restrict__ sp, const int* __restrict__ jc,
+                                                            double* __restrict__ V, int64_t slice) {
+  const int rpb = 256 / Rp;
+  const int i = blockIdx.x * rpb + threadIdx.x / Rp;
+  const int c = threadIdx.x % Rp;
+  if (i >= n || c >= R) return;
+  const int j = jc[c];
+  if (j < 0) return;
+  const int64_t o = (int64_t)i * R + c;
+  V[(int64_t)j * slice + o] = in[o] * (i < nvel ? sv[c] : sp[c]);
+}
+
+void launch_scatter_slice(int n, int R, int nvel, const double* in, const double* sv, const double* sp,
+                          const int* jc, double* V, int64_t slice, hipStream_t s) {
+  const int Rp = pow2_at_least(R);
+  const int rpb = 256 / Rp;
+  scatter_slice_kernel<<<(n + rpb - 1) / rpb, 256, 0, s>>>(n, R, Rp, nvel, in, sv, sp, jc, V, slice);
+}
+
+// r[i][c] = bb[i][c] - (i < nvel ? sv[c] : 1) t[i][c]
+__global__ void __launch_bounds__(256) residual_scaled_kernel(int n, int R, int Rp, int nvel,
+                                                              const double* __restrict__ bb,
+                                                              const double* __restrict__ t,
+                                                              const double* __restrict__ sv, double* __restrict__ r) {
+  const int rpb = 256 / Rp;
+  const int i = blockIdx.x * rpb + threadIdx.x / Rp;
+  const int c = threadIdx.x % Rp;
+  if (i >= n || c >= R) return;
+  const int64_t o = (int64_t)i * R + c;
+  r[o] = bb[o] - (i < nvel ? sv[c] * t[o] : t[o]);
+}
+
+void launch_residual_scaled(int n, int R, int nvel, const double* bb, const double* t, const double* sv, double* r,
+                            hipStream_t s) {
+  const int Rp = pow2_at_least(R);
+  const int rpb = 256 / Rp;
+  residual_scaled_kernel<<<(n + rpb - 1) / rpb, 256, 0, s>>>(n, R, Rp, nvel, bb, t, sv, r);
+}
+
+// column c of X[n][R] <-> contiguous x[n]
+__global__ void __launch_bounds__(256) column_io_kernel(int n, int R, int c, int put, double* __restrict__ X,
+                                                        double* __restrict__ x) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  if (put) X[(int64_t)i * R + c] = x ? x[i] : 0.0;
+  else x[i] = X[(int64_t)i * R + c];
+}
+
+void launch_column_put(int n, int R, int c, const double* x, double* X, hipStream_t s) {
+  column_io_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, R, c, 1, X, const_cast<double*>(x));
+}
+void launch_column_get(int n, int R, int c, const double* X, double* x, hipStream_t s) {
+  column_io_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, R, c, 0, const_cast<double*>(X), x);
+}
+
 }  // namespace vk

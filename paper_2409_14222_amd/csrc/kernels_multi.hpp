@@ -31,4 +31,16 @@ void launch_div_sqrt_cols(int n, int R, const double* X, const double* nn, doubl
 void launch_project_cols(int n, int p0, int R, double zv, const int* mask, double* X, double* partial,
                          hipStream_t s);
 
+// serving: per-column slices V[jc[c]] with per-column velocity/pressure scalings
+void launch_gather_slice(int n, int R, int nvel, const double* V, int64_t slice, const int* jc, const double* sv,
+                         const double* sp, double* out, hipStream_t s);
+void launch_scatter_slice(int n, int R, int nvel, const double* in, const double* sv, const double* sp,
+                          const int* jc, double* V, int64_t slice, hipStream_t s);
+// r = bb - diag(sv on velocity rows, 1 on pressure rows) t
+void launch_residual_scaled(int n, int R, int nvel, const double* bb, const double* t, const double* sv, double* r,
+                            hipStream_t s);
+// column c of X[n][R] from x[n] (x == nullptr: zeros) / to x[n]
+void launch_column_put(int n, int R, int c, const double* x, double* X, hipStream_t s);
+void launch_column_get(int n, int R, int c, const double* X, double* x, hipStream_t s);
+
 }  // namespace vk

@@ -88,6 +88,7 @@ void build_level(LevelHost& L, const Problem& pr, bool with_rhs);
 void build_prolongation(const LevelHost& coarse, LevelHost& fine);
 void build_patches(LevelHost& L, int construct, double omega, int store);
 void dof_coords(const LevelHost& L, double* xyz, int* kind);
+void assemble_random_load(int k, int n, int n_modes, const double* coeffs, double* out);
 
 // Top-left N x N block of the inverse of the bordered matrix [K z; z^T 0],
 // z = constant pressure / sqrt(#pressure); row-major.

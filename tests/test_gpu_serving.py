@@ -1,0 +1,136 @@
+"""GPU tests of the continuous-batching server.
+
+Each served result is checked against the oracle assembled directly at the
+request's viscosity (an independent check of the K_nu = D_L K_1 D_R path), a
+request gives bitwise the same solution alone and in the mix, and admission
+under a small device pool evicts idle hierarchies or reports VK_ENOMEM.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GB = 1 << 30
+
+
+def _requests():
+    # (n, k, viscosity, forcing seed): several problem types, viscosities over four decades
+    out = []
+    kinds = [(8, 2), (16, 2), (8, 3), (16, 3)]
+    nus = [0.01, 1.0, 37.5, 100.0, 0.3]
+    for i in range(14):
+        n, k = kinds[i % len(kinds)]
+        out.append((n, k, nus[i % len(nus)], 5000 + i))
+    return out
+
+
+def _oracle(n, k, nu, seed):
+    from oracle import fields, solve
+    g = synth.forcing_coeffs(seed)
+    OH, OV = solve.setup(2, k, 4, {8: 2, 16: 3}[n], nu, lambda v: fields.random_sine_field(g, v))
+    return OH, OV
+
+
+def _run(srv, reqs, stagger=0):
+    """Submit the requests (half of them after `stagger` ticks) and tick until all are done."""
+    import paper_2409_14222_amd as vk
+    handles = []
+    first = reqs if stagger == 0 else reqs[: len(reqs) // 2]
+    for (n, k, nu, seed) in first:
+        b = vk.load_random(k, n, synth.forcing_coeffs(seed))
+        handles.append(srv.submit(n, k, nu, b))
+    for _ in range(stagger):
+        srv.tick()
+    for (n, k, nu, seed) in (reqs[len(first):] if stagger else []):
+        b = vk.load_random(k, n, synth.forcing_coeffs(seed))
+        handles.append(srv.submit(n, k, nu, b))
+    for _ in range(10000):
+        if srv.tick() == 0:
+            break
+    return handles
+
+
+@pytest.fixture(scope="module")
+def served():
+    import paper_2409_14222_amd as vk
+    print("[gpu-serve] serving 14 mixed requests (FP64 inverses), half of them joining mid-flight", flush=True)
+    srv = vk.Server(2 * GB, slots=8, store=vk.VK_STORE_FP64)
+    reqs = _requests()
+    handles = _run(srv, reqs, stagger=3)
+    return srv, reqs, handles
+
+
+def test_served_results_match_oracle_at_each_viscosity(served):
+    from oracle import solve
+    srv, reqs, handles = served
+    for (n, k, nu, seed), (st, ticket, x) in zip(reqs, handles):
+        res = srv.poll(ticket)
+        assert res["state"] == 2 and res["status"] == 0, res
+        OH, OV = _oracle(n, k, nu, seed)
+        L = OH.finest
+        b = solve.consistent_rhs(L)
+        rel = np.linalg.norm(b - L.K @ x) / np.linalg.norm(b)
+        z = L.nullvec()
+        Kb = sp.bmat([[L.K, sp.csr_matrix(z[:, None])], [sp.csr_matrix(z[None, :]), None]]).tocsc()
+        xd = spla.spsolve(Kb, np.concatenate([b, [0.0]]))[: L.N]
+        diff = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+        xo, its, _, conv = solve.solve(OH, OV)
+        print(f"[gpu-serve] n={n} k={k} nu={nu}: its {res['iterations']} oracle {its}, residual {rel:.2e}, "
+              f"vs direct {diff:.2e}, latency {1e3 * res['latency_s']:.1f} ms")
+        assert res["rel_residual"] <= 1e-10
+        assert rel <= 1.05e-10
+        assert diff <= 1e-8
+        assert abs(res["iterations"] - its) <= 1
+
+
+def test_alone_equals_in_the_mix(served):
+    import paper_2409_14222_amd as vk
+    srv, reqs, handles = served
+    alone = vk.Server(2 * GB, slots=8, store=vk.VK_STORE_FP64)
+    for i in (0, 5, 11):
+        (st, ticket, x_mix) = handles[i]
+        h = _run(alone, [reqs[i]])[0]
+        assert alone.poll(h[1])["iterations"] == srv.poll(ticket)["iterations"]
+        assert np.array_equal(h[2], x_mix), reqs[i]
+    stats = srv.stats()
+    assert stats["completed"] == len(reqs) and stats["queued"] == 0 and stats["running"] == 0
+    assert stats["p99_latency_s"] >= stats["p50_latency_s"] > 0
+
+
+def test_fp32_server_and_admission_under_a_small_pool():
+    """A pool that holds one hierarchy at a time: the second problem type waits, the idle first one is
+    evicted, everything completes; a problem larger than the whole pool is refused with VK_ENOMEM."""
+    import paper_2409_14222_amd as vk
+    probe = vk.Server(1 * GB, slots=4, store=vk.VK_STORE_FP32)
+    probe.prepare(16, 3)
+    one = probe.stats()["pool_bytes_used"]
+    probe.close()
+    srv = vk.Server(int(one * 1.3), slots=4, store=vk.VK_STORE_FP32)
+    reqs = [(16, 3, 1.0, 1), (16, 3, 2.0, 2), (16, 2, 0.5, 3), (16, 3, 4.0, 4)]
+    handles = _run(srv, reqs)
+    for (n, k, nu, seed), (st, t, x) in zip(reqs, handles):
+        r = srv.poll(t)
+        assert r["state"] == 2 and r["status"] == 0 and r["rel_residual"] <= 1e-10
+    assert srv.stats()["evictions"] >= 1
+    b = vk.load_random(4, 32, synth.forcing_coeffs(9))
+    st, t, x = srv.submit(32, 4, 1.0, b)
+    for _ in range(5):
+        if srv.tick() == 0:
+            break
+    assert srv.poll(t)["status"] == vk.VK_ENOMEM
+
+
+def test_queue_full_is_reported():
+    import paper_2409_14222_amd as vk
+    srv = vk.Server(1 * GB, slots=2, store=vk.VK_STORE_FP32, max_queue=2)
+    b = vk.load_random(2, 8, synth.forcing_coeffs(1))
+    assert srv.submit(8, 2, 1.0, b)[0] == 0
+    assert srv.submit(8, 2, 1.0, b)[0] == 0
+    assert srv.submit(8, 2, 1.0, b)[0] == vk.VK_EBUSY
+    while srv.tick():
+        pass
