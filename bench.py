@@ -68,6 +68,87 @@ def cpu_sample(workload, iterations):
                       f"full workload, scaled by the {iterations} iterations of a solve"}
 
 
+def serve_bench(args):
+    """Serving workload: 512 requests, mesh n in {16, 32, 64, 128}, order k in {2, 3, 4} (uniform),
+    log10(viscosity) ~ U[-2, 2], smooth random forcing (seed 20240922 + 1000 + id).  Run (i): all
+    requests at t = 0 (throughput); run (ii): Poisson arrivals at 0.8 x the measured capacity
+    (latency).  Hierarchies are prepared and right-hand sides assembled before the clock starts."""
+    import numpy as np
+    import torch
+
+    import paper_2409_14222_amd as vk
+    import synth
+    rng = np.random.default_rng(synth.SEED)
+    nreq = args.serve_requests
+    ns = rng.choice([16, 32, 64, 128], nreq)
+    ks = rng.choice([2, 3, 4], nreq)
+    nus = 10.0 ** rng.uniform(-2.0, 2.0, nreq)
+    gaps = rng.exponential(1.0, nreq)  # unit-rate inter-arrival times, scaled below
+    store = vk.VK_STORE_FP32 if args.store == "fp32" else vk.VK_STORE_FP64
+    t0 = time.perf_counter()
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:  # the library call releases the GIL
+        rhs = list(ex.map(lambda a: vk.load_random(int(a[1]), int(a[0]), synth.forcing_coeffs(synth.SEED + 1000 + a[2])),
+                          zip(ns, ks, range(nreq))))
+    t_rhs = time.perf_counter() - t0
+
+    def make_server():
+        srv = vk.Server(args.serve_pool_gb * (1 << 30), slots=args.serve_slots, store=store)
+        for n in (16, 32, 64, 128):
+            for k in (2, 3, 4):
+                srv.prepare(n, k)
+        return srv
+
+    def run(srv, arrival):
+        torch.cuda.synchronize()
+        start = time.perf_counter()
+        handles = [None] * nreq
+        nxt = 0
+        while True:
+            now = time.perf_counter() - start
+            while nxt < nreq and arrival[nxt] <= now:
+                handles[nxt] = srv.submit(int(ns[nxt]), int(ks[nxt]), float(nus[nxt]), rhs[nxt])
+                nxt += 1
+            active = srv.tick()
+            if nxt == nreq and active == 0:
+                break
+            if active == 0 and nxt < nreq:
+                time.sleep(max(0.0, min(arrival[nxt] - (time.perf_counter() - start), 0.01)))
+        elapsed = time.perf_counter() - start
+        res = [srv.poll(h[1]) for h in handles]
+        lat = np.array([r["latency_s"] for r in res])
+        ok = all(r["status"] == 0 and r["rel_residual"] <= 1e-10 for r in res)
+        return elapsed, lat, ok, res
+
+    t0 = time.perf_counter()
+    srv = make_server()
+    t_prep = time.perf_counter() - t0
+    el, lat, ok, res = run(srv, np.zeros(nreq))
+    cap = nreq / el
+    arrival = np.cumsum(gaps) / (0.8 * cap)
+    el2, lat2, ok2, _ = run(srv, arrival)
+    st = srv.stats()
+    out = {
+        "metric": "Stokes solves/s to 1e-10 rel. residual (served, continuous batching)",
+        "value": cap, "unit": "solves/s", "n_gpus": 1, "steps": nreq, "warmup": 0,
+        "ms_per_step": 1e3 * el / nreq, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if store == vk.VK_STORE_FP64 else "f64 (patch inverses stored/applied in f32)",
+        "data": "synthetic (seeded random smooth forcings, seeded Poisson arrivals)",
+        "config": {"workload": f"{nreq} requests, n in {{16,32,64,128}}, k in {{2,3,4}}, nu log-uniform in "
+                               f"[1e-2, 1e2], V(2,2), omega 0.5, FGMRES(30) to 1e-10",
+                   "slots_per_hierarchy": args.serve_slots, "pool_gb": args.serve_pool_gb, "store": args.store},
+        "all_at_once": {"solves_per_s": cap, "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
+                        "p99_latency_ms": 1e3 * float(np.percentile(lat, 99)), "all_converged": ok,
+                        "mean_iterations": float(np.mean([r["iterations"] for r in res]))},
+        "poisson_0p8_capacity": {"rate_per_s": 0.8 * cap, "solves_per_s": nreq / el2,
+                                 "p50_latency_ms": 1e3 * float(np.percentile(lat2, 50)),
+                                 "p99_latency_ms": 1e3 * float(np.percentile(lat2, 99)), "all_converged": ok2},
+        "resident_hierarchies": st["resident_hierarchies"], "pool_bytes_used": st["pool_bytes_used"],
+        "setup_s": {"prepare_12_hierarchies": t_prep, "assemble_rhs": t_rhs},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +162,10 @@ def main():
     ap.add_argument("--graphs", action="store_true",
                     help="replay every Arnoldi step from a captured HIP graph (the apply kernel is then not "
                          "event-timed; the roofline entry is omitted)")
+    ap.add_argument("--serve", action="store_true", help="serving workload (continuous batching) instead of one solve")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-pool-gb", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy (y = x), the reference for HBM counter scaling")
@@ -105,6 +190,9 @@ def main():
         print("bench.py measures one GPU: the solver path here is single-GPU (multi-GPU sharding is a design "
               "note, not built). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_bench(args)
+        return
 
     import numpy as np
     import torch
