@@ -99,6 +99,35 @@ def poly_k2(nu):
                  lambda x: np.stack([np.full(len(x), 1 - 2 * nu), np.ones(len(x))], 1), gu)
 
 
+def poly_k3(nu):
+    """u = (2x^2 y + x^3, -2 x y^2 - 3 x^2 y) (the curl of x^2 y^2 + x^3 y), p = x^2 + x y - 7/12:
+    lies in (P3, P2) and in (P3, dP2); f = -nu Laplace(u) + grad p."""
+    def u(x):
+        X, Y = x[:, 0], x[:, 1]
+        return np.stack([2 * X * X * Y + X ** 3, -2 * X * Y * Y - 3 * X * X * Y], 1)
+
+    def gu(x):
+        X, Y = x[:, 0], x[:, 1]
+        g = np.zeros((len(X), 2, 2))
+        g[:, 0, 0] = 4 * X * Y + 3 * X * X
+        g[:, 0, 1] = 2 * X * X
+        g[:, 1, 0] = -2 * Y * Y - 6 * X * Y
+        g[:, 1, 1] = -4 * X * Y - 3 * X * X
+        return g
+
+    def f(x):
+        X, Y = x[:, 0], x[:, 1]
+        return np.stack([(2 - 6 * nu) * X + (1 - 4 * nu) * Y, (1 + 4 * nu) * X + 6 * nu * Y], 1)
+
+    return Field(2, u, lambda x: x[:, 0] ** 2 + x[:, 0] * x[:, 1] - 7.0 / 12.0, f, gu)
+
+
+def with_gradient(field, psi, grad_psi):
+    """The same velocity with the pressure p + psi: f gains grad psi (Sec. 2, pressure robustness)."""
+    return Field(field.dim, field.u, lambda x: field.p(x) + psi(x), lambda x: field.f(x) + grad_psi(x),
+                 field.grad_u, field.homogeneous)
+
+
 def poly_k4(nu):
     """u = (2 x^3 y, -3 x^2 y^2), p = x^3 - 1/4: lies in (P4, P3)."""
     def u(x):

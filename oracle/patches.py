@@ -20,7 +20,8 @@ Ordering convention: each patch's DoF list is ascending, and patches are
 ordered by their smallest pressure DoF.
 
 The "star" option (vertex patches only, with the pressure DoFs of the open
-vertex star) is provided for comparison runs.
+vertex star) is provided for comparison runs.  The "macro" option is the
+macro-element patch of the barycentric Scott-Vogelius levels (oracle.sv).
 """
 import numpy as np
 
@@ -38,6 +39,9 @@ def _entity_of(bary):
 
 
 def build_patches(level, construct="composite"):
+    if construct == "macro":
+        from .sv import macro_patches
+        return macro_patches(level)
     dim, k = level.dim, level.k
     # global entity key: frozenset of global vertex tuples
     ent_pdofs = {}          # entity -> set of pressure DoFs interior to it

@@ -11,8 +11,13 @@ from . import mg, th
 
 
 def setup(dim, k, n0, nlevels, nu, field_factory, omega=0.5, nu_sweeps=2, construct="composite",
-          weighting="multiplicity"):
-    H = th.THHierarchy(dim, k, n0, nlevels, nu, field_factory)
+          weighting="multiplicity", family="th"):
+    if family == "sv":
+        from . import sv
+        H = sv.SVHierarchy(k, n0, nlevels, nu, field_factory)
+        construct = "macro"
+    else:
+        H = th.THHierarchy(dim, k, n0, nlevels, nu, field_factory)
     V = mg.VCycle(H, omega=omega, nu_pre=nu_sweeps, nu_post=nu_sweeps, construct=construct,
                   weighting=weighting)
     return H, V
