@@ -29,6 +29,10 @@ WORKLOADS = {
     "p2p1-3d-16": dict(k=2, n0=4, levels=3, dim=3,
                        desc="3D P2-P1 Taylor-Hood, 16^3 cubes each split into 6 Kuhn tetrahedra, 3-level hierarchy "
                             "(4^3, 8^3, 16^3), vertex Vanka (up to 196 DoFs), V(2,2), omega 0.5, FGMRES(30) to 1e-10"),
+    "sv-p3dp2-64": dict(k=3, n0=4, levels=5, family="sv", nrhs=64, store="fp32",
+                        desc="Scott-Vogelius P3-dP2 on the barycentric refinement of the 64x64 two-triangle mesh, "
+                             "5 non-nested levels (4..64), macro-element Vanka (56 DoFs), 64 random smooth forcings "
+                             "solved in lockstep, FP32 matrix-core patch GEMMs, V(2,2), omega 0.5, FGMRES(30) to 1e-10"),
 }
 HBM_PEAK_GBS = 8000.0
 
@@ -55,7 +59,13 @@ def cpu_sample(workload, iterations):
     from oracle import fields, solve
     w = WORKLOADS[workload]
     dim = w.get("dim", 2)
-    H, V = solve.setup(dim, w["k"], w["n0"], w["levels"], 1.0, fields.cube_mms if dim == 3 else fields.baseline_mms)
+    if w.get("family") == "sv":
+        g = synth.forcing_coeffs(synth.SEED)
+        H, V = solve.setup(2, w["k"], w["n0"], w["levels"], 1.0, lambda nu: fields.random_sine_field(g, nu),
+                           family="sv")
+    else:
+        H, V = solve.setup(dim, w["k"], w["n0"], w["levels"], 1.0,
+                           fields.cube_mms if dim == 3 else fields.baseline_mms)
     L = H.finest
     v = synth.vector(L.N, 1)
     v /= np.linalg.norm(v)
@@ -155,10 +165,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="p4p3-64", choices=sorted(WORKLOADS))
-    ap.add_argument("--store", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--nrhs", type=int, default=1,
+    ap.add_argument("--store", default=None, choices=["fp64", "fp32"], help="default: the workload's (else fp64)")
+    ap.add_argument("--nrhs", type=int, default=None,
                     help="right-hand sides solved together (random smooth forcings, seeds 20240922 + j); "
-                         "with --store fp32 the patch applies are FP32 matrix-core GEMMs")
+                         "with --store fp32 the patch applies are FP32 matrix-core GEMMs; default: the "
+                         "workload's (else 1)")
     ap.add_argument("--graphs", action="store_true",
                     help="replay every Arnoldi step from a captured HIP graph (the apply kernel is then not "
                          "event-timed; the roofline entry is omitted)")
@@ -199,6 +210,10 @@ def main():
 
     import paper_2409_14222_amd as vk
     w = WORKLOADS[args.workload]
+    if args.store is None:
+        args.store = w.get("store", "fp64")
+    if args.nrhs is None:
+        args.nrhs = w.get("nrhs", 1)
     store = vk.VK_STORE_FP32 if args.store == "fp32" else vk.VK_STORE_FP64
     torch.cuda.init()
     stream = torch.cuda.Stream()  # a non-default stream (needed for graph capture)
@@ -206,7 +221,8 @@ def main():
     t0 = time.perf_counter()
     dim = w.get("dim", 2)
     H = vk.Hierarchy(w["k"], w["n0"], w["levels"], dim=dim, store=store,
-                     forcing=vk.VK_F_CUBE_MMS if dim == 3 else vk.VK_F_BASELINE_MMS)
+                     forcing=vk.VK_F_CUBE_MMS if dim == 3 else vk.VK_F_BASELINE_MMS,
+                     family=vk.VK_SV if w.get("family") == "sv" else vk.VK_TH)
     t_host = time.perf_counter() - t0
     t0 = time.perf_counter()
     R = args.nrhs
@@ -221,12 +237,16 @@ def main():
     t_tune = time.perf_counter() - t0
     Lf = w["levels"] - 1
     info = H.level_info(Lf)
-    if R == 1:
+    import synth
+    if R == 1 and w.get("family") != "sv":
         b = torch.tensor(H.rhs(), device="cuda")
     else:
-        import synth
-        b = torch.tensor(np.stack([H.rhs_random(synth.forcing_coeffs(synth.SEED + j)) for j in range(R)], axis=1),
-                         device="cuda").contiguous()
+        import concurrent.futures as cf
+        with cf.ThreadPoolExecutor(max_workers=16) as ex:  # the library call releases the GIL
+            cols = list(ex.map(lambda j: H.rhs_random(synth.forcing_coeffs(synth.SEED + j)), range(R)))
+        b = torch.tensor(np.stack(cols, axis=1), device="cuda").contiguous()
+        if R == 1:
+            b = b[:, 0].contiguous()
     x = torch.empty_like(b)
 
     def one_solve():
@@ -307,7 +327,7 @@ def main():
                    HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
         r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample", args.workload,
                             "--cpu-iterations", str(int(round(its_mean)))], capture_output=True, text=True, env=env,
-                           timeout=600)
+                           timeout=900)
         if r.returncode == 0:
             out["cpu_baseline"] = json.loads(r.stdout.strip().splitlines()[-1])
         else:

@@ -58,7 +58,10 @@ enum {
   VK_ESTATE = -7        /* call out of order (e.g. solve before bind) */
 };
 
-enum { VK_TH = 0 }; /* Taylor-Hood (P_k, P_{k-1}), continuous pressure */
+enum {
+  VK_TH = 0, /* Taylor-Hood (P_k, P_{k-1}), continuous pressure */
+  VK_SV = 1  /* Scott-Vogelius (P_k, dP_{k-1}) on the barycentric refinement of each level (Sec. 2) */
+};
 
 enum {
   VK_F_BASELINE_MMS = 0, /* u = (sin pi x sin pi y, cos pi x cos pi y), p = 0 */
@@ -67,13 +70,13 @@ enum {
   VK_F_CUBE_MMS = 3      /* 3D divergence-free sin/cos field, p = 0 */
 };
 
-enum { VK_PATCH_COMPOSITE = 0, VK_PATCH_STAR = 1 };
+enum { VK_PATCH_COMPOSITE = 0, VK_PATCH_STAR = 1, VK_PATCH_MACRO = 2 };
 enum { VK_STORE_FP64 = 0, VK_STORE_FP32 = 1 };
 
 /* Problem statement (Sec. 2 weak form; Sec. 3 hierarchy; Sec. 4 mesh). */
 typedef struct vk_problem {
   int dim;          /* 2 (triangles) or 3 (Kuhn tetrahedra, k = 2 only) */
-  int family;       /* VK_TH */
+  int family;       /* VK_TH, or VK_SV (2D, 2 <= k <= 4, VK_PATCH_MACRO, see below) */
   int k;            /* velocity order, pressure order k-1; 2 <= k <= 6 in 2D */
   int n_coarse;     /* cells per direction on level 0 (>= 1) */
   int n_levels;     /* >= 2 */
@@ -85,7 +88,9 @@ typedef struct vk_problem {
 
 /* Relaxation options (Sec. 3.1, Algorithm 1 as a damped smoother). */
 typedef struct vk_patch_opts {
-  int construct; /* VK_PATCH_COMPOSITE (vertex + edge + cell patches) or VK_PATCH_STAR */
+  int construct; /* VK_TH: VK_PATCH_COMPOSITE (vertex + edge + cell patches) or VK_PATCH_STAR;
+                    VK_SV: VK_PATCH_MACRO (one patch per macro triangle: the pressure of its three
+                    sub-cells and the free velocity on its closure) */
   int store;     /* VK_STORE_FP64, or VK_STORE_FP32: inverses factored in FP64, stored and applied in FP32 */
   double omega;  /* global damping; each DoF is further scaled by 1/multiplicity */
 } vk_patch_opts;
@@ -129,7 +134,19 @@ typedef struct vk_hierarchy vk_hierarchy;
  * finest right-hand side with Dirichlet lifting, prolongations by nodal
  * interpolation (restriction = transpose) and the patch DoF lists and
  * inverse map (Sec. 3.1).  No device memory is touched.  VK_EINVAL on bad
- * sizes; *out receives a hierarchy to be freed with vk_hierarchy_destroy. */
+ * sizes; *out receives a hierarchy to be freed with vk_hierarchy_destroy.
+ *
+ * VK_SV (the Scott-Vogelius pair named in Sec. 2, stable on barycentric
+ * refinements): each level's n x n macro mesh is split at every triangle's
+ * barycentre c into sub-cells (v0,v1,c), (v1,v2,c), (v2,v0,c), numbered
+ * 3 m + s.  Velocity DoFs: the interior P_k nodes of the sub-cell mesh (a
+ * lattice of spacing 1/(3kn)) in lexicographic order, x fastest, components
+ * interleaved.  Pressure DoFs: sub-cell by sub-cell, and inside a sub-cell
+ * the node V0 + (a1 (V1-V0) + a2 (V2-V0))/(k-1) in lexicographic (a1, a2)
+ * order, a1 slower.  The levels are not nested: velocity is transferred by
+ * nodal interpolation, pressure by the exact L^2 projection of the coarse
+ * discontinuous pressure onto each fine sub-cell (the natural embedding
+ * when spaces are nested). */
 vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts, vk_hierarchy** out);
 
 /* Frees host memory.  Device memory (the bound workspace) stays the caller's. */

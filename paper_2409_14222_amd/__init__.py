@@ -24,9 +24,9 @@ lib = ctypes.CDLL(LIBPATH)
 # ---------------------------------------------------------------- constants (include/vk.h)
 VK_OK, VK_NOT_CONVERGED = 0, 1
 VK_EINVAL, VK_ENOMEM, VK_EHIP, VK_ESINGULAR, VK_ENAN, VK_EBUSY, VK_ESTATE = -1, -2, -3, -4, -5, -6, -7
-VK_TH = 0
+VK_TH, VK_SV = 0, 1
 VK_F_BASELINE_MMS, VK_F_PAPER_MMS, VK_F_RANDOM, VK_F_CUBE_MMS = 0, 1, 2, 3
-VK_PATCH_COMPOSITE, VK_PATCH_STAR = 0, 1
+VK_PATCH_COMPOSITE, VK_PATCH_STAR, VK_PATCH_MACRO = 0, 1, 2
 VK_STORE_FP64, VK_STORE_FP32 = 0, 1
 
 _c_int, _c_dbl, _p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
@@ -158,7 +158,9 @@ class Hierarchy:
     on the current device and binds the current stream) and setup()."""
 
     def __init__(self, k, n_coarse, n_levels, dim=2, viscosity=1.0, forcing=VK_F_BASELINE_MMS, coeffs=None,
-                 construct=VK_PATCH_COMPOSITE, store=VK_STORE_FP64, omega=0.5):
+                 construct=None, store=VK_STORE_FP64, omega=0.5, family=VK_TH):
+        if construct is None:
+            construct = VK_PATCH_MACRO if family == VK_SV else VK_PATCH_COMPOSITE
         self._coeffs = None
         n_modes = 0
         cptr = None
@@ -166,7 +168,7 @@ class Hierarchy:
             self._coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
             n_modes = self._coeffs.shape[-1]
             cptr = self._coeffs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        self.prob = vk_problem(dim, VK_TH, k, n_coarse, n_levels, viscosity, forcing, n_modes, cptr)
+        self.prob = vk_problem(dim, family, k, n_coarse, n_levels, viscosity, forcing, n_modes, cptr)
         self.opts = vk_patch_opts(construct, store, omega)
         h = ctypes.c_void_p()
         check(lib.vk_hierarchy_create(ctypes.byref(self.prob), ctypes.byref(self.opts), ctypes.byref(h)))

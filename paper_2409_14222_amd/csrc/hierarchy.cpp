@@ -645,16 +645,21 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
     require(prob && opts && out, VK_EINVAL, "null argument");
     const vk_problem& p = *prob;
     require(p.dim == 2 || p.dim == 3, VK_EINVAL, "dim must be 2 or 3");
-    require(p.family == VK_TH, VK_EINVAL, "unsupported family");
+    require(p.family == VK_TH || (p.family == VK_SV && p.dim == 2), VK_EINVAL, "unsupported family");
+    if (p.family == VK_SV) require(p.k >= 2 && p.k <= 4, VK_EINVAL, "Scott-Vogelius supports 2 <= k <= 4");
     require(p.k >= 2 && p.k <= (p.dim == 2 ? 6 : 2), VK_EINVAL, "unsupported order k");
     require(p.n_coarse >= 1 && p.n_levels >= 2 && p.n_levels <= 12, VK_EINVAL, "bad hierarchy size");
     require(p.viscosity > 0 && std::isfinite(p.viscosity), VK_EINVAL, "viscosity must be positive");
     require(opts->omega > 0 && std::isfinite(opts->omega), VK_EINVAL, "omega must be positive");
     require(opts->store == VK_STORE_FP64 || opts->store == VK_STORE_FP32, VK_EINVAL, "bad store");
-    require(opts->construct == VK_PATCH_COMPOSITE || (opts->construct == VK_PATCH_STAR && p.dim == 2), VK_EINVAL,
-            "bad patch construction");
+    if (p.family == VK_SV)
+      require(opts->construct == VK_PATCH_MACRO, VK_EINVAL, "Scott-Vogelius levels use VK_PATCH_MACRO");
+    else
+      require(opts->construct == VK_PATCH_COMPOSITE || (opts->construct == VK_PATCH_STAR && p.dim == 2), VK_EINVAL,
+              "bad patch construction");
     const int nf = p.n_coarse << (p.n_levels - 1);
-    require((int64_t)nf * p.k <= (p.dim == 2 ? 4096 : 256), VK_EINVAL, "mesh too fine");
+    require((int64_t)nf * p.k * (p.family == VK_SV ? 3 : 1) <= (p.dim == 2 ? 4096 : 256), VK_EINVAL,
+            "mesh too fine");
     if (p.dim == 3) require(p.forcing == VK_F_CUBE_MMS, VK_EINVAL, "3D supports the cube field only");
     else require(p.forcing == VK_F_BASELINE_MMS || p.forcing == VK_F_PAPER_MMS || p.forcing == VK_F_RANDOM,
                  VK_EINVAL, "bad forcing");
@@ -672,6 +677,7 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
       L.dim = p.dim;
       L.k = p.k;
       L.n = p.n_coarse << l;
+      L.family = p.family;
       build_level(L, h->pr, l == p.n_levels - 1);
       if (l > 0) {
         build_prolongation(h->H[l - 1], L);
@@ -1051,19 +1057,10 @@ vk_status vk_rhs_random(const vk_hierarchy* h, int n_modes, const double* coeffs
     require(h && coeffs && hb, VK_EINVAL, "null argument");
     require(h->H.back().dim == 2, VK_EINVAL, "random forcing is defined on the unit square");
     require(n_modes >= 1 && n_modes <= 64, VK_EINVAL, "n_modes out of range");
-    Problem pr = h->pr;
-    pr.p.forcing = VK_F_RANDOM;
-    pr.p.n_modes = n_modes;
-    pr.coeffs.assign(coeffs, coeffs + 2 * n_modes * n_modes);
-    LevelHost L;
-    L.dim = h->H.back().dim;
-    L.k = h->H.back().k;
-    L.n = h->H.back().n;
-    build_level(L, pr, true);
-    const double zv = 1.0 / std::sqrt((double)L.npres);
-    double zb = 0.0;
-    for (int i = L.nvel; i < L.N; ++i) zb += L.b[i] * zv;
-    for (int i = 0; i < L.N; ++i) hb[i] = i < L.nvel ? L.b[i] : L.b[i] - zb * zv;
+    // zero boundary velocity: no lifting, pressure rows are zero, so the load is already
+    // consistent (orthogonal to the constant pressure)
+    const LevelHost& F = h->H.back();
+    assemble_random_load(F.family, F.k, F.n, n_modes, coeffs, hb);
     return VK_OK;
   });
 }

@@ -1,5 +1,6 @@
 // Host-side assembly of one multigrid level: structured mesh, Taylor-Hood
-// DoF numbering, K = [A B^T; B 0] on the free DoFs, right-hand side with
+// (or Scott-Vogelius, whose mesh and numbering come from host_sv.cpp) DoF
+// numbering, K = [A B^T; B 0] on the free DoFs, right-hand side with
 // Dirichlet lifting (Sec. 2 weak form, Sec. 3 per-level saddle-point
 // matrix), and the prolongation by nodal interpolation (Sec. 3, grid
 // transfers: natural embedding of the nested spaces).
@@ -13,6 +14,12 @@ namespace vk {
 static const double PI = 3.14159265358979323846;
 
 int LevelHost::vel_dof(const int* G, int c) const {
+  if (family == VK_SV) {
+    const int M = k * unit;
+    if (G[0] <= 0 || G[1] <= 0 || G[0] >= M || G[1] >= M) return -1;
+    const int id = vmap[(size_t)G[1] * (M + 1) + G[0]];
+    return id < 0 ? -1 : 2 * id + c;
+  }
   const int M = k * n;
   int idx = 0;
   for (int d = dim - 1; d >= 0; --d) {
@@ -59,6 +66,24 @@ static void make_cells(LevelHost& L) {
             L.cells.push_back(c);
           }
   }
+}
+
+void setup_mesh(LevelHost& L) {
+  if (L.family == VK_SV) {
+    setup_mesh_sv(L);
+    return;
+  }
+  make_cells(L);
+  L.unit = L.n;
+  const int Mv = L.k * L.n, Mp = (L.k - 1) * L.n;
+  int nint = 1, np = 1;
+  for (int d = 0; d < L.dim; ++d) {
+    nint *= (Mv - 1);
+    np *= (Mp + 1);
+  }
+  L.nvel = L.dim * nint;
+  L.npres = np;
+  L.N = L.nvel + L.npres;
 }
 
 // exact velocity, forcing (returns dim components)
@@ -117,16 +142,8 @@ static inline void node_lattice(const Cell& c, const std::vector<int>& a, int di
 void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
   const int dim = L.dim, k = L.k;
   const double nu = pr.p.viscosity;
-  make_cells(L);
-  const int Mv = k * L.n, Mp = (k - 1) * L.n;
-  int nint = 1, np = 1;
-  for (int d = 0; d < dim; ++d) {
-    nint *= (Mv - 1);
-    np *= (Mp + 1);
-  }
-  L.nvel = dim * nint;
-  L.npres = np;
-  L.N = L.nvel + L.npres;
+  setup_mesh(L);
+  const int unit = L.unit;
 
   const Basis vb = make_basis(dim, k), pb = make_basis(dim, k - 1);
   const int nbv = vb.size(), nbp = pb.size();
@@ -144,6 +161,10 @@ void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
       for (int c = 0; c < dim; ++c) cvd[(size_t)e * nlv + j * dim + c] = L.vel_dof(G, c);
     }
     for (int j = 0; j < nbp; ++j) {
+      if (L.family == VK_SV) {
+        cpd[(size_t)e * nbp + j] = L.sv_pres_dof(e, pb.nodes[j][1], pb.nodes[j][2]);
+        continue;
+      }
       node_lattice(L.cells[e], pb.nodes[j], dim, G);
       cpd[(size_t)e * nbp + j] = L.pres_dof(G);
     }
@@ -212,7 +233,7 @@ void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
     // affine map x = x0 + J xi, J columns = (x_i - x_0), x = v / n
     double J[3][3], Ji[3][3];
     for (int d = 0; d < dim; ++d)
-      for (int i = 0; i < dim; ++i) J[d][i] = (double)(C.v[i + 1][d] - C.v[0][d]) / L.n;
+      for (int i = 0; i < dim; ++i) J[d][i] = (double)(C.v[i + 1][d] - C.v[0][d]) / unit;
     double det;
     if (dim == 2) {
       det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
@@ -274,7 +295,7 @@ void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
       if (with_rhs) {
         double x[3] = {0, 0, 0};
         for (int d = 0; d < dim; ++d) {
-          double s = C.v[0][d] / (double)L.n;
+          double s = C.v[0][d] / (double)unit;
           for (int i = 1; i <= dim; ++i) s += J[d][i - 1] * rule.lam[q * (dim + 1) + i];
           x[d] = s;
         }
@@ -294,7 +315,7 @@ void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
         int G[3];
         node_lattice(C, vb.nodes[j], dim, G);
         double x[3];
-        for (int d = 0; d < dim; ++d) x[d] = (double)G[d] / (k * L.n);
+        for (int d = 0; d < dim; ++d) x[d] = (double)G[d] / (k * unit);
         field_u(pr, x, &uD[j * dim]);
       }
     }
@@ -329,16 +350,14 @@ void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
 // Only the forcing is integrated (no matrix), with sin(a pi x) and
 // sin(b pi y) tabulated per quadrature point; the per-point value is summed
 // in the same (a, b) order as the general path, so both give the same bits.
-void assemble_random_load(int k, int n, int n_modes, const double* coeffs, double* out) {
+void assemble_random_load(int family, int k, int n, int n_modes, const double* coeffs, double* out) {
   LevelHost L;
   L.dim = 2;
   L.k = k;
   L.n = n;
-  make_cells(L);
-  const int Mv = k * n, Mp = (k - 1) * n;
-  L.nvel = 2 * (Mv - 1) * (Mv - 1);
-  L.npres = (Mp + 1) * (Mp + 1);
-  L.N = L.nvel + L.npres;
+  L.family = family;
+  setup_mesh(L);
+  const int unit = L.unit;
   const Basis vb = make_basis(2, k);
   const int nbv = vb.size();
   const SimplexRule rule = simplex_rule(2, k + 3);
@@ -353,13 +372,13 @@ void assemble_random_load(int k, int n, int n_modes, const double* coeffs, doubl
   for (const Cell& C : L.cells) {
     double J[2][2];
     for (int d = 0; d < 2; ++d)
-      for (int i = 0; i < 2; ++i) J[d][i] = (double)(C.v[i + 1][d] - C.v[0][d]) / n;
+      for (int i = 0; i < 2; ++i) J[d][i] = (double)(C.v[i + 1][d] - C.v[0][d]) / unit;
     const double adet = std::fabs(J[0][0] * J[1][1] - J[0][1] * J[1][0]);
     std::fill(Floc.begin(), Floc.end(), 0.0);
     for (int q = 0; q < nq; ++q) {
       double x[2];
       for (int d = 0; d < 2; ++d) {
-        double s = C.v[0][d] / (double)n;
+        double s = C.v[0][d] / (double)unit;
         for (int i = 1; i <= 2; ++i) s += J[d][i - 1] * rule.lam[q * 3 + i];
         x[d] = s;
       }
@@ -438,6 +457,10 @@ static void locate(int dim, int nc, int kk, const int* G, Cell& cell, double* kl
 }
 
 void build_prolongation(const LevelHost& C, LevelHost& F) {
+  if (F.family == VK_SV) {
+    build_prolongation_sv(C, F);
+    return;
+  }
   const int dim = F.dim;
   Csr P;
   P.nrows = F.N;
@@ -495,6 +518,10 @@ void build_prolongation(const LevelHost& C, LevelHost& F) {
 }
 
 void dof_coords(const LevelHost& L, double* xyz, int* kind) {
+  if (L.family == VK_SV) {
+    dof_coords_sv(L, xyz, kind);
+    return;
+  }
   const int dim = L.dim, Mv = L.k * L.n, Mp = (L.k - 1) * L.n;
   const int nint = L.nvel / dim;
   for (int idx = 0; idx < nint; ++idx) {

@@ -48,6 +48,12 @@ inline Cell tri_upper(int i, int j) { return {{{i + 1, j + 1, 0}, {i, j + 1, 0},
 }  // namespace
 
 void build_patches(LevelHost& L, int construct, double omega, int store) {
+  if (construct == VK_PATCH_MACRO) {
+    require(L.family == VK_SV, VK_EINVAL, "macro patches belong to Scott-Vogelius levels");
+    build_patches_macro(L, omega, store);
+    return;
+  }
+  require(L.family == VK_TH, VK_EINVAL, "Scott-Vogelius levels use macro patches");
   Builder B(L);
   const int n = L.n, k = L.k, km = k - 1;
   std::vector<std::vector<int>> patches;
@@ -163,6 +169,10 @@ void build_patches(LevelHost& L, int construct, double omega, int store) {
         }
   }
 
+  finalize_patches(L, patches, omega, store);
+}
+
+void finalize_patches(LevelHost& L, std::vector<std::vector<int>>& patches, double omega, int store) {
   // order by smallest pressure DoF
   std::vector<std::pair<int, int>> key(patches.size());
   for (size_t p = 0; p < patches.size(); ++p) {

@@ -716,7 +716,7 @@ vk_status vk_load_random(int k, int n, int n_modes, const double* coeffs, double
     require(coeffs && hb, VK_EINVAL, "null argument");
     require(k >= 2 && k <= 6 && n >= 1 && n <= 4096 / k, VK_EINVAL, "bad problem size");
     require(n_modes >= 1 && n_modes <= 64, VK_EINVAL, "n_modes out of range");
-    assemble_random_load(k, n, n_modes, coeffs, hb);
+    assemble_random_load(VK_TH, k, n, n_modes, coeffs, hb);
     return VK_OK;
   });
 }

@@ -60,6 +60,9 @@ struct Cell {
 
 struct LevelHost {
   int dim = 2, k = 2, n = 0;
+  int family = VK_TH;        // VK_TH or VK_SV (barycentric sub-cells, discontinuous pressure)
+  int unit = 0;              // cell vertex coordinates are integers in units of 1/unit (n, or 3n for VK_SV)
+  std::vector<int> vmap;     // VK_SV: velocity lattice point y * (k unit + 1) + x -> interior node or -1
   int N = 0, nvel = 0, npres = 0;
   std::vector<Cell> cells;
   Csr K;
@@ -76,7 +79,9 @@ struct LevelHost {
   int64_t sum_n2 = 0;
 
   int vel_dof(const int* G, int c) const;  // -1 on the boundary
-  int pres_dof(const int* G) const;
+  int pres_dof(const int* G) const;         // VK_TH only
+  // VK_SV: pressure DoF of local node (a1, a2) of sub-cell e (node V0 + (a1 E1 + a2 E2) / (k - 1))
+  int sv_pres_dof(int e, int a1, int a2) const;
 };
 
 struct Problem {
@@ -84,11 +89,22 @@ struct Problem {
   std::vector<double> coeffs;
 };
 
+// cells, DoF numbering and counts of a level (dim, k, n, family set by the caller)
+void setup_mesh(LevelHost& L);
 void build_level(LevelHost& L, const Problem& pr, bool with_rhs);
 void build_prolongation(const LevelHost& coarse, LevelHost& fine);
 void build_patches(LevelHost& L, int construct, double omega, int store);
+// ordering, inverse map, relaxation scale and inverse storage of collected patch DoF lists
+void finalize_patches(LevelHost& L, std::vector<std::vector<int>>& patches, double omega, int store);
 void dof_coords(const LevelHost& L, double* xyz, int* kind);
-void assemble_random_load(int k, int n, int n_modes, const double* coeffs, double* out);
+// load vector of the random forcing (zero boundary velocity) on the finest-level numbering of (family, k, n)
+void assemble_random_load(int family, int k, int n, int n_modes, const double* coeffs, double* out);
+
+// Scott-Vogelius levels (host_sv.cpp)
+void setup_mesh_sv(LevelHost& L);
+void build_prolongation_sv(const LevelHost& coarse, LevelHost& fine);
+void build_patches_macro(LevelHost& L, double omega, int store);
+void dof_coords_sv(const LevelHost& L, double* xyz, int* kind);
 
 // Top-left N x N block of the inverse of the bordered matrix [K z; z^T 0],
 // z = constant pressure / sqrt(#pressure); row-major.

@@ -153,3 +153,63 @@ def test_singular_coarsest_level_is_reported():
     with pytest.raises(vk.VkError) as e:
         vk.Hierarchy(2, 1, 2, dim=3, forcing=vk.VK_F_CUBE_MMS)
     assert e.value.code == vk.VK_ESINGULAR
+
+
+# ---------------------------------------------------------------- Scott-Vogelius (barycentric) levels
+@pytest.mark.parametrize("k", [2, 3])
+def test_host_assembly_sv_matches_oracle(k):
+    """P_k-dP_{k-1} on barycentric refinements of 2x2 / 4x4 / 8x8: numbering, CSR, non-nested
+    transfers (nodal velocity, exact L^2 pressure projection), macro patches and the rhs."""
+    from oracle import sv
+    H = vk.Hierarchy(k, 2, 3, family=vk.VK_SV)
+    OH = sv.SVHierarchy(k, 2, 3, 1.0, fields.baseline_mms)
+    for l in range(3):
+        ol = OH.levels[l]
+        inf = H.level_info(l)
+        assert (inf.n_free, inf.nnz, inf.n_velocity) == (ol.N, ol.K.nnz, ol.nu_free)
+        X, kind = H.dof_coords(l)
+        OX, okind = ol.dof_coords()
+        assert np.array_equal(kind, okind) and np.abs(X - OX).max() < 1e-15
+        rp, col, val = H.csr(l)
+        assert np.array_equal(rp, ol.K.indptr) and np.array_equal(col, ol.K.indices)
+        B = ol.vb
+        cV = np.linalg.cond(B._mono(B.nodes))
+        rowmax = np.maximum.reduceat(np.abs(ol.K.data), ol.K.indptr[:-1])
+        assert np.all(np.abs(val - ol.K.data) <= cV * np.finfo(float).eps * np.repeat(rowmax, np.diff(ol.K.indptr)))
+        if l > 0:
+            prp, pcol, pval = H.prolongation(l)
+            P = OH.P[l]
+            assert np.array_equal(prp, P.indptr) and np.array_equal(pcol, P.indices)
+            # the pressure rows come from clipped-polygon quadrature and a 3x3 / 6x6 mass solve on
+            # both sides (values up to ~2): a few hundred roundings
+            assert np.abs(pval - P.data).max() <= 1e-13
+            ptr, dofs = H.patches(l)
+            op = patches.build_patches(ol, "macro")
+            assert [list(dofs[ptr[i]:ptr[i + 1]]) for i in range(len(op))] == [list(I) for I in op]
+    assert np.abs(H.rhs() - solve.consistent_rhs(OH.finest)).max() <= 1e-13 * np.abs(OH.finest.b).max()
+
+
+def test_sv_counts_and_random_rhs():
+    import synth
+    from oracle import sv
+    H = vk.Hierarchy(3, 4, 3, family=vk.VK_SV)
+    for l, n in enumerate((4, 8, 16)):
+        inf = H.level_info(l)
+        assert inf.n_free == 90 * n * n - 12 * n + 2
+    inf = H.level_info(2)
+    assert (inf.nnz, inf.n_patches, inf.sum_n, inf.sum_n2, inf.max_n) == (802292, 512, 28044, 1539784, 56)
+    g = synth.forcing_coeffs(7)
+    Hs = vk.Hierarchy(3, 2, 2, family=vk.VK_SV)
+    L = sv.SVLevel(3, 4, 1.0, fields.random_sine_field(g))
+    assert np.abs(Hs.rhs_random(g) - solve.consistent_rhs(L)).max() <= 1e-13 * np.abs(L.b).max()
+
+
+def test_sv_invalid_combinations_are_rejected():
+    for kw in (dict(family=vk.VK_SV, construct=vk.VK_PATCH_COMPOSITE), dict(construct=vk.VK_PATCH_MACRO),
+               dict(family=vk.VK_SV, dim=3, forcing=vk.VK_F_CUBE_MMS)):
+        with pytest.raises(vk.VkError) as e:
+            vk.Hierarchy(3, 2, 2, **kw)
+        assert e.value.code == vk.VK_EINVAL
+    with pytest.raises(vk.VkError) as e:
+        vk.Hierarchy(5, 2, 2, family=vk.VK_SV)
+    assert e.value.code == vk.VK_EINVAL
