@@ -41,6 +41,8 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.rowptr = cv.take<int>(lh.N + 1);
     d.col = cv.take<int>(lh.K.col.size());
     d.val = cv.take<double>(lh.K.val.size());
+    d.nkg = (int)lh.kgrp.size() - 1;
+    d.kgrp = cv.take<int>(lh.kgrp.size());
     d.b = cv.take<double>((size_t)lh.N * R);
     d.x = cv.take<double>((size_t)lh.N * R);
     d.t = cv.take<double>((size_t)lh.N * R);
@@ -54,6 +56,10 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.ptrow = cv.take<int>(lh.PT.rowptr.size());
     d.ptcol = cv.take<int>(lh.PT.col.size());
     d.ptval = cv.take<double>(lh.PT.val.size());
+    d.npg = (int)lh.pgrp.size() - 1;
+    d.pgrp = cv.take<int>(lh.pgrp.size());
+    d.nptg = (int)lh.ptgrp.size() - 1;
+    d.ptgrp = cv.take<int>(lh.ptgrp.size());
     d.p_mean = (double)lh.P.nnz() / std::max(1, lh.P.nrows);
     d.pt_mean = (double)lh.PT.nnz() / std::max(1, lh.PT.nrows);
     d.p_lanes = csr_default_lanes(d.p_mean);
@@ -80,7 +86,7 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
   h->bb = cv.take<double>((size_t)N * R);
   h->r = cv.take<double>((size_t)N * R);
   h->partial = cv.take<double>(std::max<size_t>((size_t)kReduceBlocks * 2 * (max_restart + 2) + 512,
-                                                (size_t)(max_restart + 2) * 64 * 64 + 64 * 64 + 64));
+                                                (size_t)(max_restart + 2) * kColBlocks * 64 + kColBlocks * 64 + 64));
   h->small = cv.take<double>((size_t)4 * (max_restart + 2) * R + 16);
   h->ydev = cv.take<double>((size_t)(max_restart + 2) * R);
   h->singular = cv.take<int>(64);
@@ -413,7 +419,7 @@ void smooth_multi(vk_hierarchy* h, int l, int R, const double* B, double* X, int
     const bool first_zero = x_zero && it == 0;
     const double* T = B;
     if (!first_zero) {
-      launch_spmm(1, d.N, R, d.rowptr, d.col, d.val, X, B, d.t, s);
+      launch_spmm(1, d.N, d.nkg, d.kgrp, R, d.rowptr, d.col, d.val, X, B, d.t, s);
       T = d.t;
     }
     const bool timed = h->timing && !h->capturing && l == h->L() - 1;
@@ -454,11 +460,11 @@ void vk::vcycle_multi(vk_hierarchy* h, int l, int R, const double* Rv, double* E
   }
   DevLevel& c = h->D[l - 1];
   smooth_multi(h, l, R, Rv, E, nu_pre, true);
-  launch_spmm(1, d.N, R, d.rowptr, d.col, d.val, E, Rv, d.t, s);
-  launch_spmm(0, c.N, R, d.ptrow, d.ptcol, d.ptval, d.t, nullptr, c.b, s);
+  launch_spmm(1, d.N, d.nkg, d.kgrp, R, d.rowptr, d.col, d.val, E, Rv, d.t, s);
+  launch_spmm(0, c.N, d.nptg, d.ptgrp, R, d.ptrow, d.ptcol, d.ptval, d.t, nullptr, c.b, s);
   check_launch();
   vcycle_multi(h, l - 1, R, c.b, c.x, nu_pre, nu_post);
-  launch_spmm(2, d.N, R, d.prow, d.pcol, d.pval, c.x, nullptr, E, s);
+  launch_spmm(2, d.N, d.npg, d.pgrp, R, d.prow, d.pcol, d.pval, c.x, nullptr, E, s);
   check_launch();
   smooth_multi(h, l, R, Rv, E, nu_post, false);
 }
@@ -539,7 +545,7 @@ vk_status fgmres_multi(vk_hierarchy* h, int R, const double* B, double* X, const
       double* zj = h->Z + j * NR;
       double* w = h->V + (j + 1) * NR;
       vcycle_multi(h, Lf, R, vj, zj, o.nu_pre, o.nu_post);
-      launch_spmm(0, N, R, F.rowptr, F.col, F.val, zj, nullptr, w, s);
+      launch_spmm(0, N, F.nkg, F.kgrp, R, F.rowptr, F.col, F.val, zj, nullptr, w, s);
       launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h->small, s);
       launch_axpy_cols(N, R, j + 1, nullptr, -1.0, h->V, NR, h->small, w, s);
       launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h->small + (size_t)(m + 2) * R, s);
@@ -600,7 +606,7 @@ vk_status fgmres_multi(vk_hierarchy* h, int R, const double* B, double* X, const
     HIPCHECK(hipMemcpyAsync(h->mask, mask.data(), R * sizeof(int), hipMemcpyHostToDevice, s));
     launch_axpy_cols(N, R, m, h->nvc, 1.0, h->Z, (int64_t)N * R, h->ydev, X, s);
     launch_project_cols(N, nvel, R, zv, h->mask, X, h->partial, s);
-    launch_spmm(1, N, R, F.rowptr, F.col, F.val, X, h->bb, h->r, s);
+    launch_spmm(1, N, F.nkg, F.kgrp, R, F.rowptr, F.col, F.val, X, h->bb, h->r, s);
     check_launch();
   }
   if (h->timing) collect_timing(h);
@@ -679,8 +685,11 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
       L.n = p.n_coarse << l;
       L.family = p.family;
       build_level(L, h->pr, l == p.n_levels - 1);
+      L.kgrp = row_groups(L.K, 8);
       if (l > 0) {
         build_prolongation(h->H[l - 1], L);
+        L.pgrp = row_groups(L.P, 8);
+        L.ptgrp = row_groups(L.PT, 8);
         build_patches(L, opts->construct, opts->omega, opts->store);
         require(L.max_n <= 224, VK_EINVAL, "patches above 224 DoFs are not supported");
       }
@@ -753,6 +762,7 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_r
       up(d.rowptr, L.K.rowptr, s);
       up(d.col, L.K.col, s);
       up(d.val, L.K.val, s);
+      up(d.kgrp, L.kgrp, s);
       if (l == 0) {
         up(d.M, h->coarse_M, s);
         continue;
@@ -763,6 +773,8 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_r
       up(d.ptrow, L.PT.rowptr, s);
       up(d.ptcol, L.PT.col, s);
       up(d.ptval, L.PT.val, s);
+      up(d.pgrp, L.pgrp, s);
+      up(d.ptgrp, L.ptgrp, s);
       up(d.pptr, L.pptr, s);
       up(d.pdofs, L.pdofs, s);
       up(d.dptr, L.dptr, s);

@@ -25,6 +25,8 @@ struct DevLevel {
   double mean_row = 0, p_mean = 0, pt_mean = 0;
   int *rowptr = nullptr, *col = nullptr;
   double* val = nullptr;
+  int *kgrp = nullptr, *pgrp = nullptr, *ptgrp = nullptr;  // row runs with identical patterns (K, P, P^T)
+  int nkg = 0, npg = 0, nptg = 0;
   int *prow = nullptr, *pcol = nullptr, *ptrow = nullptr, *ptcol = nullptr;
   double *pval = nullptr, *ptval = nullptr;
   int *pptr = nullptr, *pdofs = nullptr, *dptr = nullptr, *dslot = nullptr, *order = nullptr, *classes = nullptr;

@@ -1,5 +1,6 @@
 // Host-side finite-element building blocks: quadrature on simplices and the
 // equispaced Lagrange basis in barycentric form (Sec. 2, Taylor-Hood spaces).
+#include <algorithm>
 #include <cmath>
 
 #include "vk_internal.hpp"
@@ -145,6 +146,22 @@ Csr transpose(const Csr& a) {
       pos[c]++;
     }
   return t;
+}
+
+std::vector<int> row_groups(const Csr& a, int cap) {
+  std::vector<int> g;
+  int r = 0;
+  while (r < a.nrows) {
+    g.push_back(r);
+    const int b = a.rowptr[r], m = a.rowptr[r + 1] - b;
+    int e = r + 1;
+    while (e < a.nrows && e - r < cap && a.rowptr[e + 1] - a.rowptr[e] == m &&
+           std::equal(a.col.begin() + b, a.col.begin() + b + m, a.col.begin() + a.rowptr[e]))
+      ++e;
+    r = e;
+  }
+  g.push_back(a.nrows);
+  return g;
 }
 
 }  // namespace vk

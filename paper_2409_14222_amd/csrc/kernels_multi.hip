@@ -20,36 +20,138 @@ static inline int pow2_at_least(int r) {
 }
 
 // ============================================================================
-// SpMM: Y = A X (mode 0), Y = B - A X (mode 1), Y += A X (mode 2).  One lane
-// per right-hand side, 256 / Rp rows per block; each lane sums its row in
-// ascending entry order.
+// SpMM: Y = A X (mode 0), Y = B - A X (mode 1), Y += A X (mode 2), one lane
+// per right-hand side.  Rows come in runs with identical column lists (the
+// two components of a velocity node; the pressure DoFs of a discontinuous
+// cell; at most 8 rows): Rp lanes take one run, read each needed row of X
+// once for the whole run, and sum every row of the run in ascending entry
+// order.  Entries are taken 8 at a time so that 8 row loads of X are in
+// flight per lane.
 // ============================================================================
-template <int MODE>
-__global__ void __launch_bounds__(256) spmm_kernel(int nrows, int R, int Rp, const int* __restrict__ rowptr,
-                                                   const int* __restrict__ col, const double* __restrict__ val,
-                                                   const double* __restrict__ X, const double* __restrict__ B,
-                                                   double* __restrict__ Y) {
-  const int rpb = 256 / Rp;
-  const int row = blockIdx.x * rpb + threadIdx.x / Rp;
-  const int c = threadIdx.x % Rp;
-  if (row >= nrows || c >= R) return;
-  double acc = 0.0;
-  for (int q = rowptr[row]; q < rowptr[row + 1]; ++q) acc += val[q] * X[(int64_t)col[q] * R + c];
-  const int64_t o = (int64_t)row * R + c;
-  if (MODE == 0) Y[o] = acc;
-  else if (MODE == 1) Y[o] = B[o] - acc;
-  else Y[o] += acc;
+template <int MODE, int G>
+__device__ __forceinline__ void spmm_run(int r0, int c, int R, const int* __restrict__ rowptr,
+                                         const int* __restrict__ col, const double* __restrict__ val,
+                                         const double* __restrict__ X, const double* __restrict__ B,
+                                         double* __restrict__ Y, bool store = true) {
+  const int qb = rowptr[r0], m = rowptr[r0 + 1] - qb;  // every row of the run has m entries
+  double acc[G];
+#pragma unroll
+  for (int t = 0; t < G; ++t) acc[t] = 0.0;
+  int q = 0;
+  for (; q + 8 <= m; q += 8) {
+    int cc[8];
+    double xx[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cc[u] = col[qb + q + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xx[u] = X[(int64_t)cc[u] * R + c];
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      double vv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) vv[u] = val[qb + t * m + q + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[t] += vv[u] * xx[u];
+    }
+  }
+  if (q < m) {
+    // the last partial batch is padded with its final entry, whose value is multiplied by zero:
+    // the padded terms add zeros (X is finite), so the sums keep the ascending order
+    int cc[8];
+    double xx[8], msk[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      cc[u] = col[qb + min(q + u, m - 1)];
+      msk[u] = q + u < m ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xx[u] = X[(int64_t)cc[u] * R + c];
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      double vv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) vv[u] = val[qb + t * m + min(q + u, m - 1)] * msk[u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[t] += vv[u] * xx[u];
+    }
+  }
+  if (!store) return;
+#pragma unroll
+  for (int t = 0; t < G; ++t) {
+    const int64_t o = (int64_t)(r0 + t) * R + c;
+    if (MODE == 0) Y[o] = acc[t];
+    else if (MODE == 1) Y[o] = B[o] - acc[t];
+    else Y[o] += acc[t];
+  }
 }
 
-void launch_spmm(int mode, int nrows, int R, const int* rp, const int* col, const double* val, const double* X,
-                 const double* B, double* Y, hipStream_t s) {
+template <int MODE>
+__global__ void __launch_bounds__(256) spmm_kernel(int ngroups, const int* __restrict__ grp, int R, int Rp,
+                                                   const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                   const double* __restrict__ val, const double* __restrict__ X,
+                                                   const double* __restrict__ B, double* __restrict__ Y) {
+  const int gpb = 256 / Rp;
+  const int g = blockIdx.x * gpb + threadIdx.x / Rp;
+  const int c = threadIdx.x % Rp;
+  if (g >= ngroups || c >= R) return;
+  const int r0 = grp[g];
+  switch (grp[g + 1] - r0) {
+    case 1: spmm_run<MODE, 1>(r0, c, R, rowptr, col, val, X, B, Y); break;
+    case 2: spmm_run<MODE, 2>(r0, c, R, rowptr, col, val, X, B, Y); break;
+    case 3: spmm_run<MODE, 3>(r0, c, R, rowptr, col, val, X, B, Y); break;
+    case 4: spmm_run<MODE, 4>(r0, c, R, rowptr, col, val, X, B, Y); break;
+    case 5: spmm_run<MODE, 5>(r0, c, R, rowptr, col, val, X, B, Y); break;
+    case 6: spmm_run<MODE, 6>(r0, c, R, rowptr, col, val, X, B, Y); break;
+    case 7: spmm_run<MODE, 7>(r0, c, R, rowptr, col, val, X, B, Y); break;
+    default: spmm_run<MODE, 8>(r0, c, R, rowptr, col, val, X, B, Y); break;  // runs are capped at 8 rows
+  }
+}
+
+// R > 32: one run per wave.  The run index is made wave-uniform (readfirstlane), so the row
+// pointers, column indices and values, identical for all lanes, are fetched by scalar loads and
+// only the accumulators and the X rows occupy vector registers.  Lanes c >= R follow the same
+// control flow on a clamped column and store nothing.
+template <int MODE>
+__global__ void __launch_bounds__(256) spmm_wave_kernel(int ngroups, const int* __restrict__ grp, int R,
+                                                        const int* __restrict__ rowptr,
+                                                        const int* __restrict__ col, const double* __restrict__ val,
+                                                        const double* __restrict__ X, const double* __restrict__ B,
+                                                        double* __restrict__ Y) {
+  const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (g >= ngroups) return;
+  const int c = threadIdx.x & 63;
+  const int cl = c < R ? c : R - 1;
+  const bool st = c < R;
+  const int r0 = __builtin_amdgcn_readfirstlane(grp[g]);
+  switch (__builtin_amdgcn_readfirstlane(grp[g + 1]) - r0) {
+    case 1: spmm_run<MODE, 1>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
+    case 2: spmm_run<MODE, 2>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
+    case 3: spmm_run<MODE, 3>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
+    case 4: spmm_run<MODE, 4>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
+    case 5: spmm_run<MODE, 5>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
+    case 6: spmm_run<MODE, 6>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
+    case 7: spmm_run<MODE, 7>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
+    default: spmm_run<MODE, 8>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
+  }
+}
+
+void launch_spmm(int mode, int nrows, int ngroups, const int* grp, int R, const int* rp, const int* col,
+                 const double* val, const double* X, const double* B, double* Y, hipStream_t s) {
+  (void)nrows;
+  if (ngroups <= 0) return;
+  if (R > 32) {
+    const int grid = (ngroups + 3) / 4;
+    if (mode == 0) spmm_wave_kernel<0><<<grid, 256, 0, s>>>(ngroups, grp, R, rp, col, val, X, B, Y);
+    else if (mode == 1) spmm_wave_kernel<1><<<grid, 256, 0, s>>>(ngroups, grp, R, rp, col, val, X, B, Y);
+    else spmm_wave_kernel<2><<<grid, 256, 0, s>>>(ngroups, grp, R, rp, col, val, X, B, Y);
+    return;
+  }
   const int Rp = pow2_at_least(R);
-  const int rpb = 256 / Rp;
-  const int grid = (nrows + rpb - 1) / rpb;
-  if (grid == 0) return;
-  if (mode == 0) spmm_kernel<0><<<grid, 256, 0, s>>>(nrows, R, Rp, rp, col, val, X, B, Y);
-  else if (mode == 1) spmm_kernel<1><<<grid, 256, 0, s>>>(nrows, R, Rp, rp, col, val, X, B, Y);
-  else spmm_kernel<2><<<grid, 256, 0, s>>>(nrows, R, Rp, rp, col, val, X, B, Y);
+  const int gpb = 256 / Rp;
+  const int grid = (ngroups + gpb - 1) / gpb;
+  if (mode == 0) spmm_kernel<0><<<grid, 256, 0, s>>>(ngroups, grp, R, Rp, rp, col, val, X, B, Y);
+  else if (mode == 1) spmm_kernel<1><<<grid, 256, 0, s>>>(ngroups, grp, R, Rp, rp, col, val, X, B, Y);
+  else spmm_kernel<2><<<grid, 256, 0, s>>>(ngroups, grp, R, Rp, rp, col, val, X, B, Y);
 }
 
 // ============================================================================
@@ -64,63 +166,106 @@ void launch_spmm(int mode, int nrows, int R, const int* rp, const int* col, cons
 // ============================================================================
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
-// NW waves per patch; wave w computes the 16-row tiles w, w + NW, ...  The
-// residual block lives in dynamic LDS sized by the launch's largest patch.
-// The A operand is prefetched 8 MFMA steps (32 columns of K_i^{-1}) ahead.
+// NW waves per patch (nmax <= 64 NW); wave w computes the 16-row tiles w,
+// w + NW, ...  The residual block R_i T (FP64 rows of T, converted to FP32)
+// is staged in dynamic LDS sized by the launch's largest patch, with the
+// column index XOR-swizzled by bit 0 of the row so that the four k-groups of
+// one MFMA read disjoint banks.  Latency hiding: the patch's DoF indices sit
+// in registers (read back with readlane), each lane keeps 16 row loads in
+// flight during the gather, and the A operand of a tile (16 MFMA steps = 64
+// columns of K_i^{-1}) is loaded in one batch, the first one before the
+// gather and each next one before the current tile's stores.
+__device__ __forceinline__ int bs_index(int j, int c) { return j * 64 + (c ^ ((j & 1) << 4)); }
+
 template <int NW>
 __global__ void __launch_bounds__(64 * NW) patch_gemm_mfma_kernel(const int4* __restrict__ meta,
                                                                   const int* __restrict__ pdofs,
                                                                   const float* __restrict__ inv,
                                                                   const double* __restrict__ T, int R, int nmax,
                                                                   float* __restrict__ delta) {
-  extern __shared__ float Bs[];  // [nk][64]
+  extern __shared__ float Bs[];  // [nk][64], swizzled
   const int4 m4 = meta[blockIdx.x];
   const int base = m4.x, n = m4.y;
   const int64_t off = (int64_t)(uint32_t)m4.z | ((int64_t)m4.w << 32);
-  if (n > nmax || n <= 0) return;  // the launch sizes LDS for nmax >= every n; never taken
+  if (n > nmax || n <= 0 || n > 64 * NW) return;  // the launch sizes LDS and waves for every n; never taken
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int ld = (n + 3) / 4 * 4;  // FP32 inverses: leading dimension rounded to 4
   const int nk = ld;               // depth padded to the MFMA depth 4
-  for (int e = tid; e < nk * 64; e += 64 * NW) {
-    const int j = e >> 6, c = e & 63;
-    Bs[e] = (j < n && c < R) ? (float)T[(int64_t)pdofs[base + j] * R + c] : 0.f;
-  }
-  __syncthreads();
+  // uniform bases with 32-bit element offsets (the host keeps N R and sum(n) R below 2^31), so each
+  // load needs one offset register
   const float* A = inv + off;
+  float* D = delta + (int64_t)base * R;
   const int lr = lane & 15, lk = lane >> 4;
   const int ntiles = (n + 15) / 16;
-  for (int rt = wave; rt < ntiles; rt += NW) {
+
+  // loads are unconditional at clamped (in-bounds) addresses and masked afterwards by a multiply
+  // (a select lets the compiler sink each load into a branch of its own, one wait per load)
+  float a[16];
+  auto load_a = [&](int rt, int k0) {
+    const int row = rt * 16 + lr;
+    const int rowc = min(row, ld - 1);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int k = k0 + 4 * u + lk;
+      const float x = A[(uint32_t)(min(k, n - 1) * ld + rowc)];
+      a[u] = x * ((row < ld && k < n) ? 1.f : 0.f);  // finite entries: exact 0 or x
+    }
+  };
+  int rt = wave;
+  if (rt < ntiles) load_a(rt, 0);
+
+  int pd[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) pd[q] = lane + 64 * q < n ? pdofs[base + lane + 64 * q] : 0;
+  const int lc = min(lane, R - 1);
+  for (int j0 = wave; j0 < nk; j0 += 8 * NW) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u * NW;
+      const int jj = j < n ? j : 0;
+      int dof = pd[0];
+#pragma unroll
+      for (int t = 1; t < NW; ++t) dof = (jj >> 6) == t ? pd[t] : dof;
+      dof = __builtin_amdgcn_readlane(dof, jj & 63);
+      v[u] = T[(uint32_t)(dof * R + lc)];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] *= (j0 + u * NW < n && lane < R) ? 1.0 : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u * NW;
+      if (j < nk) Bs[bs_index(j, lane)] = (float)v[u];
+    }
+  }
+  __syncthreads();
+
+  for (; rt < ntiles; rt += NW) {
     floatx4_t acc[4];
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[ct] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
-    const int row = rt * 16 + lr;
-    const bool rok = row < ld;
-    for (int k0 = 0; k0 < nk; k0 += 32) {
-      float a[8];
+    for (int k0 = 0; k0 < nk; k0 += 64) {
+      if (k0 > 0) load_a(rt, k0);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = k0 + 4 * u + lk;
-        a[u] = (rok && k < n) ? A[(int64_t)k * ld + row] : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = k0 + 4 * u + lk;
+      for (int u = 0; u < 16; ++u) {
         if (k0 + 4 * u < nk) {
+          const int k = k0 + 4 * u + lk;
 #pragma unroll
           for (int ct = 0; ct < 4; ++ct) {
-            const float b = Bs[k * 64 + ct * 16 + lr];
+            const float b = Bs[bs_index(k, ct * 16 + lr)];
             acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b, acc[ct], 0, 0, 0);
           }
         }
       }
     }
+    if (rt + NW < ntiles) load_a(rt + NW, 0);
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
       const int c = ct * 16 + lr;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = rt * 16 + 4 * lk + i;
-        if (r < n && c < R) delta[(int64_t)(base + r) * R + c] = acc[ct][i];
+        if (r < n && c < R) D[(uint32_t)(r * R + c)] = acc[ct][i];
       }
     }
   }
@@ -171,8 +316,10 @@ void launch_patch_gemm(bool fp32, int count, int nmax, const int4* meta, const i
   if (fp32) {
     const int nk = (nmax + 3) / 4 * 4;
     const size_t lds = (size_t)nk * 64 * sizeof(float);
-    if (nmax > 64)
+    if (nmax > 128)
       patch_gemm_mfma_kernel<4><<<count, 256, lds, s>>>(meta, pdofs, (const float*)inv, T, R, nmax, (float*)delta);
+    else if (nmax > 64)
+      patch_gemm_mfma_kernel<2><<<count, 128, lds, s>>>(meta, pdofs, (const float*)inv, T, R, nmax, (float*)delta);
     else
       patch_gemm_mfma_kernel<1><<<count, 64, lds, s>>>(meta, pdofs, (const float*)inv, T, R, nmax, (float*)delta);
   } else {
@@ -199,8 +346,47 @@ __global__ void __launch_bounds__(256) scatter_multi_kernel(int N, int R, int Rp
   else X[o] += scale[d] * s;
 }
 
+// R > 32: one DoF per wave, made wave-uniform so that the slot list comes by scalar loads; the
+// slot rows of delta are read 8 at a time (the last batch padded with its final slot times zero;
+// delta is finite), summed in the same ascending order.
+template <typename TD, bool SET>
+__global__ void __launch_bounds__(256) scatter_wave_kernel(int N, int R, const int* __restrict__ dptr,
+                                                           const int* __restrict__ dslot,
+                                                           const TD* __restrict__ delta,
+                                                           const double* __restrict__ scale, double* __restrict__ X) {
+  const int d = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (d >= N) return;
+  const int c = threadIdx.x & 63;
+  const int cl = c < R ? c : R - 1;
+  const int q0 = __builtin_amdgcn_readfirstlane(dptr[d]), q1 = __builtin_amdgcn_readfirstlane(dptr[d + 1]);
+  double s = 0.0;
+  for (int q = q0; q < q1; q += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (double)delta[(int64_t)dslot[min(q + u, q1 - 1)] * R + cl];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u] * (q + u < q1 ? 1.0 : 0.0);
+  }
+  if (c >= R) return;
+  const int64_t o = (int64_t)d * R + c;
+  if (SET) X[o] = scale[d] * s;
+  else X[o] += scale[d] * s;
+}
+
 void launch_scatter_multi(bool fp32, bool set, int N, int R, const int* dptr, const int* dslot, const void* delta,
                           const double* scale, double* X, hipStream_t s) {
+  if (R > 32) {
+    const int grid = (N + 3) / 4;
+    if (grid == 0) return;
+    if (fp32) {
+      if (set) scatter_wave_kernel<float, true><<<grid, 256, 0, s>>>(N, R, dptr, dslot, (const float*)delta, scale, X);
+      else scatter_wave_kernel<float, false><<<grid, 256, 0, s>>>(N, R, dptr, dslot, (const float*)delta, scale, X);
+    } else {
+      if (set) scatter_wave_kernel<double, true><<<grid, 256, 0, s>>>(N, R, dptr, dslot, (const double*)delta, scale, X);
+      else scatter_wave_kernel<double, false><<<grid, 256, 0, s>>>(N, R, dptr, dslot, (const double*)delta, scale, X);
+    }
+    return;
+  }
   const int Rp = pow2_at_least(R);
   const int rpb = 256 / Rp;
   const int grid = (N + rpb - 1) / rpb;
@@ -214,21 +400,37 @@ void launch_scatter_multi(bool fp32, bool set, int N, int R, const int* dptr, co
 }
 
 // ============================================================================
-// Coarsest level: E = M Rv, M dense row-major N0 x N0; one block per row,
-// one lane per right-hand side, ascending j.
+// Coarsest level: E = M Rv, M dense row-major N0 x N0.  One 256-thread block
+// per row: wave w sums the columns j = w, w + 4, ... (8 in flight per lane,
+// ascending within the wave), lane = right-hand side; the four wave partials
+// are added in wave order.
 // ============================================================================
-__global__ void __launch_bounds__(64) dense_gemm_kernel(int N, int R, const double* __restrict__ M,
-                                                        const double* __restrict__ Rv, double* __restrict__ E) {
-  const int row = blockIdx.x, c = threadIdx.x;
-  if (c >= R) return;
+__global__ void __launch_bounds__(256) dense_gemm_kernel(int N, int R, const double* __restrict__ M,
+                                                         const double* __restrict__ Rv, double* __restrict__ E) {
+  __shared__ double part[4][64];
+  const int row = blockIdx.x, c = threadIdx.x & 63, w = threadIdx.x >> 6;
   const double* m = M + (int64_t)row * N;
+  const int cl = c < R ? c : R - 1;
   double acc = 0.0;
-  for (int j = 0; j < N; ++j) acc += m[j] * Rv[(int64_t)j * R + c];
-  E[(int64_t)row * R + c] = acc;
+  int j = w;
+  for (; j + 28 < N; j += 32) {
+    double mm[8], xx[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      mm[u] = m[j + 4 * u];
+      xx[u] = Rv[(int64_t)(j + 4 * u) * R + cl];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += mm[u] * xx[u];
+  }
+  for (; j < N; j += 4) acc += m[j] * Rv[(int64_t)j * R + cl];
+  part[w][c] = acc;
+  __syncthreads();
+  if (w == 0 && c < R) E[(int64_t)row * R + c] = (part[0][c] + part[1][c]) + (part[2][c] + part[3][c]);
 }
 
 void launch_dense_gemm(int N, int R, const double* M, const double* Rv, double* E, hipStream_t s) {
-  dense_gemm_kernel<<<N, 64, 0, s>>>(N, R, M, Rv, E);
+  dense_gemm_kernel<<<N, 256, 0, s>>>(N, R, M, Rv, E);
 }
 
 // ============================================================================
@@ -236,24 +438,40 @@ void launch_dense_gemm(int N, int R, const double* M, const double* Rv, double* 
 // chunk for every column (4 row lanes x 64 columns, fixed tree), then one
 // final pass sums the block partials in block order.
 // ============================================================================
-constexpr int kColBlocks = 64;
+constexpr int kDotGroup = 8;     // basis vectors per block of the column dot products
 
-__global__ void __launch_bounds__(256) dots_partial_kernel(int n, int R, const double* __restrict__ V, int64_t ldv,
-                                                           const double* __restrict__ W, double* __restrict__ partial) {
-  __shared__ double sh[256];
-  const int v = blockIdx.y, c = threadIdx.x & 63, rl = threadIdx.x >> 6;
-  const double* x = V + (int64_t)v * ldv;
+// Block (chunk b, group g): 4 row lanes x 64 columns; W is read once per row and multiplied with
+// up to 8 basis vectors v = 8 g + t.  Each lane sums rows i0 + rl, i0 + rl + 4, ... in order; the
+// four row lanes are combined in a fixed tree.
+__global__ void __launch_bounds__(256) dots_partial_kernel(int n, int R, int nv, const double* __restrict__ V,
+                                                           int64_t ldv, const double* __restrict__ W,
+                                                           double* __restrict__ partial) {
+  __shared__ double sh[kDotGroup][256];
+  const int c = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int v0 = blockIdx.y * kDotGroup;
   const int chunk = (n + kColBlocks - 1) / kColBlocks;
   const int i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
-  double acc = 0.0;
-  if (c < R)
-    for (int i = i0 + rl; i < i1; i += 4) acc += x[(int64_t)i * R + c] * W[(int64_t)i * R + c];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  if (rl == 0) {
-    const double s = (sh[c] + sh[64 + c]) + (sh[128 + c] + sh[192 + c]);
-    partial[((int64_t)v * kColBlocks + blockIdx.x) * 64 + c] = s;
+  const int cl = c < R ? c : R - 1;
+  double acc[kDotGroup];
+#pragma unroll
+  for (int t = 0; t < kDotGroup; ++t) acc[t] = 0.0;
+  for (int i = i0 + rl; i < i1; i += 4) {
+    const int64_t o = (int64_t)i * R + cl;
+    const double w = W[o];
+    double x[kDotGroup];
+#pragma unroll
+    for (int t = 0; t < kDotGroup; ++t) x[t] = V[(int64_t)min(v0 + t, nv - 1) * ldv + o];
+#pragma unroll
+    for (int t = 0; t < kDotGroup; ++t) acc[t] += x[t] * w;
   }
+#pragma unroll
+  for (int t = 0; t < kDotGroup; ++t) sh[t][threadIdx.x] = acc[t];
+  __syncthreads();
+  if (rl == 0 && c < R)
+    for (int t = 0; t < kDotGroup && v0 + t < nv; ++t) {
+      const double s = (sh[t][c] + sh[t][64 + c]) + (sh[t][128 + c] + sh[t][192 + c]);
+      partial[((int64_t)(v0 + t) * kColBlocks + blockIdx.x) * 64 + c] = s;
+    }
 }
 
 __global__ void __launch_bounds__(64) dots_final_kernel(int R, const double* __restrict__ partial,
@@ -267,11 +485,14 @@ __global__ void __launch_bounds__(64) dots_final_kernel(int R, const double* __r
 
 void launch_dots_cols(int n, int R, int nv, const double* V, int64_t ldv, const double* W, double* partial,
                       double* out, hipStream_t s) {
-  dots_partial_kernel<<<dim3(kColBlocks, nv), 256, 0, s>>>(n, R, V, ldv, W, partial);
+  dots_partial_kernel<<<dim3(kColBlocks, (nv + kDotGroup - 1) / kDotGroup), 256, 0, s>>>(n, R, nv, V, ldv, W,
+                                                                                         partial);
   dots_final_kernel<<<nv, 64, 0, s>>>(R, partial, out);
 }
 
-// W[i][c] += sign * sum_{v < nvc[c]} V_v[i][c] h[v][c]  (nvc == nullptr: nv for every column)
+// W[i][c] += sign * sum_{v < nvc[c]} V_v[i][c] h[v][c]  (nvc == nullptr: nv for every column).  The
+// basis vectors are loaded 8 at a time for every column up to nv (all finite), and terms with
+// v >= nvc[c] are multiplied by zero, so the loads carry no per-lane branch.
 __global__ void __launch_bounds__(256) axpy_cols_kernel(int n, int R, int Rp, int nv, const int* __restrict__ nvc,
                                                         double sign, const double* __restrict__ V, int64_t ldv,
                                                         const double* __restrict__ h, double* __restrict__ W) {
@@ -280,9 +501,21 @@ __global__ void __launch_bounds__(256) axpy_cols_kernel(int n, int R, int Rp, in
   const int c = threadIdx.x % Rp;
   if (i >= n || c >= R) return;
   const int m = nvc ? nvc[c] : nv;
+  const int64_t o = (int64_t)i * R + c;
   double s = 0.0;
-  for (int v = 0; v < m; ++v) s += V[(int64_t)v * ldv + (int64_t)i * R + c] * h[(int64_t)v * R + c];
-  W[(int64_t)i * R + c] += sign * s;
+  for (int v0 = 0; v0 < nv; v0 += 8) {
+    double x[8], hv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int v = min(v0 + t, nv - 1);
+      x[t] = V[(int64_t)v * ldv + o];
+      hv[t] = v0 + t < m ? h[(int64_t)v * R + c] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      if (v0 + t < nv) s += x[t] * hv[t];
+  }
+  W[o] += sign * s;
 }
 
 void launch_axpy_cols(int n, int R, int nv, const int* nvc, double sign, const double* V, int64_t ldv,

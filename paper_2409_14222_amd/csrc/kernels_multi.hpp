@@ -8,9 +8,10 @@
 
 namespace vk {
 
-// Y = A X (mode 0), Y = B - A X (mode 1), Y += A X (mode 2)
-void launch_spmm(int mode, int nrows, int R, const int* rowptr, const int* col, const double* val, const double* X,
-                 const double* B, double* Y, hipStream_t s);
+// Y = A X (mode 0), Y = B - A X (mode 1), Y += A X (mode 2); grp: the ngroups + 1 starts of the
+// runs of rows with identical column lists (at most 8 rows each, from row_groups)
+void launch_spmm(int mode, int nrows, int ngroups, const int* grp, int R, const int* rowptr, const int* col,
+                 const double* val, const double* X, const double* B, double* Y, hipStream_t s);
 // Delta_i = K_i^{-1} T[I_i, :] for `count` patches (meta as for the single-vector apply);
 // FP32 inverses run on the matrix cores (FP32 accumulation), FP64 inverses (n <= 128) on vector FMAs.
 // nmax: the largest patch among the `count` (sizes the LDS block).
@@ -19,7 +20,9 @@ void launch_patch_gemm(bool fp32, int count, int nmax, const int4* meta, const i
 void launch_scatter_multi(bool fp32, bool set, int N, int R, const int* dptr, const int* dslot, const void* delta,
                           const double* scale, double* X, hipStream_t s);
 void launch_dense_gemm(int N, int R, const double* M, const double* Rv, double* E, hipStream_t s);
-// out[v][c] = sum_i V_v[i][c] W[i][c], v < nv; partial holds nv * 64 * 64 doubles
+// row chunks of the column reductions (fixes their summation order)
+constexpr int kColBlocks = 256;
+// out[v][c] = sum_i V_v[i][c] W[i][c], v < nv; partial holds nv * kColBlocks * 64 doubles
 void launch_dots_cols(int n, int R, int nv, const double* V, int64_t ldv, const double* W, double* partial,
                       double* out, hipStream_t s);
 // W[i][c] += sign sum_{v < nvc[c] (or nv)} V_v[i][c] h[v][c]
@@ -27,7 +30,8 @@ void launch_axpy_cols(int n, int R, int nv, const int* nvc, double sign, const d
                       const double* h, double* W, hipStream_t s);
 // Y[i][c] = X[i][c] / sqrt(nn[c]), 0 where nn[c] <= 0
 void launch_div_sqrt_cols(int n, int R, const double* X, const double* nn, double* Y, hipStream_t s);
-// remove the constant pressure (rows p0..n) of the columns with mask[c] != 0; partial >= 64 * 64 + 64 doubles
+// remove the constant pressure (rows p0..n) of the columns with mask[c] != 0;
+// partial >= kColBlocks * 64 + 64 doubles
 void launch_project_cols(int n, int p0, int R, double zv, const int* mask, double* X, double* partial,
                          hipStream_t s);
 

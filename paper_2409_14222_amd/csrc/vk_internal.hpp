@@ -27,6 +27,9 @@ struct Csr {
 };
 
 Csr transpose(const Csr& a);
+// starts of the maximal runs (capped at `cap` rows) of consecutive rows with identical column lists,
+// followed by nrows: a many-right-hand-side product reads each input row once per run
+std::vector<int> row_groups(const Csr& a, int cap);
 
 // ---------------------------------------------------------------- FEM kernels (host_fem.cpp)
 // Collapsed Gauss-Legendre rule on the reference simplex with q points per
@@ -67,6 +70,8 @@ struct LevelHost {
   std::vector<Cell> cells;
   Csr K;
   Csr P, PT;                 // prolongation from level-1 (rows: this level) and its transpose
+  // runs of consecutive rows with identical column lists (at most 8 rows): starts, then the row count
+  std::vector<int> kgrp, pgrp, ptgrp;
   std::vector<double> b;     // right-hand side (finest level only)
   // patches (host_patches.cpp)
   std::vector<int> pptr, pdofs;   // patch i: pdofs[pptr[i] .. pptr[i+1])
