@@ -36,18 +36,20 @@ WORKLOADS = {
 }
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per finest-level apply measured with rocprofv3 FETCH_SIZE/WRITE_SIZE
-# (scaled by a plain-copy calibration), keyed by the kernel source they were
-# taken on; any change to the kernels invalidates them (reported as null).
-# Source: profiles/patch_apply_p4p3_64_fp64.md
+# HBM bytes per launch of the dominant kernel measured with rocprofv3
+# FETCH_SIZE/WRITE_SIZE (scaled by a plain-copy calibration), keyed by the
+# source file of that kernel (its hash) and the workload; any change to that
+# file invalidates them (reported as null).
+# Sources: profiles/patch_apply_p4p3_64_fp64.md, profiles/many_rhs_sv_p3dp2_64.md
 MEASURED_TRAFFIC = {
-    ("9553874308af0a27", "p4p3-64", "fp64"): 858.7e6,
+    ("kernels.hip", "72476104b32e3fb5", "p4p3-64", "fp64", 1): 858.6e6,
+    ("kernels_multi.hip", "eebd8d9c6d769573", "sv-p3dp2-64", "fp32", 64): 555.2e6,
 }
 
 
-def kernel_source_hash():
+def kernel_source_hash(name):
     import hashlib
-    path = os.path.join(ROOT, "paper_2409_14222_amd", "csrc", "kernels.hip")
+    path = os.path.join(ROOT, "paper_2409_14222_amd", "csrc", name)
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
@@ -280,6 +282,7 @@ def main():
     apply_bytes = info.sum_n2 * s + info.sum_n * 4 + info.sum_n * R * (8 + s)
     apply_flops = 2.0 * info.sum_n2 * R
     avg_s = kms / 1e3 / max(launches, 1)
+    src = "kernels.hip" if R == 1 else "kernels_multi.hip"
     achieved = apply_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
     out = {
         "metric": "Stokes solves/s to 1e-10 rel. residual",
@@ -305,7 +308,7 @@ def main():
         "tuning": tuning,
         "roofline": {"kernel": "patch_apply_kernel (finest level)", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": MEASURED_TRAFFIC.get((kernel_source_hash(), args.workload, args.store)),
+                     "traffic": MEASURED_TRAFFIC.get((src, kernel_source_hash(src), args.workload, args.store, R)),
                      "algorithmic_bytes_per_launch": apply_bytes, "avg_launch_us": avg_s * 1e6,
                      "launches": launches},
     }
