@@ -277,9 +277,12 @@ def main():
     solves_per_s = args.steps * R / elapsed
     its_mean = float(np.mean(its))
 
-    # dominant kernel: finest-level additive patch apply (a GEMM over R columns when R > 1)
+    # dominant kernel: finest-level additive patch apply (a GEMM over R columns when R > 1).  With
+    # one right-hand side the inverses are read from the symmetric tiled storage (the 8 x 8 tiles
+    # on and below the diagonal), with several from the full column-major storage (sum n^2)
     s = 4 if store == vk.VK_STORE_FP32 else 8
-    apply_bytes = info.sum_n2 * s + info.sum_n * 4 + info.sum_n * R * (8 + s)
+    inv_bytes = (info.inv_elems_tri if R == 1 else info.sum_n2) * s
+    apply_bytes = inv_bytes + info.sum_n * 4 + info.sum_n * R * (8 + s)
     apply_flops = 2.0 * info.sum_n2 * R
     avg_s = kms / 1e3 / max(launches, 1)
     src = "kernels.hip" if R == 1 else "kernels_multi.hip"

@@ -105,6 +105,9 @@ typedef struct vk_level_info {
   int64_t sum_n2;  /* sum of squared patch sizes */
   int max_n;       /* largest patch */
   int64_t p_nnz;   /* nonzeros of the prolongation from level-1 (0 on level 0) */
+  int64_t inv_elems_full; /* stored elements of the patch inverses, column-major (bound for > 1 RHS) */
+  int64_t inv_elems_tri;  /* stored elements in the symmetric tiled storage (bound for 1 RHS): the
+                             8 x 8 tiles on and below the diagonal, zero-padded */
 } vk_level_info;
 
 typedef struct vk_solve_opts {

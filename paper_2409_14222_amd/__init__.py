@@ -45,7 +45,7 @@ class vk_patch_opts(ctypes.Structure):
 class vk_level_info(ctypes.Structure):
     _fields_ = [("n", _c_int), ("n_free", _c_int), ("n_velocity", _c_int), ("nnz", ctypes.c_int64),
                 ("n_patches", _c_int), ("sum_n", ctypes.c_int64), ("sum_n2", ctypes.c_int64), ("max_n", _c_int),
-                ("p_nnz", ctypes.c_int64)]
+                ("p_nnz", ctypes.c_int64), ("inv_elems_full", ctypes.c_int64), ("inv_elems_tri", ctypes.c_int64)]
 
 
 class vk_tuning(ctypes.Structure):

@@ -74,10 +74,11 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.dslot = cv.take<int>(lh.dslot.size());
     d.order = cv.take<int>(lh.order.size());
     d.classes = cv.take<int>(lh.order.size());
+    d.tri = R == 1;
     d.inv_off = cv.take<int64_t>(lh.inv_off.size());
     d.meta = cv.take<int4>(lh.order.size());
     d.scale = cv.take<double>(lh.scale.size());
-    d.inv = cv.take<char>((size_t)lh.inv_elems * es);
+    d.inv = cv.take<char>((size_t)(d.tri ? lh.inv_elems_tri : lh.inv_elems) * es);
     d.delta = cv.take<char>(lh.pdofs.size() * es * R);
   }
   const int N = Hs.back().N;
@@ -136,9 +137,11 @@ void patch_apply(vk_hierarchy* h, int l, const double* t) {
     h->ev_free.pop_back();
     HIPCHECK(hipEventRecord(ev.first, h->stream));
   }
-  launch_patch_apply(h->fp32(), d.waves_large, d.nt_large != 0, d.n_large, d.meta, d.pdofs, d.inv, t, d.delta,
+  launch_patch_apply(h->fp32(), d.tri, d.max_n, d.waves_large, d.nt_large != 0, d.n_large, d.meta, d.pdofs, d.inv, t,
+                     d.delta,
                      h->stream);
-  launch_patch_apply(h->fp32(), d.waves_small, d.nt_small != 0, d.J - d.n_large, d.meta + d.n_large, d.pdofs, d.inv,
+  launch_patch_apply(h->fp32(), d.tri, std::min(d.max_n, 64), d.waves_small, d.nt_small != 0, d.J - d.n_large,
+                     d.meta + d.n_large, d.pdofs, d.inv,
                      t, d.delta, h->stream);
   check_launch();
   if (timed) {
@@ -398,7 +401,8 @@ void autotune(vk_hierarchy* h, int reps) {
       for (int nt = 1; nt >= 0; --nt)
         for (int w : waves) {
           const float t = time_ms(s, reps, [&] {
-            launch_patch_apply(h->fp32(), w, nt != 0, count, d.meta + first, d.pdofs, d.inv, d.b, d.delta, s);
+            launch_patch_apply(h->fp32(), d.tri, part == 0 ? d.max_n : std::min(d.max_n, 64), w, nt != 0, count,
+                               d.meta + first, d.pdofs, d.inv, d.b, d.delta, s);
           });
           if (t < bt * 0.98f) { bt = t; best = w; best_nt = nt; }
         }
@@ -435,9 +439,17 @@ void smooth_multi(vk_hierarchy* h, int l, int R, const double* B, double* X, int
       h->ev_free.pop_back();
       HIPCHECK(hipEventRecord(ev.first, s));
     }
-    launch_patch_gemm(h->fp32(), d.n_large, d.max_n, d.meta, d.pdofs, d.inv, T, R, d.delta, s);
-    launch_patch_gemm(h->fp32(), d.J - d.n_large, std::min(d.max_n, 64), d.meta + d.n_large, d.pdofs, d.inv, T, R,
-                      d.delta, s);
+    if (d.tri) {
+      // bound for one right-hand side: [N][1] multivectors are plain vectors
+      launch_patch_apply(h->fp32(), true, d.max_n, d.waves_large, d.nt_large != 0, d.n_large, d.meta, d.pdofs, d.inv,
+                         T, d.delta, s);
+      launch_patch_apply(h->fp32(), true, std::min(d.max_n, 64), d.waves_small, d.nt_small != 0, d.J - d.n_large,
+                         d.meta + d.n_large, d.pdofs, d.inv, T, d.delta, s);
+    } else {
+      launch_patch_gemm(h->fp32(), d.n_large, d.max_n, d.meta, d.pdofs, d.inv, T, R, d.delta, s);
+      launch_patch_gemm(h->fp32(), d.J - d.n_large, std::min(d.max_n, 64), d.meta + d.n_large, d.pdofs, d.inv, T, R,
+                        d.delta, s);
+    }
     if (timed) {
       HIPCHECK(hipEventRecord(ev.second, s));
       h->ev_pending.push_back(ev);
@@ -781,12 +793,13 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_r
       up(d.dslot, L.dslot, s);
       up(d.order, L.order, s);
       up(d.classes, h->class_lists[l], s);
-      up(d.inv_off, L.inv_off, s);
+      const std::vector<int64_t>& ioff = d.tri ? L.inv_off_tri : L.inv_off;
+      up(d.inv_off, ioff, s);
       {
         std::vector<int4> meta(L.order.size());
         for (size_t i = 0; i < L.order.size(); ++i) {
           const int p = L.order[i];
-          const int64_t o = L.inv_off[p];
+          const int64_t o = ioff[p];
           meta[i] = make_int4(L.pptr[p], L.pptr[p + 1] - L.pptr[p], (int)(uint32_t)(o & 0xffffffffLL),
                               (int)(o >> 32));
         }
@@ -819,10 +832,14 @@ vk_status vk_patches_setup(vk_hierarchy* h) {
       std::vector<int> init(1, INT_MAX);
       HIPCHECK(hipMemcpyAsync(h->singular, init.data(), sizeof(int), hipMemcpyHostToDevice, s));
       int first = 0;
+      const LevelHost& lh = h->H[l];
+      // tile padding beyond n must read as zero (the register-resident inversion writes only n x n)
+      HIPCHECK(hipMemsetAsync(d.inv, 0,
+                              (size_t)(d.tri ? lh.inv_elems_tri : lh.inv_elems) * (h->fp32() ? 4 : 8), s));
       const int lim[4] = {32, 64, 128, 224};
       for (int c = 0; c < 4; ++c) {
-        launch_gather_invert(lim[c], h->fp32(), d.class_count[c], d.classes + first, d.pptr, d.pdofs, d.rowptr,
-                             d.col, d.val, d.inv_off, d.inv, h->singular, s);
+        launch_gather_invert(lim[c], h->fp32(), d.tri, d.class_count[c], d.classes + first, d.pptr, d.pdofs,
+                             d.rowptr, d.col, d.val, d.inv_off, d.inv, h->singular, s);
         check_launch();
         first += d.class_count[c];
       }
@@ -851,6 +868,8 @@ vk_status vk_level_info_get(const vk_hierarchy* h, int level, vk_level_info* inf
     info->sum_n2 = level == 0 ? 0 : L.sum_n2;
     info->max_n = level == 0 ? 0 : L.max_n;
     info->p_nnz = level == 0 ? 0 : L.P.nnz();
+    info->inv_elems_full = level == 0 ? 0 : L.inv_elems;
+    info->inv_elems_tri = level == 0 ? 0 : L.inv_elems_tri;
     return VK_OK;
   });
 }
@@ -950,7 +969,9 @@ vk_status vk_patch_inverse(vk_hierarchy* h, int level, int patch, double* d_out)
     const LevelHost& L = h->H[level];
     require(patch >= 0 && patch + 1 < (int)L.pptr.size(), VK_EINVAL, "patch out of range");
     const int n = L.pptr[patch + 1] - L.pptr[patch];
-    launch_copy_inverse(h->fp32(), n, h->D[level].inv, L.inv_off[patch], d_out, h->stream);
+    const DevLevel& dl = h->D[level];
+    launch_copy_inverse(h->fp32(), dl.tri, n, dl.inv, dl.tri ? L.inv_off_tri[patch] : L.inv_off[patch], d_out,
+                        h->stream);
     check_launch();
     return VK_OK;
   });

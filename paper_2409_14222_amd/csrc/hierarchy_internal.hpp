@@ -43,6 +43,7 @@ struct DevLevel {
   int nt_large = 1, nt_small = 1;  // non-temporal (streaming) loads of the inverses
   int max_n = 0;
   int4* meta = nullptr;            // per patch in processing order: {first slot, n, inverse offset}
+  bool tri = false;                // inverses in symmetric tiled storage (bound for one right-hand side)
 };
 
 // Sequential carving of one caller buffer into 256-byte aligned pieces.  Run

@@ -229,6 +229,16 @@ void finalize_patches(LevelHost& L, std::vector<std::vector<int>>& patches, doub
     off = (off + 3) / 4 * 4;
   }
   L.inv_elems = off;
+  // symmetric tiled storage (one right-hand side): lower-triangular 8x8 tiles, same order
+  L.inv_off_tri.assign(J, 0);
+  off = 0;
+  for (int t = 0; t < J; ++t) {
+    const int p = L.order[t];
+    const int nb = (L.pptr[p + 1] - L.pptr[p] + 7) / 8;
+    L.inv_off_tri[p] = off;
+    off += (int64_t)nb * (nb + 1) / 2 * 64;
+  }
+  L.inv_elems_tri = off;
 }
 
 }  // namespace vk

@@ -4,6 +4,8 @@
 // point atomics), so results are bitwise reproducible run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <climits>
 #include <cstdint>
 
@@ -120,6 +122,19 @@ __device__ inline void gather_tile(int n, const int* __restrict__ Ii, const int*
 // (ties -> lowest row), found by a wave-wide xor butterfly.  Row swaps are
 // undone as column swaps at the end.
 // ============================================================================
+// Symmetric tiled storage of a patch inverse (bound for one right-hand side):
+// the 8 x 8 tiles (I, J) with I >= J, tile I (I + 1) / 2 + J, and inside a tile
+// element (row k, column c) at ((k / E) * 8 + c) * E + k % E, E = 16 / sizeof
+// (2 doubles or 4 floats): lane c of a tile loads its column in 16-byte
+// pieces while one load instruction across 8 lanes reads 128 contiguous bytes.
+// Padding rows and columns (beyond n) hold zeros.
+template <typename TS>
+__device__ __forceinline__ int64_t tri_pos(int i, int j) {
+  constexpr int E = 16 / sizeof(TS);
+  const int I = i >> 3, J = j >> 3, k = i & 7, c = j & 7;
+  return ((int64_t)(I * (I + 1) / 2 + J) << 6) + ((k / E) * 8 + c) * E + k % E;
+}
+
 template <int NMAX, typename TS>
 __global__ void __launch_bounds__(256) gather_invert_kernel(const int* __restrict__ list, const int* __restrict__ pptr,
                                                             const int* __restrict__ pdofs,
@@ -127,7 +142,7 @@ __global__ void __launch_bounds__(256) gather_invert_kernel(const int* __restric
                                                             const int* __restrict__ col,
                                                             const double* __restrict__ val,
                                                             const int64_t* __restrict__ inv_off, TS* __restrict__ inv,
-                                                            int* __restrict__ singular) {
+                                                            int* __restrict__ singular, bool tri) {
   __shared__ double T[NMAX * NMAX];
   __shared__ int Ii[NMAX];
   __shared__ double colk[NMAX];
@@ -210,9 +225,17 @@ __global__ void __launch_bounds__(256) gather_invert_kernel(const int* __restric
       }
     __syncthreads();
   }
+  TS* out = inv + inv_off[p];
+  if (tri) {
+    const int m = (n + 7) & ~7;
+    for (int e = tid; e < m * m; e += 256) {
+      const int jj = e / m, ii = e - jj * m;
+      if ((ii >> 3) >= (jj >> 3)) out[tri_pos<TS>(ii, jj)] = (ii < n && jj < n) ? (TS)T[jj * n + ii] : (TS)0;
+    }
+    return;
+  }
   constexpr int RPL = 16 / sizeof(TS);
   const int ld = (n + RPL - 1) / RPL * RPL;
-  TS* out = inv + inv_off[p];
   for (int e = tid; e < ld * n; e += 256) {
     const int jj = e / ld, ii = e - jj * ld;
     out[e] = ii < n ? (TS)T[jj * n + ii] : (TS)0;
@@ -236,7 +259,8 @@ __global__ void __launch_bounds__(1024) gather_invert_big_kernel(const int* __re
                                                                 const int* __restrict__ col,
                                                                 const double* __restrict__ val,
                                                                 const int64_t* __restrict__ inv_off,
-                                                                TS* __restrict__ inv, int* __restrict__ singular) {
+                                                                TS* __restrict__ inv, int* __restrict__ singular,
+                                                                bool tri) {
   constexpr int TX = 32, TY = 32, NX = 7, NY = 7, T = 224, NT = 1024;
   __shared__ double slab[TX * T];
   __shared__ int Ii[T];
@@ -415,36 +439,44 @@ __global__ void __launch_bounds__(1024) gather_invert_big_kernel(const int* __re
 #pragma unroll
     for (int x = 0; x < NX; ++x) {
       const int i = ti + TX * x;
-      if (i < ld) out[(int64_t)j * ld + i] = (TS)a[x][y];
+      if (tri) {
+        // padding of the stored tiles was zeroed before the launch
+        if (i < n && (i >> 3) >= (j >> 3)) out[tri_pos<TS>(i, j)] = (TS)a[x][y];
+      } else if (i < ld) {
+        out[(int64_t)j * ld + i] = (TS)a[x][y];
+      }
     }
   }
 }
 
 template <int NMAX>
-static void gather_invert_dispatch(bool fp32, int count, const int* list, const int* pptr, const int* pdofs,
-                                   const int* rowptr, const int* col, const double* val, const int64_t* inv_off,
-                                   void* inv, int* singular, hipStream_t s) {
+static void gather_invert_dispatch(bool fp32, bool tri, int count, const int* list, const int* pptr,
+                                   const int* pdofs, const int* rowptr, const int* col, const double* val,
+                                   const int64_t* inv_off, void* inv, int* singular, hipStream_t s) {
   if (fp32)
     gather_invert_kernel<NMAX, float><<<count, 256, 0, s>>>(list, pptr, pdofs, rowptr, col, val, inv_off,
-                                                            (float*)inv, singular);
+                                                            (float*)inv, singular, tri);
   else
     gather_invert_kernel<NMAX, double><<<count, 256, 0, s>>>(list, pptr, pdofs, rowptr, col, val, inv_off,
-                                                             (double*)inv, singular);
+                                                             (double*)inv, singular, tri);
 }
 
-void launch_gather_invert(int nmax, bool fp32, int count, const int* list, const int* pptr, const int* pdofs,
-                          const int* rowptr, const int* col, const double* val, const int64_t* inv_off, void* inv,
-                          int* singular, hipStream_t s) {
+void launch_gather_invert(int nmax, bool fp32, bool tri, int count, const int* list, const int* pptr,
+                          const int* pdofs, const int* rowptr, const int* col, const double* val,
+                          const int64_t* inv_off, void* inv, int* singular, hipStream_t s) {
   if (count <= 0) return;
-  if (nmax <= 32) gather_invert_dispatch<32>(fp32, count, list, pptr, pdofs, rowptr, col, val, inv_off, inv, singular, s);
-  else if (nmax <= 64) gather_invert_dispatch<64>(fp32, count, list, pptr, pdofs, rowptr, col, val, inv_off, inv, singular, s);
-  else if (nmax <= 128) gather_invert_dispatch<128>(fp32, count, list, pptr, pdofs, rowptr, col, val, inv_off, inv, singular, s);
+  if (nmax <= 32)
+    gather_invert_dispatch<32>(fp32, tri, count, list, pptr, pdofs, rowptr, col, val, inv_off, inv, singular, s);
+  else if (nmax <= 64)
+    gather_invert_dispatch<64>(fp32, tri, count, list, pptr, pdofs, rowptr, col, val, inv_off, inv, singular, s);
+  else if (nmax <= 128)
+    gather_invert_dispatch<128>(fp32, tri, count, list, pptr, pdofs, rowptr, col, val, inv_off, inv, singular, s);
   else if (fp32)
     gather_invert_big_kernel<float><<<count, 1024, 0, s>>>(list, pptr, pdofs, rowptr, col, val, inv_off, (float*)inv,
-                                                          singular);
+                                                          singular, tri);
   else
     gather_invert_big_kernel<double><<<count, 1024, 0, s>>>(list, pptr, pdofs, rowptr, col, val, inv_off,
-                                                           (double*)inv, singular);
+                                                           (double*)inv, singular, tri);
 }
 
 template <int NMAX>
@@ -499,19 +531,21 @@ void launch_gather_dense(int nmax, int first, int count, const int* pptr, const 
 }
 
 template <typename TS>
-__global__ void copy_inverse_kernel(int n, const TS* __restrict__ inv, int64_t off, double* __restrict__ out) {
+__global__ void copy_inverse_kernel(int n, const TS* __restrict__ inv, int64_t off, double* __restrict__ out,
+                                    bool tri) {
   constexpr int RPL = 16 / sizeof(TS);
   const int ld = (n + RPL - 1) / RPL * RPL;
   for (int e = blockIdx.x * 256 + threadIdx.x; e < n * n; e += gridDim.x * 256) {
     const int j = e / n, i = e - j * n;
-    out[e] = (double)inv[off + (int64_t)j * ld + i];
+    if (tri) out[e] = (double)inv[off + ((i >> 3) >= (j >> 3) ? tri_pos<TS>(i, j) : tri_pos<TS>(j, i))];
+    else out[e] = (double)inv[off + (int64_t)j * ld + i];
   }
 }
 
-void launch_copy_inverse(bool fp32, int n, const void* inv, int64_t off, double* out, hipStream_t s) {
+void launch_copy_inverse(bool fp32, bool tri, int n, const void* inv, int64_t off, double* out, hipStream_t s) {
   const int grid = (n * n + 255) / 256;
-  if (fp32) copy_inverse_kernel<float><<<grid, 256, 0, s>>>(n, (const float*)inv, off, out);
-  else copy_inverse_kernel<double><<<grid, 256, 0, s>>>(n, (const double*)inv, off, out);
+  if (fp32) copy_inverse_kernel<float><<<grid, 256, 0, s>>>(n, (const float*)inv, off, out, tri);
+  else copy_inverse_kernel<double><<<grid, 256, 0, s>>>(n, (const double*)inv, off, out, tri);
 }
 
 // ============================================================================
@@ -652,6 +686,128 @@ __global__ void __launch_bounds__(64 * W) patch_apply_kernel(const int4* __restr
   }
 }
 
+// Symmetric tiled apply (storage described at tri_pos): y = S x with S the
+// symmetric inverse, from the tiles on and below the diagonal only.  Tile
+// (I, J) adds S_IJ x_J to rows 8 I.. and, when I > J, S_IJ^T x_I to rows 8 J...
+// Eight lanes take one tile, lane c its column c (8 rows, 16-byte loads); a
+// wave takes 8 tiles per step and keeps 4 steps of loads in flight.  Inside a
+// tile the row sums combine the 8 columns by a fixed transposing xor tree (lane
+// c ends with row c), the column sums are lane-local in row order.  Every tile
+// writes its partial vectors to Q[I][J][.] (and Q[J][I][.]); row i then sums
+// Q[I][0..nb)[i % 8] in ascending J.  Which wave takes which tile changes
+// nothing, so the result depends on neither waves nor the cache policy.
+template <typename TS, int W, bool NT>
+__global__ void __launch_bounds__(64 * W) patch_apply_tri_kernel(const int4* __restrict__ meta,
+                                                                 const int* __restrict__ pdofs,
+                                                                 const TS* __restrict__ inv,
+                                                                 const double* __restrict__ t,
+                                                                 TS* __restrict__ delta) {
+  constexpr int E = 16 / sizeof(TS);  // rows per 16-byte load
+  constexpr int NV = 8 / E;           // loads per tile column
+  constexpr int U = 4;                // tile steps in flight
+  constexpr int NTH = 64 * W;
+  using V = typename vec16<TS>::type;
+  extern __shared__ char smem[];
+  const int4 m4 = meta[blockIdx.x];
+  const int base = m4.x, n = m4.y;
+  const int64_t off = (int64_t)(uint32_t)m4.z | ((int64_t)m4.w << 32);
+  if (n > 224 || n <= 0) return;  // the launch sizes LDS for every n of the launch; never taken
+  const int nb = (n + 7) >> 3;
+  const int T = nb * (nb + 1) / 2;
+  TS* xs = (TS*)smem;   // 8 nb gathered residual entries (zero padding)
+  TS* Q = xs + 8 * nb;  // nb x nb x 8 partial vectors
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int ts = lane >> 3, c = lane & 7;
+  const TS* A = inv + off;
+  const int t0 = wave * 8 + ts;
+  const int nsteps = T > wave * 8 ? (T - wave * 8 + 8 * W - 1) / (8 * W) : 0;  // wave-uniform
+  V a[U][NV];
+  auto load_step = [&](int s, V* dst) {
+    const int tt = min(t0 + s * 8 * W, T - 1);
+    const TS* tp = A + ((int64_t)tt << 6) + c * E;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dst[v] = load16<TS, NT>(tp + v * 8 * E);
+  };
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (u < nsteps) load_step(u, a[u]);
+  for (int j = tid; j < 8 * nb; j += NTH) xs[j] = j < n ? (TS)t[pdofs[base + j]] : (TS)0;
+  __syncthreads();
+  for (int s0 = 0; s0 < nsteps; s0 += U) {
+    if (s0 > 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (s0 + u < nsteps) load_step(s0 + u, a[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (s0 + u >= nsteps) break;
+      const int tt = t0 + (s0 + u) * 8 * W;
+      const int tc = min(tt, T - 1);  // lanes past the last tile repeat it and write nothing
+      int I = (int)((sqrtf(8.f * (float)tc + 1.f) - 1.f) * 0.5f);
+      while ((I + 1) * (I + 2) / 2 <= tc) ++I;
+      while (I * (I + 1) / 2 > tc) --I;
+      const int J = tc - I * (I + 1) / 2;
+      TS col[8];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < E; ++e) col[v * E + e] = a[u][v][e];
+      // row part: p_k = S[k][c] x_J[c], summed over the 8 columns (lanes)
+      const TS xj = xs[8 * J + c];
+      TS p[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) p[k] = col[k] * xj;
+      TS q4[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {  // xor 4: keep rows 4 (c & 4) .. + 3, send the other half
+        const TS keep = (c & 4) ? p[4 + k] : p[k];
+        const TS send = (c & 4) ? p[k] : p[4 + k];
+        q4[k] = keep + __shfl_xor(send, 4);
+      }
+      TS q2[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {  // xor 2: keep rows 4 (c & 4) + 2 (c & 2) / 2 ..
+        const TS keep = (c & 2) ? q4[2 + k] : q4[k];
+        const TS send = (c & 2) ? q4[k] : q4[2 + k];
+        q2[k] = keep + __shfl_xor(send, 2);
+      }
+      const TS keep = (c & 1) ? q2[1] : q2[0];
+      const TS send = (c & 1) ? q2[0] : q2[1];
+      const TS rowsum = keep + __shfl_xor(send, 1);  // row c of the tile
+      // column part: sum_k S[k][c] x_I[k] in row order
+      TS colsum = (TS)0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) colsum += col[k] * xs[8 * I + k];
+      if (tt < T) {
+        Q[(I * nb + J) * 8 + c] = rowsum;
+        if (I > J) Q[(J * nb + I) * 8 + c] = colsum;
+      }
+    }
+  }
+  __syncthreads();
+  TS* dout = delta + base;
+  for (int i = tid; i < n; i += NTH) {
+    const TS* q = Q + (i >> 3) * nb * 8 + (i & 7);
+    TS y = q[0];
+    for (int J = 1; J < nb; ++J) y += q[J * 8];
+    dout[i] = y;
+  }
+}
+
+template <typename TS, bool NT>
+static void apply_tri_dispatch(int waves, int nmax, int count, const int4* meta, const int* pdofs, const TS* inv,
+                               const double* t, TS* delta, hipStream_t s) {
+  if (count <= 0) return;
+  const int nb = (std::min(nmax, 224) + 7) / 8;
+  const size_t lds = (size_t)(8 * nb + 8 * nb * nb) * sizeof(TS);
+  switch (waves) {
+    case 1: patch_apply_tri_kernel<TS, 1, NT><<<count, 64, lds, s>>>(meta, pdofs, inv, t, delta); break;
+    case 2: patch_apply_tri_kernel<TS, 2, NT><<<count, 128, lds, s>>>(meta, pdofs, inv, t, delta); break;
+    default: patch_apply_tri_kernel<TS, 4, NT><<<count, 256, lds, s>>>(meta, pdofs, inv, t, delta); break;
+  }
+}
+
 template <typename TS, bool NT>
 static void apply_dispatch(int waves, int count, const int4* meta, const int* pdofs, const TS* inv, const double* t,
                            TS* delta, hipStream_t s) {
@@ -663,8 +819,18 @@ static void apply_dispatch(int waves, int count, const int4* meta, const int* pd
   }
 }
 
-void launch_patch_apply(bool fp32, int waves, bool nontemporal, int count, const int4* meta, const int* pdofs,
-                        const void* inv, const double* t, void* delta, hipStream_t s) {
+void launch_patch_apply(bool fp32, bool tri, int nmax, int waves, bool nontemporal, int count, const int4* meta,
+                        const int* pdofs, const void* inv, const double* t, void* delta, hipStream_t s) {
+  if (tri) {
+    if (fp32) {
+      if (nontemporal) apply_tri_dispatch<float, true>(waves, nmax, count, meta, pdofs, (const float*)inv, t, (float*)delta, s);
+      else apply_tri_dispatch<float, false>(waves, nmax, count, meta, pdofs, (const float*)inv, t, (float*)delta, s);
+    } else {
+      if (nontemporal) apply_tri_dispatch<double, true>(waves, nmax, count, meta, pdofs, (const double*)inv, t, (double*)delta, s);
+      else apply_tri_dispatch<double, false>(waves, nmax, count, meta, pdofs, (const double*)inv, t, (double*)delta, s);
+    }
+    return;
+  }
   if (fp32) {
     if (nontemporal) apply_dispatch<float, true>(waves, count, meta, pdofs, (const float*)inv, t, (float*)delta, s);
     else apply_dispatch<float, false>(waves, count, meta, pdofs, (const float*)inv, t, (float*)delta, s);

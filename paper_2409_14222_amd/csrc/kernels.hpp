@@ -14,27 +14,30 @@ void launch_csr(int mode, int nrows, int lanes, const int* rowptr, const int* co
 int csr_default_lanes(double mean_row);
 
 // Matrix-full patch setup: gather K_i = K[I_i, I_i] into LDS, invert it by
-// Gauss-Jordan with partial pivoting (FP64), store the inverse column-major
-// (leading dimension rounded to 2 doubles / 4 floats) as double or float.
-// `list` holds `count` patch ids whose size is <= nmax (32, 64, 128 or 224).
-// `singular` receives the smallest patch id with a zero pivot (initialise to INT_MAX).
-void launch_gather_invert(int nmax, bool fp32, int count, const int* list, const int* pptr, const int* pdofs,
-                          const int* rowptr, const int* col, const double* val, const int64_t* inv_off, void* inv,
-                          int* singular, hipStream_t s);
+// Gauss-Jordan with partial pivoting (FP64), store the inverse as double or
+// float: column-major (leading dimension rounded to 2 doubles / 4 floats), or
+// with `tri` the symmetric tiled storage (the 8 x 8 tiles on and below the
+// diagonal; the padding must have been zeroed).  `list` holds `count` patch ids
+// whose size is <= nmax (32, 64, 128 or 224).  `singular` receives the smallest
+// patch id with a zero pivot (initialise to INT_MAX).
+void launch_gather_invert(int nmax, bool fp32, bool tri, int count, const int* list, const int* pptr,
+                          const int* pdofs, const int* rowptr, const int* col, const double* val,
+                          const int64_t* inv_off, void* inv, int* singular, hipStream_t s);
 
 // Dense K_i tiles (n_i x n_i, column-major, packed) of patches first..first+count-1.
 void launch_gather_dense(int nmax, int first, int count, const int* pptr, const int* pdofs, const int* rowptr,
                          const int* col, const double* val, const int64_t* out_off, double* out, hipStream_t s);
 
-// Copy one stored inverse (double or float, padded) to a dense n x n double array.
-void launch_copy_inverse(bool fp32, int n, const void* inv, int64_t off, double* out, hipStream_t s);
+// Copy one stored inverse (double or float, padded or tiled) to a dense n x n double array.
+void launch_copy_inverse(bool fp32, bool tri, int n, const void* inv, int64_t off, double* out, hipStream_t s);
 
-// delta_i = K_i^{-1} t[I_i] for `count` patches described by meta[0..count)
-// ({first slot, n, inverse offset low, high}) with `waves` (1, 2 or 4)
-// wavefronts per patch; `nontemporal` streams the inverses past the caches.
-// Results depend on neither.
-void launch_patch_apply(bool fp32, int waves, bool nontemporal, int count, const int4* meta, const int* pdofs,
-                        const void* inv, const double* t, void* delta, hipStream_t s);
+// delta_i = K_i^{-1} t[I_i] for `count` patches (n_i <= nmax) described by
+// meta[0..count) ({first slot, n, inverse offset low, high}), from column-major
+// or (`tri`) symmetric tiled inverses, with `waves` (1, 2 or 4) wavefronts per
+// patch; `nontemporal` streams the inverses past the caches.  Results depend on
+// neither waves nor nontemporal.
+void launch_patch_apply(bool fp32, bool tri, int nmax, int waves, bool nontemporal, int count, const int4* meta,
+                        const int* pdofs, const void* inv, const double* t, void* delta, hipStream_t s);
 
 // x[d] += scale[d] * sum_{slots of d, ascending patch id} delta[slot]
 void launch_scatter(bool fp32, int N, const int* dptr, const int* dslot, const void* delta, const double* scale,

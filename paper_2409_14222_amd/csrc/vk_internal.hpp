@@ -80,6 +80,10 @@ struct LevelHost {
   std::vector<int> order;         // patch processing order (largest first)
   std::vector<int64_t> inv_off;   // element offset of each patch inverse (indexed by patch id)
   int64_t inv_elems = 0;
+  // the same for the symmetric tiled storage: the 8x8 tiles (I, J), I >= J, of the inverse,
+  // tile I (I + 1) / 2 + J, each column-major (64 elements)
+  std::vector<int64_t> inv_off_tri;
+  int64_t inv_elems_tri = 0;
   int max_n = 0;
   int64_t sum_n2 = 0;
 
