@@ -686,13 +686,28 @@ __global__ void __launch_bounds__(64 * W) patch_apply_kernel(const int4* __restr
   }
 }
 
+
+// Exchange with a partner lane through the DPP lane crossbar (a VALU move): CTRL 0xB1
+// (quad_perm [1,0,3,2]: lane xor 1), 0x4E (quad_perm [2,3,0,1]: lane xor 2), 0x141 (half-row
+// mirror: lane c <-> 7 - c within each group of 8 lanes).
+template <int CTRL>
+__device__ __forceinline__ double dpp_x(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_x(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
 // Symmetric tiled apply (storage described at tri_pos): y = S x with S the
 // symmetric inverse, from the tiles on and below the diagonal only.  Tile
 // (I, J) adds S_IJ x_J to rows 8 I.. and, when I > J, S_IJ^T x_I to rows 8 J...
 // Eight lanes take one tile, lane c its column c (8 rows, 16-byte loads); a
-// wave takes 8 tiles per step and keeps 4 steps of loads in flight.  Inside a
-// tile the row sums combine the 8 columns by a fixed transposing xor tree (lane
-// c ends with row c), the column sums are lane-local in row order.  Every tile
+// wave takes 8 tiles per step and keeps 2 steps of loads in flight.  Inside a
+// tile the row sums combine the 8 columns by a fixed transposing tree (partners
+// 7 - c, then c xor 2, then c xor 1; lane c ends with row c), the column sums are
+// lane-local in row order.  Every tile
 // writes its partial vectors to Q[I][J][.] (and Q[J][I][.]); row i then sums
 // Q[I][0..nb)[i % 8] in ascending J.  Which wave takes which tile changes
 // nothing, so the result depends on neither waves nor the cache policy.
@@ -704,7 +719,7 @@ __global__ void __launch_bounds__(64 * W) patch_apply_tri_kernel(const int4* __r
                                                                  TS* __restrict__ delta) {
   constexpr int E = 16 / sizeof(TS);  // rows per 16-byte load
   constexpr int NV = 8 / E;           // loads per tile column
-  constexpr int U = 4;                // tile steps in flight
+  constexpr int U = 2;                // tile steps in flight (more costs occupancy)
   constexpr int NTH = 64 * W;
   using V = typename vec16<TS>::type;
   extern __shared__ char smem[];
@@ -760,21 +775,21 @@ __global__ void __launch_bounds__(64 * W) patch_apply_tri_kernel(const int4* __r
       for (int k = 0; k < 8; ++k) p[k] = col[k] * xj;
       TS q4[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {  // xor 4: keep rows 4 (c & 4) .. + 3, send the other half
+      for (int k = 0; k < 4; ++k) {  // keep rows 4 (c & 4) .. + 3, take the same rows of lane 7 - c
         const TS keep = (c & 4) ? p[4 + k] : p[k];
         const TS send = (c & 4) ? p[k] : p[4 + k];
-        q4[k] = keep + __shfl_xor(send, 4);
+        q4[k] = keep + dpp_x<0x141>(send);  // half-row mirror: lane c <-> 7 - c
       }
       TS q2[2];
 #pragma unroll
       for (int k = 0; k < 2; ++k) {  // xor 2: keep rows 4 (c & 4) + 2 (c & 2) / 2 ..
         const TS keep = (c & 2) ? q4[2 + k] : q4[k];
         const TS send = (c & 2) ? q4[k] : q4[2 + k];
-        q2[k] = keep + __shfl_xor(send, 2);
+        q2[k] = keep + dpp_x<0x4E>(send);  // quad_perm [2,3,0,1]: xor 2
       }
       const TS keep = (c & 1) ? q2[1] : q2[0];
       const TS send = (c & 1) ? q2[0] : q2[1];
-      const TS rowsum = keep + __shfl_xor(send, 1);  // row c of the tile
+      const TS rowsum = keep + dpp_x<0xB1>(send);  // quad_perm [1,0,3,2]: xor 1; row c of the tile
       // column part: sum_k S[k][c] x_I[k] in row order
       TS colsum = (TS)0;
 #pragma unroll
