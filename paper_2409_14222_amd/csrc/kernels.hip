@@ -17,7 +17,8 @@ namespace vk {
 // CSR products: y = A x, y = b - A x, y += A x.  A group of LANES lanes owns
 // one row.  The summation order is canonical and independent of LANES: the
 // row's entries are dealt to 64 virtual positions p = (q - rowstart) mod 64,
-// each position accumulates its entries in ascending order, and the 64
+// each position accumulates its entries in ascending order (a position past the
+// row's end in the last chunk adds an exact zero), and the 64
 // partial sums are combined by the xor tree with offsets 32, 16, ..., 1.  A
 // lane holds 64/LANES positions, performs the tree levels with offsets
 // >= LANES in registers and the rest with cross-lane shuffles, so every
@@ -36,12 +37,22 @@ __global__ void __launch_bounds__(256) csr_kernel(int nrows, const int* __restri
   double a[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) a[v] = 0.0;
+  // loads are unconditional at clamped positions and masked by a multiply (a guarded load would
+  // become a branch of its own with a wait): the V column/value pairs, then the V entries of x
   for (int base = s; base < e; base += 64) {
+    int cc[V];
+    double vv[V], xx[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const int q = base + lane + v * LANES;
-      if (q < e) a[v] += val[q] * x[col[q]];
+      const int qc = min(q, e - 1);
+      cc[v] = col[qc];
+      vv[v] = val[qc] * (q < e ? 1.0 : 0.0);
     }
+#pragma unroll
+    for (int v = 0; v < V; ++v) xx[v] = x[cc[v]];
+#pragma unroll
+    for (int v = 0; v < V; ++v) a[v] += vv[v] * xx[v];
   }
 #pragma unroll
   for (int o = 32; o >= LANES; o >>= 1) {
