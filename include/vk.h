@@ -230,7 +230,8 @@ vk_status vk_rhs_random(const vk_hierarchy* h, int n_modes, const double* h_coef
 
 /* Launch shapes of one level.  They change only speed, never results: the
  * CSR products and the patch apply sum in a canonical order that does not
- * depend on the lanes per row or the waves per patch. */
+ * depend on the lanes per row, the waves per patch, the cache policy or the
+ * load depth. */
 typedef struct vk_tuning {
   int k_lanes;           /* lanes per CSR row of K (4, 8, 16, 32, 64) */
   int p_lanes;           /* lanes per row of the prolongation from level-1 */
@@ -239,6 +240,8 @@ typedef struct vk_tuning {
   int apply_waves_small; /* wavefronts per patch, the others */
   int apply_nontemporal_large; /* 1: stream the large patches' inverses with non-temporal loads */
   int apply_nontemporal_small; /* same for the small patches */
+  int apply_depth_large; /* symmetric tiled storage: tile steps of loads in flight per lane (2 or 4) */
+  int apply_depth_small; /* same for the small patches */
 } vk_tuning;
 
 /* Autotuner (batching pattern of the path): times every candidate launch

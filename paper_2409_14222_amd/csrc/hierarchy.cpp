@@ -137,11 +137,11 @@ void patch_apply(vk_hierarchy* h, int l, const double* t) {
     h->ev_free.pop_back();
     HIPCHECK(hipEventRecord(ev.first, h->stream));
   }
-  launch_patch_apply(h->fp32(), d.tri, d.max_n, d.waves_large, d.nt_large != 0, d.n_large, d.meta, d.pdofs, d.inv, t,
-                     d.delta,
+  launch_patch_apply(h->fp32(), d.tri, d.max_n, d.waves_large, d.nt_large != 0, d.depth_large, d.n_large, d.meta,
+                     d.pdofs, d.inv, t, d.delta,
                      h->stream);
-  launch_patch_apply(h->fp32(), d.tri, std::min(d.max_n, 64), d.waves_small, d.nt_small != 0, d.J - d.n_large,
-                     d.meta + d.n_large, d.pdofs, d.inv,
+  launch_patch_apply(h->fp32(), d.tri, std::min(d.max_n, 64), d.waves_small, d.nt_small != 0, d.depth_small,
+                     d.J - d.n_large, d.meta + d.n_large, d.pdofs, d.inv,
                      t, d.delta, h->stream);
   check_launch();
   if (timed) {
@@ -396,18 +396,22 @@ void autotune(vk_hierarchy* h, int reps) {
       const int first = part == 0 ? 0 : d.n_large;
       const int count = part == 0 ? d.n_large : d.J - d.n_large;
       if (count == 0) continue;
-      int best = 1, best_nt = 1;
+      int best = 1, best_nt = 1, best_depth = 2;
       float bt = 1e30f;
-      for (int nt = 1; nt >= 0; --nt)
-        for (int w : waves) {
-          const float t = time_ms(s, reps, [&] {
-            launch_patch_apply(h->fp32(), d.tri, part == 0 ? d.max_n : std::min(d.max_n, 64), w, nt != 0, count,
-                               d.meta + first, d.pdofs, d.inv, d.b, d.delta, s);
-          });
-          if (t < bt * 0.98f) { bt = t; best = w; best_nt = nt; }
-        }
+      for (int depth : {2, 4}) {
+        if (!d.tri && depth != 2) continue;  // the column-major apply has a fixed depth
+        for (int nt = 1; nt >= 0; --nt)
+          for (int w : waves) {
+            const float t = time_ms(s, reps, [&] {
+              launch_patch_apply(h->fp32(), d.tri, part == 0 ? d.max_n : std::min(d.max_n, 64), w, nt != 0, depth,
+                                 count, d.meta + first, d.pdofs, d.inv, d.b, d.delta, s);
+            });
+            if (t < bt * 0.98f) { bt = t; best = w; best_nt = nt; best_depth = depth; }
+          }
+      }
       (part == 0 ? d.waves_large : d.waves_small) = best;
       (part == 0 ? d.nt_large : d.nt_small) = best_nt;
+      (part == 0 ? d.depth_large : d.depth_small) = best_depth;
     }
   }
   check_launch();
@@ -441,10 +445,10 @@ void smooth_multi(vk_hierarchy* h, int l, int R, const double* B, double* X, int
     }
     if (d.tri) {
       // bound for one right-hand side: [N][1] multivectors are plain vectors
-      launch_patch_apply(h->fp32(), true, d.max_n, d.waves_large, d.nt_large != 0, d.n_large, d.meta, d.pdofs, d.inv,
-                         T, d.delta, s);
-      launch_patch_apply(h->fp32(), true, std::min(d.max_n, 64), d.waves_small, d.nt_small != 0, d.J - d.n_large,
-                         d.meta + d.n_large, d.pdofs, d.inv, T, d.delta, s);
+      launch_patch_apply(h->fp32(), true, d.max_n, d.waves_large, d.nt_large != 0, d.depth_large, d.n_large, d.meta,
+                         d.pdofs, d.inv, T, d.delta, s);
+      launch_patch_apply(h->fp32(), true, std::min(d.max_n, 64), d.waves_small, d.nt_small != 0, d.depth_small,
+                         d.J - d.n_large, d.meta + d.n_large, d.pdofs, d.inv, T, d.delta, s);
     } else {
       launch_patch_gemm(h->fp32(), d.n_large, d.max_n, d.meta, d.pdofs, d.inv, T, R, d.delta, s);
       launch_patch_gemm(h->fp32(), d.J - d.n_large, std::min(d.max_n, 64), d.meta + d.n_large, d.pdofs, d.inv, T, R,
@@ -1121,6 +1125,8 @@ vk_status vk_tuning_get(const vk_hierarchy* h, int level, vk_tuning* t) {
     t->apply_waves_small = d.waves_small;
     t->apply_nontemporal_large = d.nt_large;
     t->apply_nontemporal_small = d.nt_small;
+    t->apply_depth_large = d.depth_large;
+    t->apply_depth_small = d.depth_small;
     return VK_OK;
   });
 }
@@ -1134,6 +1140,8 @@ vk_status vk_tuning_set(vk_hierarchy* h, int level, const vk_tuning* t) {
     auto okw = [](int v) { return v == 1 || v == 2 || v == 4; };
     require(okl(t->k_lanes) && okl(t->p_lanes) && okl(t->pt_lanes), VK_EINVAL, "lanes must be 4, 8, 16, 32 or 64");
     require(okw(t->apply_waves_large) && okw(t->apply_waves_small), VK_EINVAL, "waves must be 1, 2 or 4");
+    auto okd = [](int v) { return v == 2 || v == 4; };
+    require(okd(t->apply_depth_large) && okd(t->apply_depth_small), VK_EINVAL, "depth must be 2 or 4");
     drop_graphs(h);
     DevLevel& d = h->D[level];
     d.k_lanes = t->k_lanes;
@@ -1143,6 +1151,8 @@ vk_status vk_tuning_set(vk_hierarchy* h, int level, const vk_tuning* t) {
     d.waves_small = t->apply_waves_small;
     d.nt_large = t->apply_nontemporal_large != 0;
     d.nt_small = t->apply_nontemporal_small != 0;
+    d.depth_large = t->apply_depth_large;
+    d.depth_small = t->apply_depth_small;
     return VK_OK;
   });
 }

@@ -715,14 +715,14 @@ __device__ __forceinline__ float dpp_x(float v) {
 // symmetric inverse, from the tiles on and below the diagonal only.  Tile
 // (I, J) adds S_IJ x_J to rows 8 I.. and, when I > J, S_IJ^T x_I to rows 8 J...
 // Eight lanes take one tile, lane c its column c (8 rows, 16-byte loads); a
-// wave takes 8 tiles per step and keeps 2 steps of loads in flight.  Inside a
+// wave takes 8 tiles per step and keeps U steps of loads in flight.  Inside a
 // tile the row sums combine the 8 columns by a fixed transposing tree (partners
 // 7 - c, then c xor 2, then c xor 1; lane c ends with row c), the column sums are
 // lane-local in row order.  Every tile
 // writes its partial vectors to Q[I][J][.] (and Q[J][I][.]); row i then sums
 // Q[I][0..nb)[i % 8] in ascending J.  Which wave takes which tile changes
 // nothing, so the result depends on neither waves nor the cache policy.
-template <typename TS, int W, bool NT>
+template <typename TS, int W, bool NT, int U>
 __global__ void __launch_bounds__(64 * W) patch_apply_tri_kernel(const int4* __restrict__ meta,
                                                                  const int* __restrict__ pdofs,
                                                                  const TS* __restrict__ inv,
@@ -730,7 +730,6 @@ __global__ void __launch_bounds__(64 * W) patch_apply_tri_kernel(const int4* __r
                                                                  TS* __restrict__ delta) {
   constexpr int E = 16 / sizeof(TS);  // rows per 16-byte load
   constexpr int NV = 8 / E;           // loads per tile column
-  constexpr int U = 2;                // tile steps in flight (more costs occupancy)
   constexpr int NTH = 64 * W;
   using V = typename vec16<TS>::type;
   extern __shared__ char smem[];
@@ -821,17 +820,25 @@ __global__ void __launch_bounds__(64 * W) patch_apply_tri_kernel(const int4* __r
   }
 }
 
+template <typename TS, bool NT, int U>
+static void apply_tri_waves(int waves, int count, size_t lds, const int4* meta, const int* pdofs, const TS* inv,
+                            const double* t, TS* delta, hipStream_t s) {
+  switch (waves) {
+    case 1: patch_apply_tri_kernel<TS, 1, NT, U><<<count, 64, lds, s>>>(meta, pdofs, inv, t, delta); break;
+    case 2: patch_apply_tri_kernel<TS, 2, NT, U><<<count, 128, lds, s>>>(meta, pdofs, inv, t, delta); break;
+    default: patch_apply_tri_kernel<TS, 4, NT, U><<<count, 256, lds, s>>>(meta, pdofs, inv, t, delta); break;
+  }
+}
+
 template <typename TS, bool NT>
-static void apply_tri_dispatch(int waves, int nmax, int count, const int4* meta, const int* pdofs, const TS* inv,
-                               const double* t, TS* delta, hipStream_t s) {
+static void apply_tri_dispatch(int waves, int depth, int nmax, int count, const int4* meta, const int* pdofs,
+                               const TS* inv, const double* t, TS* delta, hipStream_t s) {
   if (count <= 0) return;
   const int nb = (std::min(nmax, 224) + 7) / 8;
   const size_t lds = (size_t)(8 * nb + 8 * nb * nb) * sizeof(TS);
-  switch (waves) {
-    case 1: patch_apply_tri_kernel<TS, 1, NT><<<count, 64, lds, s>>>(meta, pdofs, inv, t, delta); break;
-    case 2: patch_apply_tri_kernel<TS, 2, NT><<<count, 128, lds, s>>>(meta, pdofs, inv, t, delta); break;
-    default: patch_apply_tri_kernel<TS, 4, NT><<<count, 256, lds, s>>>(meta, pdofs, inv, t, delta); break;
-  }
+  // the load depth (tile steps in flight per lane) trades occupancy against latency hiding
+  if (depth >= 4) apply_tri_waves<TS, NT, 4>(waves, count, lds, meta, pdofs, inv, t, delta, s);
+  else apply_tri_waves<TS, NT, 2>(waves, count, lds, meta, pdofs, inv, t, delta, s);
 }
 
 template <typename TS, bool NT>
@@ -845,15 +852,22 @@ static void apply_dispatch(int waves, int count, const int4* meta, const int* pd
   }
 }
 
-void launch_patch_apply(bool fp32, bool tri, int nmax, int waves, bool nontemporal, int count, const int4* meta,
-                        const int* pdofs, const void* inv, const double* t, void* delta, hipStream_t s) {
+void launch_patch_apply(bool fp32, bool tri, int nmax, int waves, bool nontemporal, int depth, int count,
+                        const int4* meta, const int* pdofs, const void* inv, const double* t, void* delta,
+                        hipStream_t s) {
   if (tri) {
     if (fp32) {
-      if (nontemporal) apply_tri_dispatch<float, true>(waves, nmax, count, meta, pdofs, (const float*)inv, t, (float*)delta, s);
-      else apply_tri_dispatch<float, false>(waves, nmax, count, meta, pdofs, (const float*)inv, t, (float*)delta, s);
+      if (nontemporal)
+        apply_tri_dispatch<float, true>(waves, depth, nmax, count, meta, pdofs, (const float*)inv, t, (float*)delta, s);
+      else
+        apply_tri_dispatch<float, false>(waves, depth, nmax, count, meta, pdofs, (const float*)inv, t, (float*)delta, s);
     } else {
-      if (nontemporal) apply_tri_dispatch<double, true>(waves, nmax, count, meta, pdofs, (const double*)inv, t, (double*)delta, s);
-      else apply_tri_dispatch<double, false>(waves, nmax, count, meta, pdofs, (const double*)inv, t, (double*)delta, s);
+      if (nontemporal)
+        apply_tri_dispatch<double, true>(waves, depth, nmax, count, meta, pdofs, (const double*)inv, t, (double*)delta,
+                                         s);
+      else
+        apply_tri_dispatch<double, false>(waves, depth, nmax, count, meta, pdofs, (const double*)inv, t,
+                                          (double*)delta, s);
     }
     return;
   }

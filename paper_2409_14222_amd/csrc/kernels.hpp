@@ -34,10 +34,12 @@ void launch_copy_inverse(bool fp32, bool tri, int n, const void* inv, int64_t of
 // delta_i = K_i^{-1} t[I_i] for `count` patches (n_i <= nmax) described by
 // meta[0..count) ({first slot, n, inverse offset low, high}), from column-major
 // or (`tri`) symmetric tiled inverses, with `waves` (1, 2 or 4) wavefronts per
-// patch; `nontemporal` streams the inverses past the caches.  Results depend on
-// neither waves nor nontemporal.
-void launch_patch_apply(bool fp32, bool tri, int nmax, int waves, bool nontemporal, int count, const int4* meta,
-                        const int* pdofs, const void* inv, const double* t, void* delta, hipStream_t s);
+// patch; `nontemporal` streams the inverses past the caches; `depth` (2 or 4)
+// sets the tile steps of loads in flight of the tiled apply.  Results depend on
+// none of waves, nontemporal and depth.
+void launch_patch_apply(bool fp32, bool tri, int nmax, int waves, bool nontemporal, int depth, int count,
+                        const int4* meta, const int* pdofs, const void* inv, const double* t, void* delta,
+                        hipStream_t s);
 
 // x[d] += scale[d] * sum_{slots of d, ascending patch id} delta[slot]
 void launch_scatter(bool fp32, int N, const int* dptr, const int* dslot, const void* delta, const double* scale,

@@ -276,10 +276,10 @@ def test_launch_shapes_do_not_change_results(fx, request):
     saved = [H.tuning(l) for l in range(len(OH.levels))]
     ref = torch.empty_like(r)
     H.vcycle(r, ref, 2, 2)
-    for lanes, waves in ((4, 1), (8, 2), (16, 4), (64, 1), (32, 4)):
+    for lanes, waves, depth in ((4, 1, 2), (8, 2, 4), (16, 4, 2), (64, 1, 4), (32, 4, 4)):
         for l in range(len(OH.levels)):
             H.set_tuning(l, k_lanes=lanes, p_lanes=lanes, pt_lanes=lanes, apply_waves_large=waves,
-                         apply_waves_small=waves)
+                         apply_waves_small=waves, apply_depth_large=depth, apply_depth_small=depth)
         e = torch.empty_like(r)
         H.vcycle(r, e, 2, 2)
         assert torch.equal(e, ref), (lanes, waves)
