@@ -7,6 +7,7 @@
 // the batch.  Reductions have a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels_multi.hpp"
@@ -197,6 +198,7 @@ __global__ void __launch_bounds__(64 * NW) patch_gemm_mfma_kernel(const int4* __
   float* D = delta + (int64_t)base * R;
   const int lr = lane & 15, lk = lane >> 4;
   const int ntiles = (n + 15) / 16;
+  const int nct = (R + 15) >> 4;  // 16-column tiles that hold right-hand sides
 
   // loads are unconditional at clamped (in-bounds) addresses and masked afterwards by a multiply
   // (a select lets the compiler sink each load into a branch of its own, one wait per load)
@@ -252,6 +254,7 @@ __global__ void __launch_bounds__(64 * NW) patch_gemm_mfma_kernel(const int4* __
           const int k = k0 + 4 * u + lk;
 #pragma unroll
           for (int ct = 0; ct < 4; ++ct) {
+            if (ct >= nct) break;  // column tiles past R hold zeros: skipped (wave-uniform)
             const float b = Bs[bs_index(k, ct * 16 + lr)];
             acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b, acc[ct], 0, 0, 0);
           }
@@ -271,41 +274,52 @@ __global__ void __launch_bounds__(64 * NW) patch_gemm_mfma_kernel(const int4* __
   }
 }
 
-// FP64 inverses: vector FMAs.  Thread (r, g) of a 64 x 4 grid computes rows
-// r, r + 64, ... for the 16 columns 16 g .. 16 g + 15; the columns of the
-// inverse stream from HBM, the residual block sits in LDS.
+// FP64 inverses: vector FMAs.  The residual block T[I_i, 0:R] sits in LDS as
+// [n][W] doubles, W = 16 ceil(R / 16); wave g computes the 16 columns
+// 16 g .. 16 g + 15 (waves past ceil(R / 16) leave after the gather) for rows
+// r, r + 64, ...  The columns of the inverse stream from HBM 8 at a time
+// (unconditional clamped loads); every column sums in ascending j.
 __global__ void __launch_bounds__(256) patch_gemm_f64_kernel(const int4* __restrict__ meta,
                                                              const int* __restrict__ pdofs,
                                                              const double* __restrict__ inv,
                                                              const double* __restrict__ T, int R,
                                                              double* __restrict__ delta) {
-  __shared__ double Bs[128 * 64];
+  extern __shared__ double Bd[];
   const int4 m4 = meta[blockIdx.x];
   const int base = m4.x, n = m4.y;
   const int64_t off = (int64_t)(uint32_t)m4.z | ((int64_t)m4.w << 32);
   if (n > 128 || n <= 0) return;  // the host limits FP64 multi-RHS patches to 128 DoFs; never taken
   const int tid = threadIdx.x;
-  for (int e = tid; e < n * 64; e += 256) {
-    const int j = e >> 6, c = e & 63;
-    Bs[e] = c < R ? T[(int64_t)pdofs[base + j] * R + c] : 0.0;
+  const int G = (R + 15) >> 4, W = 16 * G;
+  for (int e = tid; e < n * W; e += 256) {
+    const int j = e / W, c = e - j * W;
+    Bd[e] = c < R ? T[(int64_t)pdofs[base + j] * R + c] : 0.0;
   }
   __syncthreads();
+  const int g = tid >> 6, r0 = tid & 63;
+  if (g >= G) return;  // wave-uniform, after the only barrier
   const int ld = (n + 1) / 2 * 2;
   const double* A = inv + off;
-  const int r0 = tid & 63, g = tid >> 6;
   for (int r = r0; r < n; r += 64) {
     double acc[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-    for (int j = 0; j < n; ++j) {
-      const double a = A[(int64_t)j * ld + r];
+    for (int j0 = 0; j0 < n; j0 += 8) {
+      double a[8];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) acc[u] += a * Bs[j * 64 + 16 * g + u];
+      for (int u = 0; u < 8; ++u) a[u] = A[(int64_t)min(j0 + u, n - 1) * ld + r];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (j0 + u >= n) break;
+        const double* b = Bd + (j0 + u) * W + 16 * g;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[v] += a[u] * b[v];
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int c = 16 * g + u;
-      if (c < R) delta[(int64_t)(base + r) * R + c] = acc[u];
+    for (int v = 0; v < 16; ++v) {
+      const int c = 16 * g + v;
+      if (c < R) delta[(int64_t)(base + r) * R + c] = acc[v];
     }
   }
 }
@@ -323,7 +337,8 @@ void launch_patch_gemm(bool fp32, int count, int nmax, const int4* meta, const i
     else
       patch_gemm_mfma_kernel<1><<<count, 64, lds, s>>>(meta, pdofs, (const float*)inv, T, R, nmax, (float*)delta);
   } else {
-    patch_gemm_f64_kernel<<<count, 256, 0, s>>>(meta, pdofs, (const double*)inv, T, R, (double*)delta);
+    const size_t lds = (size_t)std::min(nmax, 128) * 16 * ((R + 15) / 16) * sizeof(double);
+    patch_gemm_f64_kernel<<<count, 256, lds, s>>>(meta, pdofs, (const double*)inv, T, R, (double*)delta);
   }
 }
 
