@@ -22,6 +22,7 @@ fields    manufactured solutions and forcing fields
 th        Taylor-Hood assembly: DoF numbering, K = [A B^T; B 0], rhs, transfers
 patches   composite ("topological") Vanka patches, Sec. 3.1
 vanka     additive subspace correction (Algorithm 1) as a damped smoother
+chebyshev its Chebyshev acceleration with a per-level Arnoldi eigenvalue estimate
 mg        monolithic V-cycle with a bordered coarsest solve, Sec. 3
 fgmres    right-preconditioned FGMRES with CGS2 orthogonalisation, Sec. 3
 norms     H^1 / L^2 error norms (pressure mean removed), Sec. 4.4

@@ -3,7 +3,8 @@
 One V(nu_pre, nu_post) cycle approximates K_L^{-1} r on the finest level:
 
   level l > 0 :  e = 0
-                 nu_pre smoothing sweeps on K_l e = r
+                 nu_pre smoothing sweeps on K_l e = r (damped additive Vanka, or nu_pre
+                 Chebyshev-accelerated steps of it: oracle.chebyshev)
                  r_c = P_l^T (r - K_l e)          (restriction R = P^T)
                  e_c = V(l - 1, r_c)
                  e  += P_l e_c                     (canonical prolongation)
@@ -24,7 +25,7 @@ from .vanka import AdditiveVanka
 
 class VCycle:
     def __init__(self, hier, omega=0.5, nu_pre=2, nu_post=2, construct="composite",
-                 weighting="multiplicity"):
+                 weighting="multiplicity", smoother="damped", est_steps=10, est_seed=0):
         from .patches import build_patches
         self.hier = hier
         self.levels = hier.levels
@@ -33,6 +34,19 @@ class VCycle:
         self.smoothers = [None] + [
             AdditiveVanka(L.K, build_patches(L, construct), omega, weighting)
             for L in self.levels[1:]]
+        # Chebyshev acceleration (Sec. 3): per-level largest-eigenvalue estimate of B K
+        self.cheb = None
+        if smoother == "chebyshev":
+            from . import chebyshev as ch
+            self.cheb = [None]
+            for l in range(1, len(self.levels)):
+                S = self.smoothers[l]
+                B = lambda r, S=S: S.weight * S.correction(r)
+                v0 = ch.start_vector(self.levels[l].N, est_seed, l)
+                lam = ch.arnoldi_lambda(self.levels[l].K, B, v0, est_steps)
+                self.cheb.append(ch.ChebyshevVanka(S, lam))
+        elif smoother != "damped":
+            raise ValueError(smoother)
         L0 = self.levels[0]
         z = L0.nullvec()
         N0 = L0.N
@@ -48,6 +62,8 @@ class VCycle:
         return sla.lu_solve(self.coarse_lu, rhs)[: self.N0]
 
     def smooth(self, l, b, x, nsweeps):
+        if self.cheb is not None:
+            return self.cheb[l].sweeps(b, x, nsweeps)
         for _ in range(nsweeps):
             x = self.smoothers[l].sweep(b, x)
         return x

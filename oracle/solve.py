@@ -11,7 +11,7 @@ from . import mg, th
 
 
 def setup(dim, k, n0, nlevels, nu, field_factory, omega=0.5, nu_sweeps=2, construct="composite",
-          weighting="multiplicity", family="th"):
+          weighting="multiplicity", family="th", smoother="damped", est_steps=10, est_seed=0):
     if family == "sv":
         from . import sv
         H = sv.SVHierarchy(k, n0, nlevels, nu, field_factory)
@@ -19,7 +19,7 @@ def setup(dim, k, n0, nlevels, nu, field_factory, omega=0.5, nu_sweeps=2, constr
     else:
         H = th.THHierarchy(dim, k, n0, nlevels, nu, field_factory)
     V = mg.VCycle(H, omega=omega, nu_pre=nu_sweeps, nu_post=nu_sweeps, construct=construct,
-                  weighting=weighting)
+                  weighting=weighting, smoother=smoother, est_steps=est_steps, est_seed=est_seed)
     return H, V
 
 

@@ -1,0 +1,91 @@
+"""Pins for the Chebyshev-accelerated additive Vanka smoother of the oracle (CPU only).
+
+The counter-based generator is checked against the published first outputs of
+SplitMix64; the smoother's error propagation against the closed-form
+Chebyshev polynomial of B K built from dense matrices; the Arnoldi estimate
+against dense eigenvalues; the solver against a direct solve.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import chebyshev as ch
+from oracle import fields, patches, solve, th
+from oracle.vanka import AdditiveVanka
+
+
+def test_splitmix64_reference_outputs():
+    # SplitMix64 from state 0: the first three outputs of the reference generator
+    assert ch.splitmix64_mix(1 * ch.GAMMA) == 0xE220A8397B1DCDAF
+    assert ch.splitmix64_mix(2 * ch.GAMMA) == 0x6E789E6AA1B965F4
+    assert ch.splitmix64_mix(3 * ch.GAMMA) == 0x06C45D188009454F
+
+
+def test_start_vector_is_deterministic_and_spread():
+    a = ch.start_vector(4000, 7, 2)
+    assert np.array_equal(a, ch.start_vector(4000, 7, 2))
+    assert not np.array_equal(a, ch.start_vector(4000, 7, 3))
+    assert np.all((a >= -1.0) & (a < 1.0))
+    assert abs(a.mean()) < 0.05 and abs(np.var(a) - 1.0 / 3.0) < 0.03
+
+
+@pytest.fixture(scope="module")
+def small():
+    L = th.THLevel(2, 2, 4, 1.0, fields.baseline_mms(1.0))
+    S = AdditiveVanka(L.K, patches.build_patches(L), 0.5, "none")
+    Bd = S.dense_operator() * S.weight[:, None]
+    return L, S, Bd
+
+
+def test_chebyshev_error_propagation_is_the_chebyshev_polynomial(small):
+    L, S, Bd = small
+    K = L.K.toarray()
+    A = Bd @ K
+    lam = float(np.linalg.eigvals(A).real.max())
+    C = ch.ChebyshevVanka(S, lam)
+    N = L.N
+    rng = np.random.default_rng(4)
+    e0 = rng.standard_normal(N)
+    Y = (C.theta * np.eye(N) - A) / C.delta
+    s = C.theta / C.delta
+    for nu in (1, 2, 3, 4):
+        # T_nu(Y) e0 / T_nu(s) by the three-term recurrence
+        T0, T1 = e0.copy(), Y @ e0
+        t0, t1 = 1.0, s
+        for _ in range(nu - 1):
+            T0, T1 = T1, 2.0 * Y @ T1 - T0
+            t0, t1 = t1, 2.0 * s * t1 - t0
+        want = T1 / t1
+        # smoothing K x = 0 from x = e0 leaves the error x
+        got = C.sweeps(np.zeros(N), e0.copy(), nu)
+        assert np.abs(got - want).max() <= 1e-10 * np.abs(e0).max(), nu
+
+
+def test_arnoldi_estimate(small):
+    L, S, Bd = small
+    A = Bd @ L.K.toarray()
+    true = float(np.linalg.eigvals(A).real.max())
+    B = lambda r: S.weight * S.correction(r)
+    v0 = ch.start_vector(L.N, 0, 1)
+    full = ch.arnoldi_lambda(L.K, B, v0, steps=L.N)      # a full Krylov space: exact
+    assert abs(full - true) <= 1e-8 * true
+    est = ch.arnoldi_lambda(L.K, B, v0, steps=10)
+    assert 0.8 * true <= est <= 1.001 * true
+
+
+def test_chebyshev_solver_matches_direct_and_is_h_robust():
+    counts = []
+    for nl in (2, 3):
+        H, V = solve.setup(2, 2, 4, nl, 1.0, fields.baseline_mms, smoother="chebyshev", weighting="none")
+        x, its, hist, conv = solve.solve(H, V)
+        assert conv
+        counts.append(its)
+        if nl == 3:
+            L = H.finest
+            z = L.nullvec()
+            b = solve.consistent_rhs(L)
+            Kb = sp.bmat([[L.K, sp.csr_matrix(z[:, None])], [sp.csr_matrix(z[None, :]), None]]).tocsc()
+            xd = spla.spsolve(Kb, np.concatenate([b, [0.0]]))[: L.N]
+            assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
+    assert abs(counts[1] - counts[0]) <= 2, counts
