@@ -72,6 +72,8 @@ enum {
 
 enum { VK_PATCH_COMPOSITE = 0, VK_PATCH_STAR = 1, VK_PATCH_MACRO = 2 };
 enum { VK_STORE_FP64 = 0, VK_STORE_FP32 = 1 };
+enum { VK_SMOOTH_DAMPED = 0, VK_SMOOTH_CHEBYSHEV = 1 };
+enum { VK_WEIGHT_MULTIPLICITY = 0, VK_WEIGHT_NONE = 1 };
 
 /* Problem statement (Sec. 2 weak form; Sec. 3 hierarchy; Sec. 4 mesh). */
 typedef struct vk_problem {
@@ -92,7 +94,20 @@ typedef struct vk_patch_opts {
                     VK_SV: VK_PATCH_MACRO (one patch per macro triangle: the pressure of its three
                     sub-cells and the free velocity on its closure) */
   int store;     /* VK_STORE_FP64, or VK_STORE_FP32: inverses factored in FP64, stored and applied in FP32 */
-  double omega;  /* global damping; each DoF is further scaled by 1/multiplicity */
+  double omega;  /* global damping of VK_SMOOTH_DAMPED (unused by VK_SMOOTH_CHEBYSHEV) */
+  int smoother;  /* VK_SMOOTH_DAMPED: nu sweeps x += omega W B (b - K x) (Algorithm 1);
+                    VK_SMOOTH_CHEBYSHEV: nu steps of the Chebyshev iteration preconditioned by
+                    W B (Sec. 3) on the interval [lambda / 4, 1.1 lambda] of each level, lambda
+                    the largest real part of the Ritz values of est_steps Arnoldi steps (two
+                    classical Gram-Schmidt passes) on W B K from the start vector below,
+                    computed by vk_patches_setup.  B = sum_i R_i^T K_i^{-1} R_i */
+  int weighting; /* W: VK_WEIGHT_MULTIPLICITY (1 / number of patches containing the DoF) or
+                    VK_WEIGHT_NONE (identity) */
+  int est_steps; /* Arnoldi steps of the estimate, 1..200 (0 = 10); the workspace holds
+                    max(max_restart, est_steps) + 1 basis vectors */
+  uint64_t est_seed; /* start vector of level l: entry i is 2 u - 1, u = (m >> 11) 2^-53 with m
+                        the SplitMix64 output function of the 64-bit counter seed
+                        + l 0xD1B54A32D192ED03 + (i + 1) 0x9E3779B97F4A7C15 */
 } vk_patch_opts;
 
 typedef struct vk_level_info {
@@ -108,6 +123,9 @@ typedef struct vk_level_info {
   int64_t inv_elems_full; /* stored elements of the patch inverses, column-major (bound for > 1 RHS) */
   int64_t inv_elems_tri;  /* stored elements in the symmetric tiled storage (bound for 1 RHS): the
                              8 x 8 tiles on and below the diagonal, zero-padded */
+  double cheb_lambda;     /* VK_SMOOTH_CHEBYSHEV: the eigenvalue estimate of W B K after
+                             vk_patches_setup (0 otherwise, and on level 0) */
+  int cheb_steps;         /* Arnoldi steps taken (fewer than est_steps on an exact breakdown) */
 } vk_level_info;
 
 typedef struct vk_solve_opts {
@@ -169,9 +187,12 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_workspace, size_t bytes, in
 
 /* Matrix-full patch setup on the device: gathers every K_i = K[I_i, I_i]
  * from the CSR matrix (Sec. 3.1), inverts it by Gauss-Jordan elimination
- * with partial pivoting in FP64 and stores the inverse (FP64 or FP32).
+ * with partial pivoting in FP64 and stores the inverse (FP64 or FP32).  With
+ * VK_SMOOTH_CHEBYSHEV it then estimates lambda on every level l >= 1 (the
+ * Arnoldi vectors run on the device through the FGMRES basis, the small
+ * Hessenberg eigenproblem on the host, vk_hessenberg_eigenvalues).
  * Synchronises; VK_ESINGULAR (and the level/patch in vk_last_error) on a zero
- * pivot. */
+ * pivot; VK_ENAN if the estimate is not a positive finite number. */
 vk_status vk_patches_setup(vk_hierarchy* h);
 
 vk_status vk_level_info_get(const vk_hierarchy* h, int level, vk_level_info* info);
@@ -197,8 +218,14 @@ vk_status vk_spmv(vk_hierarchy* h, int level, const double* d_x, double* d_y);
 vk_status vk_restrict(vk_hierarchy* h, int level, const double* d_rf, double* d_rc);
 /* d_ef += P_level d_ec (prolongation from level-1 to level) */
 vk_status vk_prolong_add(vk_hierarchy* h, int level, const double* d_ec, double* d_ef);
-/* nsweeps damped additive Vanka sweeps on K_level x = b (Algorithm 1):
- * x <- x + omega W sum_i R_i^T K_i^{-1} R_i (b - K x), W = diag(1/multiplicity). */
+/* nsweeps smoothing steps on K_level x = b with the hierarchy's smoother.
+ * VK_SMOOTH_DAMPED (Algorithm 1): x <- x + omega W B (b - K x).
+ * VK_SMOOTH_CHEBYSHEV (Sec. 3), with theta = (a + c) / 2, delta = (c - a) / 2 for
+ * the interval [a, c] = [lambda / 4, 1.1 lambda], sigma = theta / delta:
+ *   rho = 1 / sigma;  d = W B (b - K x) / theta;  x += d;  then nsweeps - 1 times
+ *   rho' = 1 / (2 sigma - rho);  d = rho' rho d + (2 rho' / delta) W B (b - K x);
+ *   x += d;  rho = rho'
+ * so the error is multiplied by T_nsweeps((theta - W B K) / delta) / T_nsweeps(sigma). */
 vk_status vk_smooth(vk_hierarchy* h, int level, const double* d_b, double* d_x, int nsweeps);
 /* Coarsest-level solve of the bordered system [K_0 z; z^T 0][e; mu] = [r; 0]. */
 vk_status vk_coarse_solve(vk_hierarchy* h, const double* d_r, double* d_e);
@@ -320,6 +347,14 @@ vk_status vk_server_submit(vk_server* s, const vk_request* req, double* h_x, uin
 vk_status vk_server_tick(vk_server* s, int* active);
 vk_status vk_server_poll(vk_server* s, uint64_t ticket, vk_result* res);
 vk_status vk_server_stats_get(vk_server* s, vk_server_stats* stats);
+
+/* Eigenvalues of an upper Hessenberg n x n matrix (row-major h_H, host; the
+ * entries below the subdiagonal are ignored), 1 <= n <= 512, by the shifted
+ * QR algorithm in complex arithmetic (Givens rotations, Wilkinson shifts,
+ * deflation at negligible subdiagonals).  h_re / h_im: n values each, in the
+ * order of deflation (no sorting).  VK_ENAN on non-finite input or if 100 n
+ * QR steps do not converge. */
+vk_status vk_hessenberg_eigenvalues(int n, const double* h_H, double* h_re, double* h_im);
 
 /* Load vector of the smooth random forcing (as VK_F_RANDOM) on the free DoFs
  * of the 2D (n, k) problem with zero boundary velocity, no hierarchy needed. */

@@ -28,6 +28,8 @@ VK_TH, VK_SV = 0, 1
 VK_F_BASELINE_MMS, VK_F_PAPER_MMS, VK_F_RANDOM, VK_F_CUBE_MMS = 0, 1, 2, 3
 VK_PATCH_COMPOSITE, VK_PATCH_STAR, VK_PATCH_MACRO = 0, 1, 2
 VK_STORE_FP64, VK_STORE_FP32 = 0, 1
+VK_SMOOTH_DAMPED, VK_SMOOTH_CHEBYSHEV = 0, 1
+VK_WEIGHT_MULTIPLICITY, VK_WEIGHT_NONE = 0, 1
 
 _c_int, _c_dbl, _p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
 
@@ -39,13 +41,15 @@ class vk_problem(ctypes.Structure):
 
 
 class vk_patch_opts(ctypes.Structure):
-    _fields_ = [("construct", _c_int), ("store", _c_int), ("omega", _c_dbl)]
+    _fields_ = [("construct", _c_int), ("store", _c_int), ("omega", _c_dbl), ("smoother", _c_int),
+                ("weighting", _c_int), ("est_steps", _c_int), ("est_seed", ctypes.c_uint64)]
 
 
 class vk_level_info(ctypes.Structure):
     _fields_ = [("n", _c_int), ("n_free", _c_int), ("n_velocity", _c_int), ("nnz", ctypes.c_int64),
                 ("n_patches", _c_int), ("sum_n", ctypes.c_int64), ("sum_n2", ctypes.c_int64), ("max_n", _c_int),
-                ("p_nnz", ctypes.c_int64), ("inv_elems_full", ctypes.c_int64), ("inv_elems_tri", ctypes.c_int64)]
+                ("p_nnz", ctypes.c_int64), ("inv_elems_full", ctypes.c_int64), ("inv_elems_tri", ctypes.c_int64),
+                ("cheb_lambda", _c_dbl), ("cheb_steps", _c_int)]
 
 
 class vk_tuning(ctypes.Structure):
@@ -125,6 +129,7 @@ _SIGS = {
     "vk_server_poll": ([_p, ctypes.c_uint64, _P(vk_result)], _c_int),
     "vk_server_stats_get": ([_p, _P(vk_server_stats)], _c_int),
     "vk_load_random": ([_c_int, _c_int, _c_int, _p, _p], _c_int),
+    "vk_hessenberg_eigenvalues": ([_c_int, _p, _p, _p], _c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -152,13 +157,23 @@ def _ptr(a):
     return a.data_ptr()
 
 
+def hessenberg_eigenvalues(H):
+    """Eigenvalues of an upper Hessenberg matrix by the library's QR iteration (host)."""
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    n = H.shape[0]
+    re = np.empty(n); im = np.empty(n)
+    check(lib.vk_hessenberg_eigenvalues(n, _ptr(H), _ptr(re), _ptr(im)))
+    return re + 1j * im
+
+
 class Hierarchy:
     """One Stokes problem hierarchy.  Host-side data is available right after
     construction; device work needs bind() (allocates the workspace with torch
     on the current device and binds the current stream) and setup()."""
 
     def __init__(self, k, n_coarse, n_levels, dim=2, viscosity=1.0, forcing=VK_F_BASELINE_MMS, coeffs=None,
-                 construct=None, store=VK_STORE_FP64, omega=0.5, family=VK_TH):
+                 construct=None, store=VK_STORE_FP64, omega=0.5, family=VK_TH, smoother=VK_SMOOTH_DAMPED,
+                 weighting=VK_WEIGHT_MULTIPLICITY, est_steps=10, est_seed=0):
         if construct is None:
             construct = VK_PATCH_MACRO if family == VK_SV else VK_PATCH_COMPOSITE
         self._coeffs = None
@@ -169,7 +184,7 @@ class Hierarchy:
             n_modes = self._coeffs.shape[-1]
             cptr = self._coeffs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self.prob = vk_problem(dim, family, k, n_coarse, n_levels, viscosity, forcing, n_modes, cptr)
-        self.opts = vk_patch_opts(construct, store, omega)
+        self.opts = vk_patch_opts(construct, store, omega, smoother, weighting, est_steps, est_seed)
         h = ctypes.c_void_p()
         check(lib.vk_hierarchy_create(ctypes.byref(self.prob), ctypes.byref(self.opts), ctypes.byref(h)))
         self.h = h

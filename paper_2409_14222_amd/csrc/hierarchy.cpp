@@ -27,8 +27,13 @@ thread_local std::string g_err;
 
 // Lays out every device array of the hierarchy `Hs` in the carver; pointers go
 // to `h` (a scratch object when only sizing).
-void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver& cv, int max_restart, int R) {
+// The FGMRES basis also holds the Arnoldi vectors of the Chebyshev estimate
+// (`est_steps` + 1 of them, 0 for the damped smoother).
+void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver& cv, int max_restart, int R,
+           int est_steps) {
   const int L = (int)Hs.size();
+  const bool cheb = est_steps > 0;
+  max_restart = std::max(max_restart, est_steps);
   h->D.assign(L, DevLevel());
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
   for (int l = 0; l < L; ++l) {
@@ -80,6 +85,7 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.scale = cv.take<double>(lh.scale.size());
     d.inv = cv.take<char>((size_t)(d.tri ? lh.inv_elems_tri : lh.inv_elems) * es);
     d.delta = cv.take<char>(lh.pdofs.size() * es * R);
+    if (cheb) d.cd = cv.take<double>((size_t)lh.N * R);
   }
   const int N = Hs.back().N;
   h->V = cv.take<double>((size_t)(max_restart + 1) * N * R);
@@ -94,6 +100,8 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
   h->nvc = cv.take<int>(64);
   h->mask = cv.take<int>(64);
 }
+
+int cheb_steps(const vk_hierarchy* h) { return h->cheb() ? h->opts.est_steps : 0; }
 
 template <typename T>
 void up(T* dst, const std::vector<T>& src, hipStream_t s) {
@@ -150,11 +158,43 @@ void patch_apply(vk_hierarchy* h, int l, const double* t) {
   }
 }
 
-// nsweeps of x <- x + omega W sum_i R_i^T K_i^{-1} R_i (b - K x); if x_zero the
-// first residual is b itself (x = 0) and the first update overwrites x.
+// Scatter mode and coefficients of smoothing step `it` of a sequence: the
+// damped sweep (scale = omega W), or the Chebyshev iteration on [lambda / 4,
+// 1.1 lambda] (scale = W): step 0 sets the direction to W B r / theta, step
+// it > 0 to rho' rho d + (2 rho' / delta) W B r with rho' = 1 / (2 sigma - rho).
+struct SmoothStep {
+  int mode;
+  double c1, c2;
+};
+
+struct SmoothSchedule {
+  bool cheb;
+  double sigma = 0, rho = 0, theta = 1, delta = 1;
+  SmoothSchedule(const vk_hierarchy* h, const DevLevel& d) : cheb(h->cheb()) {
+    if (cheb) {
+      theta = d.cheb_theta;
+      delta = d.cheb_delta;
+      sigma = theta / delta;
+      rho = 1.0 / sigma;
+    }
+  }
+  SmoothStep next(int it, bool first_zero) {
+    if (!cheb) return {first_zero ? kScatterSet : kScatterAdd, 0.0, 0.0};
+    if (it == 0) return {first_zero ? kChebFirstSet : kChebFirstAdd, 0.0, 1.0 / theta};
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    const SmoothStep st{kChebNext, rn * rho, 2.0 * rn / delta};
+    rho = rn;
+    return st;
+  }
+};
+
+// nsweeps smoothing steps on K x = b: x <- x + omega W sum_i R_i^T K_i^{-1} R_i (b - K x)
+// (damped), or the Chebyshev steps of SmoothSchedule; if x_zero the first
+// residual is b itself (x = 0) and the first update overwrites x.
 void smooth(vk_hierarchy* h, int l, const double* b, double* x, int nsweeps, bool x_zero) {
   DevLevel& d = h->D[l];
   const hipStream_t s = h->stream;
+  SmoothSchedule sch(h, d);
   for (int it = 0; it < nsweeps; ++it) {
     const bool first_zero = x_zero && it == 0;
     const double* t = b;
@@ -163,8 +203,8 @@ void smooth(vk_hierarchy* h, int l, const double* b, double* x, int nsweeps, boo
       t = d.t;
     }
     patch_apply(h, l, t);
-    if (first_zero) launch_scatter_set(h->fp32(), d.N, d.dptr, d.dslot, d.delta, d.scale, x, s);
-    else launch_scatter(h->fp32(), d.N, d.dptr, d.dslot, d.delta, d.scale, x, s);
+    const SmoothStep st = sch.next(it, first_zero);
+    launch_scatter_mode(h->fp32(), st.mode, d.N, d.dptr, d.dslot, d.delta, d.scale, st.c1, st.c2, d.cd, x, s);
     check_launch();
   }
   if (x_zero && nsweeps == 0) launch_fill(d.N, 0.0, x, s);
@@ -197,6 +237,72 @@ double dot_host(vk_hierarchy* h, int n, const double* a, const double* b) {
   HIPCHECK(hipMemcpyAsync(&v, h->small, sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
   return v;
+}
+
+// Interval of the Chebyshev smoother on level l (Sec. 3): lambda = the largest
+// real part of the Ritz values of est_steps Arnoldi steps on W B K, the vectors
+// in the FGMRES basis (carved with room for them), two classical Gram-Schmidt
+// passes per step as in FGMRES; the step stops early when the new vector's norm
+// is at most 1e-14 times the largest coefficient of its column (an invariant
+// subspace: the Ritz values are then exact eigenvalues).
+void estimate_lambda(vk_hierarchy* h, int l) {
+  DevLevel& d = h->D[l];
+  const hipStream_t s = h->stream;
+  const int N = d.N, k = h->opts.est_steps;
+  const int m = std::max(h->max_restart, k);
+  double* V = h->V;
+  const bool timing = h->timing;
+  h->timing = false;
+  launch_splitmix_vector(N, h->opts.est_seed, l, V, s);
+  check_launch();
+  const double n0 = std::sqrt(dot_host(h, N, V, V));
+  require(std::isfinite(n0) && n0 > 0.0, VK_ENAN, "zero start vector of the eigenvalue estimate");
+  launch_div(N, V, n0, V, s);
+  std::vector<double> H((size_t)k * k, 0.0), hh(3 * (m + 2));
+  int steps = k;
+  for (int j = 0; j < k; ++j) {
+    const double* vj = V + (size_t)j * N;
+    double* w = V + (size_t)(j + 1) * N;
+    launch_csr(0, N, d.k_lanes, d.rowptr, d.col, d.val, vj, nullptr, d.t, s);  // t = K v_j
+    patch_apply(h, l, d.t);
+    launch_scatter_mode(h->fp32(), kScatterSet, N, d.dptr, d.dslot, d.delta, d.scale, 0.0, 0.0, nullptr, w, s);
+    launch_multidot(N, j + 1, V, N, w, h->partial, h->small, s);
+    launch_multiaxpy(N, j + 1, -1.0, V, N, h->small, w, s);
+    launch_multidot(N, j + 1, V, N, w, h->partial, h->small + (m + 2), s);
+    launch_multiaxpy(N, j + 1, -1.0, V, N, h->small + (m + 2), w, s);
+    launch_multidot(N, 1, w, 0, w, h->partial, h->small + 2 * (m + 2), s);
+    check_launch();
+    HIPCHECK(hipMemcpyAsync(hh.data(), h->small, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    double big = 0.0;
+    for (int i = 0; i <= j; ++i) {
+      H[(size_t)i * k + j] = hh[i] + hh[(m + 2) + i];
+      big = std::max(big, std::fabs(H[(size_t)i * k + j]));
+    }
+    const double hn = std::sqrt(hh[2 * (m + 2)]);
+    require(std::isfinite(hn) && std::isfinite(big), VK_ENAN, "eigenvalue estimate: non-finite Arnoldi vector");
+    if (hn <= 1e-14 * big) {
+      steps = j + 1;
+      break;
+    }
+    if (j + 1 < k) H[(size_t)(j + 1) * k + j] = hn;
+    launch_div_norm(N, w, h->small + 2 * (m + 2), s);
+  }
+  h->timing = timing;
+  std::vector<double> Hs((size_t)steps * steps);
+  for (int i = 0; i < steps; ++i)
+    for (int j = 0; j < steps; ++j) Hs[(size_t)i * steps + j] = H[(size_t)i * k + j];
+  std::vector<std::complex<double>> ev;
+  require(hessenberg_eigs(steps, Hs.data(), ev), VK_ENAN, "eigenvalue estimate: QR iteration failed");
+  double lam = -INFINITY;
+  for (const auto& e : ev) lam = std::max(lam, e.real());
+  require(std::isfinite(lam) && lam > 0.0, VK_ENAN,
+          "eigenvalue estimate on level " + std::to_string(l) + " is not positive");
+  const double a = lam / 4.0, c = 1.1 * lam;
+  d.cheb_lambda = lam;
+  d.cheb_steps = steps;
+  d.cheb_theta = (a + c) / 2.0;
+  d.cheb_delta = (c - a) / 2.0;
 }
 
 void collect_timing(vk_hierarchy* h) {
@@ -423,6 +529,7 @@ void autotune(vk_hierarchy* h, int reps) {
 void smooth_multi(vk_hierarchy* h, int l, int R, const double* B, double* X, int nsweeps, bool x_zero) {
   DevLevel& d = h->D[l];
   const hipStream_t s = h->stream;
+  SmoothSchedule sch(h, d);
   for (int it = 0; it < nsweeps; ++it) {
     const bool first_zero = x_zero && it == 0;
     const double* T = B;
@@ -458,7 +565,9 @@ void smooth_multi(vk_hierarchy* h, int l, int R, const double* B, double* X, int
       HIPCHECK(hipEventRecord(ev.second, s));
       h->ev_pending.push_back(ev);
     }
-    launch_scatter_multi(h->fp32(), first_zero, d.N, R, d.dptr, d.dslot, d.delta, d.scale, X, s);
+    const SmoothStep st = sch.next(it, first_zero);
+    launch_scatter_multi_mode(h->fp32(), st.mode, d.N, R, d.dptr, d.dslot, d.delta, d.scale, st.c1, st.c2, d.cd, X,
+                              s);
     check_launch();
   }
   if (x_zero && nsweeps == 0) launch_fill(d.N * R, 0.0, X, s);
@@ -674,6 +783,10 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
     require(p.viscosity > 0 && std::isfinite(p.viscosity), VK_EINVAL, "viscosity must be positive");
     require(opts->omega > 0 && std::isfinite(opts->omega), VK_EINVAL, "omega must be positive");
     require(opts->store == VK_STORE_FP64 || opts->store == VK_STORE_FP32, VK_EINVAL, "bad store");
+    require(opts->smoother == VK_SMOOTH_DAMPED || opts->smoother == VK_SMOOTH_CHEBYSHEV, VK_EINVAL, "bad smoother");
+    require(opts->weighting == VK_WEIGHT_MULTIPLICITY || opts->weighting == VK_WEIGHT_NONE, VK_EINVAL,
+            "bad weighting");
+    require(opts->est_steps >= 0 && opts->est_steps <= 200, VK_EINVAL, "est_steps must be in 0..200");
     if (p.family == VK_SV)
       require(opts->construct == VK_PATCH_MACRO, VK_EINVAL, "Scott-Vogelius levels use VK_PATCH_MACRO");
     else
@@ -693,6 +806,7 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
     }
     h->pr.p.h_forcing_coeffs = nullptr;
     h->opts = *opts;
+    if (h->opts.est_steps == 0) h->opts.est_steps = 10;
     h->H.resize(p.n_levels);
     for (int l = 0; l < p.n_levels; ++l) {
       LevelHost& L = h->H[l];
@@ -708,6 +822,12 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
         L.ptgrp = row_groups(L.PT, 8);
         build_patches(L, opts->construct, opts->omega, opts->store);
         require(L.max_n <= 224, VK_EINVAL, "patches above 224 DoFs are not supported");
+        if (opts->smoother == VK_SMOOTH_CHEBYSHEV || opts->weighting == VK_WEIGHT_NONE) {
+          // W (and omega for the damped sweep only)
+          const double om = opts->smoother == VK_SMOOTH_CHEBYSHEV ? 1.0 : opts->omega;
+          for (int dof = 0; dof < L.N; ++dof)
+            L.scale[dof] = opts->weighting == VK_WEIGHT_NONE ? om : om / (L.dptr[dof + 1] - L.dptr[dof]);
+        }
       }
     }
     h->coarse_M = bordered_inverse(h->H[0]);
@@ -745,7 +865,7 @@ vk_status vk_hierarchy_workspace_bytes(const vk_hierarchy* h, int max_restart, i
     require(max_rhs >= 1 && max_rhs <= 64, VK_EINVAL, "max_rhs must be in 1..64");
     vk_hierarchy tmp;  // sizing pass: pointers land in a scratch object
     Carver cv(nullptr);
-    carve(h->H, h->fp32(), &tmp, cv, max_restart, max_rhs);
+    carve(h->H, h->fp32(), &tmp, cv, max_restart, max_rhs, cheb_steps(h));
     *bytes = cv.off + 256;
     return VK_OK;
   });
@@ -761,7 +881,7 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_r
     Carver dry(nullptr);
     {
       vk_hierarchy tmp;
-      carve(h->H, h->fp32(), &tmp, dry, max_restart, max_rhs);
+      carve(h->H, h->fp32(), &tmp, dry, max_restart, max_rhs, cheb_steps(h));
     }
     require(bytes >= dry.off, VK_ENOMEM, "workspace too small");
     h->stream = (hipStream_t)stream;
@@ -769,7 +889,7 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_r
     h->max_rhs = max_rhs;
     drop_graphs(h);
     Carver cv(d_ws);
-    carve(h->H, h->fp32(), h, cv, max_restart, max_rhs);
+    carve(h->H, h->fp32(), h, cv, max_restart, max_rhs, cheb_steps(h));
     h->meta_host.clear();
     const hipStream_t s = h->stream;
     for (int l = 0; l < h->L(); ++l) {
@@ -831,6 +951,8 @@ vk_status vk_patches_setup(vk_hierarchy* h) {
   return guarded([&]() -> vk_status {
     require(h && h->bound, VK_ESTATE, "hierarchy is not bound");
     const hipStream_t s = h->stream;
+    drop_graphs(h);  // captured smoothing steps hold the Chebyshev coefficients
+    h->ready = false;
     for (int l = 1; l < h->L(); ++l) {
       DevLevel& d = h->D[l];
       std::vector<int> init(1, INT_MAX);
@@ -853,6 +975,8 @@ vk_status vk_patches_setup(vk_hierarchy* h) {
       require(sing == INT_MAX, VK_ESINGULAR,
               "zero pivot in patch " + std::to_string(sing) + " on level " + std::to_string(l));
     }
+    if (h->cheb())
+      for (int l = 1; l < h->L(); ++l) estimate_lambda(h, l);
     h->ready = true;
     return VK_OK;
   });
@@ -874,6 +998,9 @@ vk_status vk_level_info_get(const vk_hierarchy* h, int level, vk_level_info* inf
     info->p_nnz = level == 0 ? 0 : L.P.nnz();
     info->inv_elems_full = level == 0 ? 0 : L.inv_elems;
     info->inv_elems_tri = level == 0 ? 0 : L.inv_elems_tri;
+    const bool est = h->ready && h->cheb() && level > 0;
+    info->cheb_lambda = est ? h->D[level].cheb_lambda : 0.0;
+    info->cheb_steps = est ? h->D[level].cheb_steps : 0;
     return VK_OK;
   });
 }

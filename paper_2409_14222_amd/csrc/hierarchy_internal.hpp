@@ -35,6 +35,9 @@ struct DevLevel {
   void* inv = nullptr;
   void* delta = nullptr;
   double *b = nullptr, *x = nullptr, *t = nullptr;
+  double* cd = nullptr;  // Chebyshev direction ([N][R], levels >= 1)
+  double cheb_lambda = 0.0, cheb_theta = 0.0, cheb_delta = 0.0;  // estimate and interval centre / half-width
+  int cheb_steps = 0;
   double* M = nullptr;  // coarsest level
   int class_count[4] = {0, 0, 0, 0};  // patches with n <= 32, <= 64, <= 128, <= 224 (ids in `classes`)
   // launch shapes (never change results): lanes per CSR row of K, P, P^T;
@@ -93,6 +96,7 @@ struct vk_hierarchy {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free, ev_pending;
 
   bool fp32() const { return opts.store == VK_STORE_FP32; }
+  bool cheb() const { return opts.smoother == VK_SMOOTH_CHEBYSHEV; }
   int L() const { return (int)H.size(); }
 };
 

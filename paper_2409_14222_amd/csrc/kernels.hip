@@ -886,10 +886,11 @@ void launch_patch_apply(bool fp32, bool tri, int nmax, int waves, bool nontempor
 // slot indices of a chunk of 8 are loaded first and the corrections after,
 // so the dependent loads overlap; the sum stays in ascending slot order.
 // ============================================================================
-template <typename TD, bool SET>
+template <typename TD, int MODE>
 __global__ void __launch_bounds__(256) scatter_kernel(int N, const int* __restrict__ dptr,
                                                       const int* __restrict__ dslot, const TD* __restrict__ delta,
-                                                      const double* __restrict__ scale, double* __restrict__ x) {
+                                                      const double* __restrict__ scale, double c1, double c2,
+                                                      double* __restrict__ dv, double* __restrict__ x) {
   const int d = blockIdx.x * 256 + threadIdx.x;
   if (d >= N) return;
   const int q0 = dptr[d], q1 = dptr[d + 1];
@@ -905,22 +906,63 @@ __global__ void __launch_bounds__(256) scatter_kernel(int N, const int* __restri
     for (int u = 0; u < 8; ++u)
       if (q + u < q1) s += (double)v[u];
   }
-  if (SET) x[d] = scale[d] * s;
-  else x[d] += scale[d] * s;
+  scatter_store<MODE>(scale[d] * s, c1, c2, x, dv, d);
+}
+
+template <int MODE>
+void scatter_launch(bool fp32, int N, const int* dptr, const int* dslot, const void* delta, const double* scale,
+                    double c1, double c2, double* dv, double* x, hipStream_t s) {
+  const int grid = (N + 255) / 256;
+  if (grid == 0) return;
+  if (fp32)
+    scatter_kernel<float, MODE><<<grid, 256, 0, s>>>(N, dptr, dslot, (const float*)delta, scale, c1, c2, dv, x);
+  else
+    scatter_kernel<double, MODE><<<grid, 256, 0, s>>>(N, dptr, dslot, (const double*)delta, scale, c1, c2, dv, x);
 }
 
 void launch_scatter(bool fp32, int N, const int* dptr, const int* dslot, const void* delta, const double* scale,
                     double* x, hipStream_t s) {
-  const int grid = (N + 255) / 256;
-  if (fp32) scatter_kernel<float, false><<<grid, 256, 0, s>>>(N, dptr, dslot, (const float*)delta, scale, x);
-  else scatter_kernel<double, false><<<grid, 256, 0, s>>>(N, dptr, dslot, (const double*)delta, scale, x);
+  scatter_launch<kScatterAdd>(fp32, N, dptr, dslot, delta, scale, 0.0, 0.0, nullptr, x, s);
 }
 
 void launch_scatter_set(bool fp32, int N, const int* dptr, const int* dslot, const void* delta,
                         const double* scale, double* x, hipStream_t s) {
-  const int grid = (N + 255) / 256;
-  if (fp32) scatter_kernel<float, true><<<grid, 256, 0, s>>>(N, dptr, dslot, (const float*)delta, scale, x);
-  else scatter_kernel<double, true><<<grid, 256, 0, s>>>(N, dptr, dslot, (const double*)delta, scale, x);
+  scatter_launch<kScatterSet>(fp32, N, dptr, dslot, delta, scale, 0.0, 0.0, nullptr, x, s);
+}
+
+void launch_scatter_mode(bool fp32, int mode, int N, const int* dptr, const int* dslot, const void* delta,
+                         const double* scale, double c1, double c2, double* dv, double* x, hipStream_t s) {
+  switch (mode) {
+    case kScatterAdd: scatter_launch<kScatterAdd>(fp32, N, dptr, dslot, delta, scale, c1, c2, dv, x, s); break;
+    case kScatterSet: scatter_launch<kScatterSet>(fp32, N, dptr, dslot, delta, scale, c1, c2, dv, x, s); break;
+    case kChebFirstSet: scatter_launch<kChebFirstSet>(fp32, N, dptr, dslot, delta, scale, c1, c2, dv, x, s); break;
+    case kChebFirstAdd: scatter_launch<kChebFirstAdd>(fp32, N, dptr, dslot, delta, scale, c1, c2, dv, x, s); break;
+    default: scatter_launch<kChebNext>(fp32, N, dptr, dslot, delta, scale, c1, c2, dv, x, s); break;
+  }
+}
+
+// ============================================================================
+// Counter-based start vector of the eigenvalue estimate: SplitMix64's output
+// function of seed + level * 0xD1B54A32D192ED03 + (i + 1) * 0x9E3779B97F4A7C15
+// (64-bit wrap-around), top 53 bits as a uniform u in [0, 1), entry 2 u - 1
+// (exact in FP64).
+// ============================================================================
+__global__ void __launch_bounds__(256) splitmix_vector_kernel(int n, uint64_t base, double* __restrict__ v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = base + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const double u = (double)(z >> 11) * 0x1.0p-53;
+  v[i] = 2.0 * u - 1.0;
+}
+
+void launch_splitmix_vector(int n, uint64_t seed, int level, double* v, hipStream_t s) {
+  const int grid = (n + 255) / 256;
+  if (grid == 0) return;
+  const uint64_t base = seed + (uint64_t)level * 0xD1B54A32D192ED03ull;
+  splitmix_vector_kernel<<<grid, 256, 0, s>>>(n, base, v);
 }
 
 // ============================================================================

@@ -41,9 +41,35 @@ void launch_patch_apply(bool fp32, bool tri, int nmax, int waves, bool nontempor
                         const int4* meta, const int* pdofs, const void* inv, const double* t, void* delta,
                         hipStream_t s);
 
+// Epilogues of the scatter of the weighted corrections y[d] = scale[d] * sum_{slots of d} delta[slot]:
+// kScatterAdd x += y; kScatterSet x = y; the Chebyshev steps keep a direction dv:
+// kChebFirstSet dv = c2 y, x = dv; kChebFirstAdd dv = c2 y, x += dv; kChebNext dv = c1 dv + c2 y, x += dv.
+enum ScatterMode { kScatterAdd = 0, kScatterSet = 1, kChebFirstSet = 2, kChebFirstAdd = 3, kChebNext = 4 };
+
+template <int MODE>
+__device__ __forceinline__ void scatter_store(double y, double c1, double c2, double* x, double* dv, int64_t o) {
+  if (MODE == kScatterAdd) {
+    x[o] += y;
+  } else if (MODE == kScatterSet) {
+    x[o] = y;
+  } else {
+    const double d = MODE == kChebNext ? c1 * dv[o] + c2 * y : c2 * y;
+    dv[o] = d;
+    if (MODE == kChebFirstSet) x[o] = d;
+    else x[o] += d;
+  }
+}
+
 // x[d] += scale[d] * sum_{slots of d, ascending patch id} delta[slot]
 void launch_scatter(bool fp32, int N, const int* dptr, const int* dslot, const void* delta, const double* scale,
                     double* x, hipStream_t s);
+
+// scatter with any ScatterMode (c1, c2, dv as documented there)
+void launch_scatter_mode(bool fp32, int mode, int N, const int* dptr, const int* dslot, const void* delta,
+                         const double* scale, double c1, double c2, double* dv, double* x, hipStream_t s);
+
+// v[i] = 2 u - 1, u = (splitmix64_mix(seed + level * 0xD1B54A32D192ED03 + (i + 1) * 0x9E3779B97F4A7C15) >> 11) 2^-53
+void launch_splitmix_vector(int n, uint64_t seed, int level, double* v, hipStream_t s);
 
 // x[d] = scale[d] * sum delta (first sweep from a zero iterate)
 void launch_scatter_set(bool fp32, int N, const int* dptr, const int* dslot, const void* delta,

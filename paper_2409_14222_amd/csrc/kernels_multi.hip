@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "kernels.hpp"
 #include "kernels_multi.hpp"
 
 namespace vk {
@@ -345,30 +346,30 @@ void launch_patch_gemm(bool fp32, int count, int nmax, const int4* meta, const i
 // ============================================================================
 // Column-wise scatter: X[d][c] (+)= scale[d] * sum over the slots of d (ascending patch id).
 // ============================================================================
-template <typename TD, bool SET>
+template <typename TD, int MODE>
 __global__ void __launch_bounds__(256) scatter_multi_kernel(int N, int R, int Rp, const int* __restrict__ dptr,
                                                             const int* __restrict__ dslot,
                                                             const TD* __restrict__ delta,
-                                                            const double* __restrict__ scale, double* __restrict__ X) {
+                                                            const double* __restrict__ scale, double c1, double c2,
+                                                            double* __restrict__ DV, double* __restrict__ X) {
   const int rpb = 256 / Rp;
   const int d = blockIdx.x * rpb + threadIdx.x / Rp;
   const int c = threadIdx.x % Rp;
   if (d >= N || c >= R) return;
   double s = 0.0;
   for (int q = dptr[d]; q < dptr[d + 1]; ++q) s += (double)delta[(int64_t)dslot[q] * R + c];
-  const int64_t o = (int64_t)d * R + c;
-  if (SET) X[o] = scale[d] * s;
-  else X[o] += scale[d] * s;
+  scatter_store<MODE>(scale[d] * s, c1, c2, X, DV, (int64_t)d * R + c);
 }
 
 // R > 32: one DoF per wave, made wave-uniform so that the slot list comes by scalar loads; the
 // slot rows of delta are read 8 at a time (the last batch padded with its final slot times zero;
 // delta is finite), summed in the same ascending order.
-template <typename TD, bool SET>
+template <typename TD, int MODE>
 __global__ void __launch_bounds__(256) scatter_wave_kernel(int N, int R, const int* __restrict__ dptr,
                                                            const int* __restrict__ dslot,
                                                            const TD* __restrict__ delta,
-                                                           const double* __restrict__ scale, double* __restrict__ X) {
+                                                           const double* __restrict__ scale, double c1, double c2,
+                                                           double* __restrict__ DV, double* __restrict__ X) {
   const int d = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (d >= N) return;
   const int c = threadIdx.x & 63;
@@ -383,34 +384,51 @@ __global__ void __launch_bounds__(256) scatter_wave_kernel(int N, int R, const i
     for (int u = 0; u < 8; ++u) s += v[u] * (q + u < q1 ? 1.0 : 0.0);
   }
   if (c >= R) return;
-  const int64_t o = (int64_t)d * R + c;
-  if (SET) X[o] = scale[d] * s;
-  else X[o] += scale[d] * s;
+  scatter_store<MODE>(scale[d] * s, c1, c2, X, DV, (int64_t)d * R + c);
 }
 
-void launch_scatter_multi(bool fp32, bool set, int N, int R, const int* dptr, const int* dslot, const void* delta,
-                          const double* scale, double* X, hipStream_t s) {
+template <typename TD, int MODE>
+void scatter_multi_launch(int N, int R, const int* dptr, const int* dslot, const void* delta, const double* scale,
+                          double c1, double c2, double* DV, double* X, hipStream_t s) {
   if (R > 32) {
     const int grid = (N + 3) / 4;
     if (grid == 0) return;
-    if (fp32) {
-      if (set) scatter_wave_kernel<float, true><<<grid, 256, 0, s>>>(N, R, dptr, dslot, (const float*)delta, scale, X);
-      else scatter_wave_kernel<float, false><<<grid, 256, 0, s>>>(N, R, dptr, dslot, (const float*)delta, scale, X);
-    } else {
-      if (set) scatter_wave_kernel<double, true><<<grid, 256, 0, s>>>(N, R, dptr, dslot, (const double*)delta, scale, X);
-      else scatter_wave_kernel<double, false><<<grid, 256, 0, s>>>(N, R, dptr, dslot, (const double*)delta, scale, X);
-    }
+    scatter_wave_kernel<TD, MODE><<<grid, 256, 0, s>>>(N, R, dptr, dslot, (const TD*)delta, scale, c1, c2, DV, X);
     return;
   }
   const int Rp = pow2_at_least(R);
   const int rpb = 256 / Rp;
   const int grid = (N + rpb - 1) / rpb;
-  if (fp32) {
-    if (set) scatter_multi_kernel<float, true><<<grid, 256, 0, s>>>(N, R, Rp, dptr, dslot, (const float*)delta, scale, X);
-    else scatter_multi_kernel<float, false><<<grid, 256, 0, s>>>(N, R, Rp, dptr, dslot, (const float*)delta, scale, X);
-  } else {
-    if (set) scatter_multi_kernel<double, true><<<grid, 256, 0, s>>>(N, R, Rp, dptr, dslot, (const double*)delta, scale, X);
-    else scatter_multi_kernel<double, false><<<grid, 256, 0, s>>>(N, R, Rp, dptr, dslot, (const double*)delta, scale, X);
+  if (grid == 0) return;
+  scatter_multi_kernel<TD, MODE><<<grid, 256, 0, s>>>(N, R, Rp, dptr, dslot, (const TD*)delta, scale, c1, c2, DV, X);
+}
+
+template <int MODE>
+void scatter_multi_prec(bool fp32, int N, int R, const int* dptr, const int* dslot, const void* delta,
+                        const double* scale, double c1, double c2, double* DV, double* X, hipStream_t s) {
+  if (fp32) scatter_multi_launch<float, MODE>(N, R, dptr, dslot, delta, scale, c1, c2, DV, X, s);
+  else scatter_multi_launch<double, MODE>(N, R, dptr, dslot, delta, scale, c1, c2, DV, X, s);
+}
+
+void launch_scatter_multi(bool fp32, bool set, int N, int R, const int* dptr, const int* dslot, const void* delta,
+                          const double* scale, double* X, hipStream_t s) {
+  launch_scatter_multi_mode(fp32, set ? kScatterSet : kScatterAdd, N, R, dptr, dslot, delta, scale, 0.0, 0.0,
+                            nullptr, X, s);
+}
+
+void launch_scatter_multi_mode(bool fp32, int mode, int N, int R, const int* dptr, const int* dslot,
+                               const void* delta, const double* scale, double c1, double c2, double* DV, double* X,
+                               hipStream_t s) {
+  switch (mode) {
+    case kScatterAdd: scatter_multi_prec<kScatterAdd>(fp32, N, R, dptr, dslot, delta, scale, c1, c2, DV, X, s); break;
+    case kScatterSet: scatter_multi_prec<kScatterSet>(fp32, N, R, dptr, dslot, delta, scale, c1, c2, DV, X, s); break;
+    case kChebFirstSet:
+      scatter_multi_prec<kChebFirstSet>(fp32, N, R, dptr, dslot, delta, scale, c1, c2, DV, X, s);
+      break;
+    case kChebFirstAdd:
+      scatter_multi_prec<kChebFirstAdd>(fp32, N, R, dptr, dslot, delta, scale, c1, c2, DV, X, s);
+      break;
+    default: scatter_multi_prec<kChebNext>(fp32, N, R, dptr, dslot, delta, scale, c1, c2, DV, X, s); break;
   }
 }
 

@@ -19,6 +19,10 @@ void launch_patch_gemm(bool fp32, int count, int nmax, const int4* meta, const i
                        const double* T, int R, void* delta, hipStream_t s);
 void launch_scatter_multi(bool fp32, bool set, int N, int R, const int* dptr, const int* dslot, const void* delta,
                           const double* scale, double* X, hipStream_t s);
+// the same with any ScatterMode of kernels.hpp (direction DV: [N][R] like X)
+void launch_scatter_multi_mode(bool fp32, int mode, int N, int R, const int* dptr, const int* dslot,
+                               const void* delta, const double* scale, double c1, double c2, double* DV, double* X,
+                               hipStream_t s);
 void launch_dense_gemm(int N, int R, const double* M, const double* Rv, double* E, hipStream_t s);
 // row chunks of the column reductions (fixes their summation order)
 constexpr int kColBlocks = 256;

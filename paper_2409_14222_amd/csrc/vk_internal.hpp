@@ -1,6 +1,7 @@
 // Internal data structures of the vk library (host side).
 #pragma once
 
+#include <complex>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -76,7 +77,7 @@ struct LevelHost {
   // patches (host_patches.cpp)
   std::vector<int> pptr, pdofs;   // patch i: pdofs[pptr[i] .. pptr[i+1])
   std::vector<int> dptr, dslot;   // DoF d: slots dslot[dptr[d] .. dptr[d+1]) ascending patch id
-  std::vector<double> scale;      // omega / multiplicity
+  std::vector<double> scale;      // smoother weight: (omega, or 1 for Chebyshev) x (1 / multiplicity, or 1)
   std::vector<int> order;         // patch processing order (largest first)
   std::vector<int64_t> inv_off;   // element offset of each patch inverse (indexed by patch id)
   int64_t inv_elems = 0;
@@ -118,5 +119,8 @@ void dof_coords_sv(const LevelHost& L, double* xyz, int* kind);
 // Top-left N x N block of the inverse of the bordered matrix [K z; z^T 0],
 // z = constant pressure / sqrt(#pressure); row-major.
 std::vector<double> bordered_inverse(const LevelHost& L);
+// eigenvalues of the upper Hessenberg n x n matrix H (row-major); false on
+// non-finite input or no convergence
+bool hessenberg_eigs(int n, const double* H, std::vector<std::complex<double>>& ev);
 
 }  // namespace vk

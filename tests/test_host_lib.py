@@ -227,3 +227,75 @@ def test_symmetric_tiled_storage_size():
             inf = H.level_info(l)
             assert inf.inv_elems_tri == int((nb * (nb + 1) // 2 * 64).sum())
             assert inf.inv_elems_tri < inf.sum_n2 or n.max() <= 8
+
+
+def _match_eigs(a, b, tol):
+    """Each of a matched to a distinct nearest entry of b (greedy on sorted distance)."""
+    a, b = list(a), list(b)
+    assert len(a) == len(b)
+    for z in a:
+        i = int(np.argmin([abs(z - w) for w in b]))
+        assert abs(z - b[i]) <= tol, (z, b[i])
+        b.pop(i)
+
+
+def test_hessenberg_eigenvalues_match_dense_eigensolver():
+    """The library's QR iteration against LAPACK's on Hessenberg matrices with real and complex
+    spectra, a zero subdiagonal (split matrix), a 1 x 1 and a 2 x 2 rotation, and the Hessenberg
+    matrices of Arnoldi on nonsymmetric operators; for a tight cluster under a non-normal part, whose
+    eigenvalues no two backward-stable methods need to agree on, only the backward error."""
+    rng = np.random.default_rng(11)
+    cases = [np.array([[3.5]]), np.array([[0.0, -2.0], [2.0, 0.0]])]
+    for n in (3, 5, 10, 30, 60):
+        cases.append(np.triu(rng.standard_normal((n, n)), -1))
+    S = np.triu(rng.standard_normal((8, 8)), -1)
+    S[4, 3] = 0.0
+    cases.append(S)
+    arnoldi = []
+    for n, spread in ((10, 1.0), (40, 1.0), (40, 0.0)):
+        # spread 0: a tight cluster under a non-normal upper part (ill-conditioned eigenvalues)
+        d = np.linspace(0.2, 2.0, n) if spread else 1.0 + 0.01 * rng.standard_normal(n)
+        A = np.diag(d) + 0.3 / np.sqrt(n) * np.triu(rng.standard_normal((n, n)), 1)
+        Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+        A = Q @ A @ Q.T
+        V = np.zeros((n, n + 1)); Hm = np.zeros((n + 1, n))
+        v = rng.standard_normal(n); V[:, 0] = v / np.linalg.norm(v)
+        for j in range(n):
+            w = A @ V[:, j]
+            for _ in range(2):
+                h = V[:, : j + 1].T @ w
+                w -= V[:, : j + 1] @ h
+                Hm[: j + 1, j] += h
+            Hm[j + 1, j] = np.linalg.norm(w)
+            V[:, j + 1] = w / Hm[j + 1, j]
+        (cases if spread else arnoldi).append(Hm[:n, :n])
+    for H in cases + arnoldi:
+        got = vk.hessenberg_eigenvalues(H)
+        nrm = np.linalg.norm(H, 2)
+        # backward error: each value is an exact eigenvalue of a matrix within a few ulps of H
+        for z in got:
+            assert np.linalg.svd(H - z * np.eye(H.shape[0]), compute_uv=False)[-1] <= 1e-13 * nrm * H.shape[0]
+        assert abs(got.sum() - np.trace(H)) <= 1e-13 * nrm * H.shape[0]
+    for H in cases:
+        got = vk.hessenberg_eigenvalues(H)
+        want = np.linalg.eigvals(H)
+        _match_eigs(got, want, 1e-9 * max(1.0, np.abs(H).max()) * H.shape[0])
+        assert abs(got.real.max() - want.real.max()) <= 1e-10 * max(1.0, np.abs(H).max()) * H.shape[0]
+
+
+def test_hessenberg_eigenvalues_reject_bad_input():
+    with pytest.raises(vk.VkError) as e:
+        vk.hessenberg_eigenvalues(np.array([[1.0, np.nan], [1.0, 2.0]]))
+    assert e.value.code == vk.VK_ENAN
+    re = np.empty(1)
+    assert vk.lib.vk_hessenberg_eigenvalues(0, re.ctypes.data, re.ctypes.data, re.ctypes.data) == vk.VK_EINVAL
+
+
+def test_chebyshev_options_are_validated():
+    for kw in ({"smoother": 2}, {"weighting": 5}, {"smoother": vk.VK_SMOOTH_CHEBYSHEV, "est_steps": 201},
+               {"est_steps": -1}):
+        with pytest.raises(vk.VkError) as e:
+            vk.Hierarchy(2, 2, 3, **kw)
+        assert e.value.code == vk.VK_EINVAL, kw
+    H = vk.Hierarchy(2, 2, 3, smoother=vk.VK_SMOOTH_CHEBYSHEV, weighting=vk.VK_WEIGHT_NONE)
+    assert H.level_info(1).cheb_lambda == 0.0  # no estimate before vk_patches_setup
