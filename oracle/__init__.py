@@ -16,7 +16,7 @@ there is no blocking, fusion or reordering beyond what the paper states.
 Modules
 -------
 quad      Gauss-Legendre rules and the collapsed (conical) rules on simplices
-lagrange  equispaced P_k Lagrange bases on the reference simplex (Vandermonde)
+lagrange  equispaced P_k Lagrange bases on the reference simplex (barycentric product form)
 mesh      structured simplicial meshes of the unit square / cube
 fields    manufactured solutions and forcing fields
 th        Taylor-Hood assembly: DoF numbering, K = [A B^T; B 0], rhs, transfers

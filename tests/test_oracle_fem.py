@@ -66,6 +66,34 @@ def test_lagrange_kronecker_and_partition_of_unity(dim, k):
         assert np.allclose(B.grad(x)[:, :, d], fd, atol=1e-6)
 
 
+@pytest.mark.parametrize("dim,k", [(2, 1), (2, 3), (2, 4), (3, 2), (3, 3)])
+def test_product_form_equals_vandermonde_basis(dim, k):
+    """The closed product form and the monomial Vandermonde route define the same polynomials;
+    at these orders the Vandermonde route is accurate (condition below 1e4)."""
+    B, V = lagrange.LagrangeBasis(dim, k), lagrange.VandermondeBasis(dim, k)
+    rng = np.random.default_rng(3)
+    x = rng.random((40, dim)) / dim
+    assert np.abs(B.eval(x) - V.eval(x)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("k", [6, 7, 8])
+def test_high_order_basis_is_nodal_and_exact(k):
+    """k = 6..8 (the Vandermonde route loses up to 8 digits here): Kronecker property to a few
+    roundings, partition of unity, and exact reproduction of a degree-k polynomial."""
+    B = lagrange.LagrangeBasis(2, k)
+    assert np.abs(B.eval(B.nodes) - np.eye(len(B.nodes))).max() <= 1e-13
+    rng = np.random.default_rng(1)
+    x = rng.random((30, 2)) / 2
+    assert np.abs(B.eval(x).sum(1) - 1.0).max() <= 1e-12
+    f = lambda p: (p[:, 0] - 0.3) ** (k - 2) * (p[:, 1] + 0.2) ** 2 - p[:, 0] * p[:, 1] ** (k - 1)
+    assert np.abs(B.eval(x) @ f(B.nodes) - f(x)).max() <= 1e-12
+    h = 1e-6
+    for d in range(2):
+        e = np.zeros(2); e[d] = h
+        fd = (B.eval(x + e) - B.eval(x - e)) / (2 * h)
+        assert np.abs(B.grad(x)[:, :, d] - fd).max() <= 1e-4
+
+
 # ---------------------------------------------------------------- element matrices
 @pytest.mark.parametrize("dim,k", [(2, 2), (2, 4), (3, 2)])
 def test_strain_form_kernel_is_rigid_motions(dim, k):
