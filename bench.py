@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # file invalidates them (reported as null).
 # Sources: profiles/patch_apply_p4p3_64_fp64.md, profiles/many_rhs_sv_p3dp2_64.md
 MEASURED_TRAFFIC = {
-    ("kernels.hip", "6eefdc788bf69268", "p4p3-64", "fp64", 1): 540.4e6,
-    ("kernels_multi.hip", "eebd8d9c6d769573", "sv-p3dp2-64", "fp32", 64): 555.2e6,
+    ("patch_apply.hip", "1e8a2ebd31d75985", "p4p3-64", "fp64", 1): 540.7e6,
+    ("patch_gemm.hip", "83fec5634a94b9c4", "sv-p3dp2-64", "fp32", 64): 562.8e6,
 }
 
 
@@ -53,21 +53,23 @@ def kernel_source_hash(name):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def cpu_sample(workload, iterations):
-    """Oracle timing (run in a child process with one BLAS/OpenMP thread)."""
+def cpu_sample(spec, iterations):
+    """Oracle timing (run in a child process with one BLAS/OpenMP thread); spec = workload:smoother:weighting."""
     import numpy as np
 
     import synth
     from oracle import fields, solve
+    workload, smoother, weighting = spec.split(":")
     w = WORKLOADS[workload]
     dim = w.get("dim", 2)
+    kw = dict(smoother=smoother, weighting=weighting)
     if w.get("family") == "sv":
         g = synth.forcing_coeffs(synth.SEED)
         H, V = solve.setup(2, w["k"], w["n0"], w["levels"], 1.0, lambda nu: fields.random_sine_field(g, nu),
-                           family="sv")
+                           family="sv", **kw)
     else:
         H, V = solve.setup(dim, w["k"], w["n0"], w["levels"], 1.0,
-                           fields.cube_mms if dim == 3 else fields.baseline_mms)
+                           fields.cube_mms if dim == 3 else fields.baseline_mms, **kw)
     L = H.finest
     v = synth.vector(L.N, 1)
     v /= np.linalg.norm(v)
@@ -161,6 +163,48 @@ def serve_bench(args):
     print(json.dumps(out))
 
 
+def paper_grid(args):
+    """Iteration counts at the paper's experiment settings (Sec. 4): 5x5 coarsest mesh cut from top left
+    to bottom right, the paper's manufactured solution, zero initial guess, unrestarted FGMRES (at most
+    100 iterations) to a 1e-10 relative residual, V(nu, nu) with nu = 1..4, l = 1..4 refinements; for
+    each order k and smoother (damped additive Vanka, omega 0.5, 1/multiplicity weights; Chebyshev on
+    [lambda / 4, 1.1 lambda] with unweighted or 1/multiplicity-weighted patch sums).  One JSON line per
+    (k, l, smoother) with the iteration counts, the solve times and the per-level estimates."""
+    import numpy as np
+    import torch
+
+    import paper_2409_14222_amd as vk
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    smoothers = [("damped", vk.VK_SMOOTH_DAMPED, vk.VK_WEIGHT_MULTIPLICITY),
+                 ("chebyshev", vk.VK_SMOOTH_CHEBYSHEV, vk.VK_WEIGHT_NONE),
+                 ("chebyshev-weighted", vk.VK_SMOOTH_CHEBYSHEV, vk.VK_WEIGHT_MULTIPLICITY)]
+    for k in [int(v) for v in args.grid_k.split(",")]:
+        for ell in [int(v) for v in args.grid_levels.split(",")]:
+            for name, sm, wt in smoothers:
+                t0 = time.perf_counter()
+                H = vk.Hierarchy(k, 5, ell + 1, forcing=vk.VK_F_PAPER_MMS, smoother=sm, weighting=wt)
+                H.bind(max_restart=100).setup()
+                t_setup = time.perf_counter() - t0
+                b = torch.tensor(H.rhs(), device="cuda")
+                x = torch.empty_like(b)
+                its, ms = {}, {}
+                for nu in (1, 2, 3, 4):
+                    H.solve(b, x, restart=100, maxit=100, nu_pre=nu, nu_post=nu)  # warm-up
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    r = H.solve(b, x, restart=100, maxit=100, nu_pre=nu, nu_post=nu)
+                    torch.cuda.synchronize()
+                    ms[nu] = 1e3 * (time.perf_counter() - t1)
+                    its[nu] = r["iterations"] if r["converged"] else None
+                lam = [H.level_info(l).cheb_lambda for l in range(1, ell + 1)] if sm else []
+                print(json.dumps({"k": k, "l": ell, "n": 5 << ell, "dofs": H.level_info(ell).n_free,
+                                  "smoother": name, "iterations": its, "solve_ms": ms,
+                                  "lambda": lam, "setup_s": t_setup}), flush=True)
+                del H
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +223,14 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-pool-gb", type=int, default=96)
+    ap.add_argument("--smoother", default="damped", choices=["damped", "chebyshev"],
+                    help="chebyshev: Chebyshev-accelerated additive Vanka on [lambda/4, 1.1 lambda] (Sec. 3)")
+    ap.add_argument("--weighting", default=None, choices=["multiplicity", "none"],
+                    help="patch-sum weights; default: multiplicity for damped, none for chebyshev")
+    ap.add_argument("--paper-grid", action="store_true",
+                    help="iteration counts at the paper's settings (5x5 coarsest mesh, unrestarted FGMRES)")
+    ap.add_argument("--grid-k", default="2,3,4,5,6")
+    ap.add_argument("--grid-levels", default="1,2,3,4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy (y = x), the reference for HBM counter scaling")
@@ -206,6 +258,9 @@ def main():
     if args.serve:
         serve_bench(args)
         return
+    if args.paper_grid:
+        paper_grid(args)
+        return
 
     import numpy as np
     import torch
@@ -222,9 +277,14 @@ def main():
     torch.cuda.set_stream(stream)
     t0 = time.perf_counter()
     dim = w.get("dim", 2)
+    cheb = args.smoother == "chebyshev"
+    if args.weighting is None:
+        args.weighting = "none" if cheb else "multiplicity"
     H = vk.Hierarchy(w["k"], w["n0"], w["levels"], dim=dim, store=store,
                      forcing=vk.VK_F_CUBE_MMS if dim == 3 else vk.VK_F_BASELINE_MMS,
-                     family=vk.VK_SV if w.get("family") == "sv" else vk.VK_TH)
+                     family=vk.VK_SV if w.get("family") == "sv" else vk.VK_TH,
+                     smoother=vk.VK_SMOOTH_CHEBYSHEV if cheb else vk.VK_SMOOTH_DAMPED,
+                     weighting=vk.VK_WEIGHT_NONE if args.weighting == "none" else vk.VK_WEIGHT_MULTIPLICITY)
     t_host = time.perf_counter() - t0
     t0 = time.perf_counter()
     R = args.nrhs
@@ -285,7 +345,7 @@ def main():
     apply_bytes = inv_bytes + info.sum_n * 4 + info.sum_n * R * (8 + s)
     apply_flops = 2.0 * info.sum_n2 * R
     avg_s = kms / 1e3 / max(launches, 1)
-    src = "kernels.hip" if R == 1 else "kernels_multi.hip"
+    src = "patch_apply.hip" if R == 1 else "patch_gemm.hip"
     achieved = apply_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
     out = {
         "metric": "Stokes solves/s to 1e-10 rel. residual",
@@ -302,7 +362,7 @@ def main():
         "data": "synthetic (manufactured solution)",
         "config": {"workload": w["desc"], "dofs_free": info.n_free, "nnz": info.nnz, "patches": info.n_patches,
                    "patch_dofs_sum": info.sum_n, "max_patch": info.max_n, "store": args.store,
-                   "graphs": args.graphs},
+                   "graphs": args.graphs, "smoother": args.smoother, "weighting": args.weighting},
         "iterations": its_mean,
         "nrhs": R,
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
@@ -331,7 +391,8 @@ def main():
     if not args.no_cpu_baseline:
         env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
                    HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
-        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample", args.workload,
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample",
+                            f"{args.workload}:{args.smoother}:{args.weighting}",
                             "--cpu-iterations", str(int(round(its_mean)))], capture_output=True, text=True, env=env,
                            timeout=900)
         if r.returncode == 0:

@@ -79,7 +79,7 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.dslot = cv.take<int>(lh.dslot.size());
     d.order = cv.take<int>(lh.order.size());
     d.classes = cv.take<int>(lh.order.size());
-    d.tri = R == 1;
+    d.tri = R == 1 && lh.max_n <= kTiledMaxN;
     d.inv_off = cv.take<int64_t>(lh.inv_off.size());
     d.meta = cv.take<int4>(lh.order.size());
     d.scale = cv.take<double>(lh.scale.size());
@@ -87,6 +87,20 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.delta = cv.take<char>(lh.pdofs.size() * es * R);
     if (cheb) d.cd = cv.take<double>((size_t)lh.N * R);
   }
+  // scratch of the global-memory inversion (patches above 224 DoFs), shared by the levels
+  int64_t big_n = 0;
+  int big_count = 0;
+  for (int l = 1; l < L; ++l) {
+    const LevelHost& lh = Hs[l];
+    if (lh.max_n <= kClassLimit[3]) continue;
+    big_n = std::max<int64_t>(big_n, lh.max_n);
+    int cnt = 0;
+    for (int i = 0; i + 1 < (int)lh.pptr.size(); ++i) cnt += lh.pptr[i + 1] - lh.pptr[i] > kClassLimit[3];
+    big_count = std::max(big_count, cnt);
+  }
+  h->big_slots = std::min(big_count, kBigSlots);
+  h->big_slot_elems = big_n * big_n;
+  h->big_scratch = h->big_slots ? cv.take<double>((size_t)h->big_slots * h->big_slot_elems) : nullptr;
   const int N = Hs.back().N;
   h->V = cv.take<double>((size_t)(max_restart + 1) * N * R);
   h->Z = cv.take<double>((size_t)max_restart * N * R);
@@ -598,9 +612,11 @@ namespace {
 
 void require_multi(const vk_hierarchy* h, int R) {
   require(R >= 1 && R <= h->max_rhs, VK_EINVAL, "nrhs exceeds the max_rhs the workspace was bound for");
-  if (!h->fp32())
-    for (int l = 1; l < h->L(); ++l)
+  for (int l = 1; l < h->L(); ++l) {
+    if (!h->fp32())
       require(h->H[l].max_n <= 128, VK_EINVAL, "FP64 inverses with many right-hand sides need patches <= 128 DoFs");
+    require(h->H[l].max_n <= 512, VK_EINVAL, "many right-hand sides need patches <= 512 DoFs");
+  }
 }
 
 // sqrt of the column dot products <A_c, B_c> on the host
@@ -778,7 +794,7 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
     require(p.dim == 2 || p.dim == 3, VK_EINVAL, "dim must be 2 or 3");
     require(p.family == VK_TH || (p.family == VK_SV && p.dim == 2), VK_EINVAL, "unsupported family");
     if (p.family == VK_SV) require(p.k >= 2 && p.k <= 4, VK_EINVAL, "Scott-Vogelius supports 2 <= k <= 4");
-    require(p.k >= 2 && p.k <= (p.dim == 2 ? 6 : 2), VK_EINVAL, "unsupported order k");
+    require(p.k >= 2 && p.k <= (p.dim == 2 ? 8 : 2), VK_EINVAL, "unsupported order k");
     require(p.n_coarse >= 1 && p.n_levels >= 2 && p.n_levels <= 12, VK_EINVAL, "bad hierarchy size");
     require(p.viscosity > 0 && std::isfinite(p.viscosity), VK_EINVAL, "viscosity must be positive");
     require(opts->omega > 0 && std::isfinite(opts->omega), VK_EINVAL, "omega must be positive");
@@ -821,7 +837,7 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
         L.pgrp = row_groups(L.P, 8);
         L.ptgrp = row_groups(L.PT, 8);
         build_patches(L, opts->construct, opts->omega, opts->store);
-        require(L.max_n <= 224, VK_EINVAL, "patches above 224 DoFs are not supported");
+        require(L.max_n <= kClassLimit[kClasses - 1], VK_EINVAL, "patches above 512 DoFs are not supported");
         if (opts->smoother == VK_SMOOTH_CHEBYSHEV || opts->weighting == VK_WEIGHT_NONE) {
           // W (and omega for the damped sweep only)
           const double om = opts->smoother == VK_SMOOTH_CHEBYSHEV ? 1.0 : opts->omega;
@@ -835,11 +851,10 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
     for (int l = 1; l < p.n_levels; ++l) {
       const LevelHost& L = h->H[l];
       std::vector<int>& cl = h->class_lists[l];
-      const int lim[4] = {32, 64, 128, 224};
-      for (int c = 0; c < 4; ++c)
+      for (int c = 0; c < kClasses; ++c)
         for (int i = 0; i + 1 < (int)L.pptr.size(); ++i) {
           const int n = L.pptr[i + 1] - L.pptr[i];
-          if (n <= lim[c] && (c == 0 || n > lim[c - 1])) cl.push_back(i);
+          if (n <= kClassLimit[c] && (c == 0 || n > kClassLimit[c - 1])) cl.push_back(i);
         }
     }
     *out = h.release();
@@ -931,12 +946,11 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_r
         up(d.meta, h->meta_host.back(), s);
       }
       up(d.scale, L.scale, s);
-      const int lim[4] = {32, 64, 128, 224};
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < kClasses; ++c) {
         d.class_count[c] = 0;
         for (int i = 0; i + 1 < (int)L.pptr.size(); ++i) {
           const int n = L.pptr[i + 1] - L.pptr[i];
-          if (n <= lim[c] && (c == 0 || n > lim[c - 1])) d.class_count[c]++;
+          if (n <= kClassLimit[c] && (c == 0 || n > kClassLimit[c - 1])) d.class_count[c]++;
         }
       }
     }
@@ -962,10 +976,10 @@ vk_status vk_patches_setup(vk_hierarchy* h) {
       // tile padding beyond n must read as zero (the register-resident inversion writes only n x n)
       HIPCHECK(hipMemsetAsync(d.inv, 0,
                               (size_t)(d.tri ? lh.inv_elems_tri : lh.inv_elems) * (h->fp32() ? 4 : 8), s));
-      const int lim[4] = {32, 64, 128, 224};
-      for (int c = 0; c < 4; ++c) {
-        launch_gather_invert(lim[c], h->fp32(), d.tri, d.class_count[c], d.classes + first, d.pptr, d.pdofs,
-                             d.rowptr, d.col, d.val, d.inv_off, d.inv, h->singular, s);
+      for (int c = 0; c < kClasses; ++c) {
+        launch_gather_invert(kClassLimit[c], h->fp32(), d.tri, d.class_count[c], d.classes + first, d.pptr,
+                             d.pdofs, d.rowptr, d.col, d.val, d.inv_off, d.inv, h->singular, h->big_scratch,
+                             h->big_slot_elems, h->big_slots, s);
         check_launch();
         first += d.class_count[c];
       }

@@ -20,6 +20,14 @@
 
 namespace vk {
 
+// patch size classes of the setup (one inversion kernel each): n <= 32, 64, 128, 224, 512
+constexpr int kClasses = 5;
+constexpr int kClassLimit[kClasses] = {32, 64, 128, 224, 512};
+// patches above 224 DoFs: inverted in global scratch slots (at most this many at once), stored
+// column-major (the symmetric tiled storage is limited to 224)
+constexpr int kBigSlots = 256;
+constexpr int kTiledMaxN = 224;
+
 struct DevLevel {
   int N = 0, nvel = 0, J = 0;
   double mean_row = 0, p_mean = 0, pt_mean = 0;
@@ -39,7 +47,7 @@ struct DevLevel {
   double cheb_lambda = 0.0, cheb_theta = 0.0, cheb_delta = 0.0;  // estimate and interval centre / half-width
   int cheb_steps = 0;
   double* M = nullptr;  // coarsest level
-  int class_count[4] = {0, 0, 0, 0};  // patches with n <= 32, <= 64, <= 128, <= 224 (ids in `classes`)
+  int class_count[kClasses] = {0, 0, 0, 0, 0};  // patches per size class of kClassLimit (ids in `classes`)
   // launch shapes (never change results): lanes per CSR row of K, P, P^T;
   // waves per patch for the large (n > 64, first in `order`) and small patches
   int k_lanes = 32, p_lanes = 8, pt_lanes = 8, waves_large = 1, waves_small = 1, n_large = 0;
@@ -83,6 +91,9 @@ struct vk_hierarchy {
   int *nvc = nullptr, *mask = nullptr;  // per-column iteration counts / active flags (multi-RHS)
   std::vector<DevLevel> D;
   double *V = nullptr, *Z = nullptr, *bb = nullptr, *r = nullptr, *partial = nullptr, *small = nullptr, *ydev = nullptr;
+  double* big_scratch = nullptr;  // kBigSlots-limited slots for the inversion of patches above 224 DoFs
+  int big_slots = 0;
+  int64_t big_slot_elems = 0;
   int* singular = nullptr;
   std::vector<double> ybuf;
   std::vector<std::vector<int4>> meta_host;  // staging of the per-patch metadata uploads

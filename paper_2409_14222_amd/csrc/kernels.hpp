@@ -1,4 +1,4 @@
-// Launchers of the gfx950 kernels (kernels.hip).  All enqueue on `s`.
+// Launchers of the gfx950 kernels (kernels.hip; the patch apply in patch_apply.hip).  All enqueue on `s`.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,11 +18,13 @@ int csr_default_lanes(double mean_row);
 // float: column-major (leading dimension rounded to 2 doubles / 4 floats), or
 // with `tri` the symmetric tiled storage (the 8 x 8 tiles on and below the
 // diagonal; the padding must have been zeroed).  `list` holds `count` patch ids
-// whose size is <= nmax (32, 64, 128 or 224).  `singular` receives the smallest
-// patch id with a zero pivot (initialise to INT_MAX).
+// whose size is <= nmax (32, 64, 128, 224 or 512).  `singular` receives the smallest
+// patch id with a zero pivot (initialise to INT_MAX).  nmax 512 (blocked, unpivoted, in
+// global memory) needs `slots` scratch slots of slot_elems >= n^2 doubles each.
 void launch_gather_invert(int nmax, bool fp32, bool tri, int count, const int* list, const int* pptr,
                           const int* pdofs, const int* rowptr, const int* col, const double* val,
-                          const int64_t* inv_off, void* inv, int* singular, hipStream_t s);
+                          const int64_t* inv_off, void* inv, int* singular, double* scratch, int64_t slot_elems,
+                          int slots, hipStream_t s);
 
 // Dense K_i tiles (n_i x n_i, column-major, packed) of patches first..first+count-1.
 void launch_gather_dense(int nmax, int first, int count, const int* pptr, const int* pdofs, const int* rowptr,

@@ -1,4 +1,4 @@
-// Launchers of the many-right-hand-side kernels (kernels_multi.hip).
+// Launchers of the many-right-hand-side kernels (kernels_multi.hip; the patch GEMMs in patch_gemm.hip).
 // Multivectors are row-major [N][R], 1 <= R <= 64.
 #pragma once
 

@@ -44,6 +44,11 @@ def hier():
     H64 = vk.Hierarchy(3, 4, 3, family=vk.VK_SV).bind(max_rhs=16).setup()
     H32 = vk.Hierarchy(3, 4, 3, family=vk.VK_SV, store=vk.VK_STORE_FP32).bind(max_rhs=16).setup()
     out["sv"] = (H64, H32, OH, OV)
+    print("[gpu-multi] building P8-P7 4x4 hierarchies (patches of 435 DoFs)", flush=True)
+    OH, OV = solve.setup(2, 8, 2, 2, 1.0, fields.baseline_mms)
+    H64 = vk.Hierarchy(8, 2, 2).bind(max_rhs=16).setup()
+    H32 = vk.Hierarchy(8, 2, 2, store=vk.VK_STORE_FP32).bind(max_rhs=16).setup()
+    out[8] = (H64, H32, OH, OV)
     return out
 
 
@@ -64,12 +69,13 @@ def test_smooth_multi_fp64(hier, k):
             assert np.abs(got[:, c] - ref).max() <= 8 * EPS * cb * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("k", [2, 4, "sv"])
+@pytest.mark.parametrize("k", [2, 4, "sv", 8])
 def test_smooth_multi_fp32_matrix_cores(hier, k):
-    """FP32 inverses on the matrix cores: error within the FP32 rounding bound."""
+    """FP32 inverses on the matrix cores: error within the FP32 rounding bound (k = 8: 8-wave
+    workgroups for the 435-DoF patches)."""
     _, H32, OH, OV = hier[k]
     R = 16
-    l = 2
+    l = len(OH.levels) - 1
     L, S = OH.levels[l], OV.smoothers[l]
     B = synth.vector(L.N * R, 1000).reshape(L.N, R)
     X = _dev(np.zeros((L.N, R)))
