@@ -202,6 +202,10 @@ vk_status vk_level_csr(const vk_hierarchy* h, int level, int* h_rowptr, int* h_c
 vk_status vk_level_prolongation(const vk_hierarchy* h, int level, int* h_rowptr, int* h_col,
                                 double* h_val); /* P from level-1 to level, rows = level's DoFs */
 vk_status vk_level_patches(const vk_hierarchy* h, int level, int* h_ptr, int* h_dofs);
+/* The coarsest level's solve operator as computed at create (row-major n_free x n_free, host):
+ * the leading block of the inverse of the bordered matrix [K_0 z; z^T 0], z the normalised
+ * constant pressure (blocked Gauss-Jordan with partial pivoting in FP64). */
+vk_status vk_coarse_inverse(const vk_hierarchy* h, double* h_out);
 vk_status vk_dof_coords(const vk_hierarchy* h, int level, double* h_xyz /* N*dim */, int* h_kind /* N */);
 /* Finest-level right-hand side, made consistent (constant pressure removed). */
 vk_status vk_rhs(const vk_hierarchy* h, double* h_b);

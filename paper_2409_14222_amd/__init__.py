@@ -130,6 +130,7 @@ _SIGS = {
     "vk_server_stats_get": ([_p, _P(vk_server_stats)], _c_int),
     "vk_load_random": ([_c_int, _c_int, _c_int, _p, _p], _c_int),
     "vk_hessenberg_eigenvalues": ([_c_int, _p, _p, _p], _c_int),
+    "vk_coarse_inverse": ([_p, _p], _c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -222,6 +223,12 @@ class Hierarchy:
         ptr = np.empty(inf.n_patches + 1, np.int32); dofs = np.empty(inf.sum_n, np.int32)
         check(lib.vk_level_patches(self.h, level, _ptr(ptr), _ptr(dofs)))
         return ptr, dofs
+
+    def coarse_inverse(self):
+        n = self.level_info(0).n_free
+        out = np.empty((n, n))
+        check(lib.vk_coarse_inverse(self.h, _ptr(out)))
+        return out
 
     def dof_coords(self, level):
         inf = self.level_info(level)

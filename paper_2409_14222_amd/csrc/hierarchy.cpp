@@ -1054,6 +1054,14 @@ vk_status vk_level_patches(const vk_hierarchy* h, int level, int* ptr, int* dofs
   });
 }
 
+vk_status vk_coarse_inverse(const vk_hierarchy* h, double* out) {
+  return guarded([&]() -> vk_status {
+    require(h && out, VK_EINVAL, "null argument");
+    std::copy(h->coarse_M.begin(), h->coarse_M.end(), out);
+    return VK_OK;
+  });
+}
+
 vk_status vk_dof_coords(const vk_hierarchy* h, int level, double* xyz, int* kind) {
   return guarded([&]() -> vk_status {
     require(h && xyz && kind, VK_EINVAL, "null argument");

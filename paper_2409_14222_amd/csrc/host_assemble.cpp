@@ -5,6 +5,8 @@
 // matrix), and the prolongation by nodal interpolation (Sec. 3, grid
 // transfers: natural embedding of the nested spaces).
 #include <algorithm>
+#include <array>
+#include <thread>
 #include <cmath>
 
 #include "vk_internal.hpp"
@@ -226,7 +228,12 @@ void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
   }
 
   if (with_rhs) L.b.assign(L.N, 0.0);
-  std::vector<double> Aloc((size_t)nlv * nlv), Bloc((size_t)nbp * nlv), Floc(nlv), uD(nlv);
+  struct Shape {
+    std::array<double, 9> key;
+    std::vector<double> A, B;
+  };
+  std::vector<Shape> shapes;
+  std::vector<double> Floc(nlv), uD(nlv);
   std::vector<double> gx((size_t)nbv * dim);
   for (int e = 0; e < ncell; ++e) {
     const Cell& C = L.cells[e];
@@ -263,36 +270,53 @@ void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
       }
       gl[0][d] = -s;
     }
-    std::fill(Aloc.begin(), Aloc.end(), 0.0);
-    std::fill(Bloc.begin(), Bloc.end(), 0.0);
-    std::fill(Floc.begin(), Floc.end(), 0.0);
-    for (int q = 0; q < nq; ++q) {
-      const double w = rule.w[q] * adet;
-      const double* dq = &dv[(size_t)q * nbv * (dim + 1)];
-      for (int j = 0; j < nbv; ++j)
-        for (int d = 0; d < dim; ++d) {
-          double s = 0.0;
-          for (int i = 0; i <= dim; ++i) s += dq[j * (dim + 1) + i] * gl[i][d];
-          gx[j * dim + d] = s;
-        }
-      // A[(i,c),(j,d)] += w nu (delta_cd grad phi_i . grad phi_j + d_d phi_i d_c phi_j)
-      for (int i = 0; i < nbv; ++i)
-        for (int j = 0; j < nbv; ++j) {
-          double dot = 0.0;
-          for (int d = 0; d < dim; ++d) dot += gx[i * dim + d] * gx[j * dim + d];
-          for (int c = 0; c < dim; ++c)
-            for (int d = 0; d < dim; ++d) {
-              double v = gx[i * dim + d] * gx[j * dim + c];
-              if (c == d) v += dot;
-              Aloc[(size_t)(i * dim + c) * nlv + (j * dim + d)] += w * nu * v;
-            }
-        }
-      // B[q,(j,d)] += -w psi_q d_d phi_j
-      const double* pq = &php[(size_t)q * nbp];
-      for (int p = 0; p < nbp; ++p)
+    // the element matrices depend on the cell only through its Jacobian: computed once per
+    // distinct Jacobian (the structured meshes have a handful) and reused bitwise
+    std::array<double, 9> key{};
+    for (int d = 0; d < dim; ++d)
+      for (int i = 0; i < dim; ++i) key[d * 3 + i] = J[d][i];
+    auto hit = std::find_if(shapes.begin(), shapes.end(), [&](const Shape& sh) { return sh.key == key; });
+    if (hit == shapes.end()) {
+      Shape sh;
+      sh.key = key;
+      sh.A.assign((size_t)nlv * nlv, 0.0);
+      sh.B.assign((size_t)nbp * nlv, 0.0);
+      for (int q = 0; q < nq; ++q) {
+        const double w = rule.w[q] * adet;
+        const double* dq = &dv[(size_t)q * nbv * (dim + 1)];
         for (int j = 0; j < nbv; ++j)
-          for (int d = 0; d < dim; ++d) Bloc[(size_t)p * nlv + j * dim + d] -= w * pq[p] * gx[j * dim + d];
-      if (with_rhs) {
+          for (int d = 0; d < dim; ++d) {
+            double s = 0.0;
+            for (int i = 0; i <= dim; ++i) s += dq[j * (dim + 1) + i] * gl[i][d];
+            gx[j * dim + d] = s;
+          }
+        // A[(i,c),(j,d)] += w nu (delta_cd grad phi_i . grad phi_j + d_d phi_i d_c phi_j)
+        for (int i = 0; i < nbv; ++i)
+          for (int j = 0; j < nbv; ++j) {
+            double dot = 0.0;
+            for (int d = 0; d < dim; ++d) dot += gx[i * dim + d] * gx[j * dim + d];
+            for (int c = 0; c < dim; ++c)
+              for (int d = 0; d < dim; ++d) {
+                double v = gx[i * dim + d] * gx[j * dim + c];
+                if (c == d) v += dot;
+                sh.A[(size_t)(i * dim + c) * nlv + (j * dim + d)] += w * nu * v;
+              }
+          }
+        // B[q,(j,d)] += -w psi_q d_d phi_j
+        const double* pq = &php[(size_t)q * nbp];
+        for (int p = 0; p < nbp; ++p)
+          for (int j = 0; j < nbv; ++j)
+            for (int d = 0; d < dim; ++d) sh.B[(size_t)p * nlv + j * dim + d] -= w * pq[p] * gx[j * dim + d];
+      }
+      shapes.push_back(std::move(sh));
+      hit = shapes.end() - 1;
+    }
+    const std::vector<double>& Aloc = hit->A;
+    const std::vector<double>& Bloc = hit->B;
+    std::fill(Floc.begin(), Floc.end(), 0.0);
+    for (int q = 0; q < nq && with_rhs; ++q) {
+      const double w = rule.w[q] * adet;
+      {
         double x[3] = {0, 0, 0};
         for (int d = 0; d < dim; ++d) {
           double s = C.v[0][d] / (double)unit;
@@ -565,29 +589,76 @@ std::vector<double> bordered_inverse(const LevelHost& L) {
   for (double v : A) amax = std::max(amax, std::fabs(v));
   const double tiny = M * 2.220446049250313e-16 * amax;
   std::vector<int> perm(M);
-  for (int c = 0; c < M; ++c) {
-    int p = c;
-    double best = std::fabs(A[(size_t)c * M + c]);
-    for (int r = c + 1; r < M; ++r) {
-      double v = std::fabs(A[(size_t)r * M + c]);
-      if (v > best) { best = v; p = r; }
+  // Blocked by panels of B pivots, the same pivots and updates as the column-by-column
+  // algorithm: the panel (all rows, B columns) is eliminated step by step (pivot search on the
+  // current panel column, full-row swaps); then, with D the pivot rows of the panel as they were
+  // before (C the other rows) and R the pivot rows outside the panel,
+  //   pivot rows -> D^{-1} R,   other rows -> E - C D^{-1} R      (E: their columns outside the panel)
+  // with the trailing product split over host threads by rows (each entry summed in panel order,
+  // independent of the thread count).
+  constexpr int B = 32;
+  const int nth = std::max(1, std::min<int>({16, (int)std::thread::hardware_concurrency(), M / 64}));
+  std::vector<double> P0((size_t)M * B), Rn((size_t)B * M);
+  for (int c0 = 0; c0 < M; c0 += B) {
+    const int cb = std::min(B, M - c0);
+    for (int r = 0; r < M; ++r)
+      for (int t = 0; t < cb; ++t) P0[(size_t)r * B + t] = A[(size_t)r * M + c0 + t];
+    for (int sidx = 0; sidx < cb; ++sidx) {
+      const int c = c0 + sidx;
+      int p = c;
+      double best = std::fabs(A[(size_t)c * M + c]);
+      for (int r = c + 1; r < M; ++r) {
+        const double v = std::fabs(A[(size_t)r * M + c]);
+        if (v > best) { best = v; p = r; }
+      }
+      require(best > tiny, VK_ESINGULAR, "coarsest bordered matrix is singular (refine the coarsest mesh)");
+      perm[c] = p;
+      if (p != c) {
+        for (int j = 0; j < M; ++j) std::swap(A[(size_t)c * M + j], A[(size_t)p * M + j]);
+        for (int t = 0; t < B; ++t) std::swap(P0[(size_t)c * B + t], P0[(size_t)p * B + t]);
+      }
+      double* ac = &A[(size_t)c * M + c0];  // the pivot row's panel part
+      const double piv = ac[sidx];
+      for (int t = 0; t < cb; ++t) ac[t] = t == sidx ? 1.0 / piv : ac[t] / piv;
+      for (int r = 0; r < M; ++r) {
+        if (r == c) continue;
+        double* ar = &A[(size_t)r * M + c0];
+        const double f = ar[sidx];
+        if (f == 0.0) continue;
+        for (int t = 0; t < cb; ++t) ar[t] = t == sidx ? -f * ac[t] : ar[t] - f * ac[t];
+      }
     }
-    require(best > tiny, VK_ESINGULAR, "coarsest bordered matrix is singular (refine the coarsest mesh)");
-    perm[c] = p;
-    if (p != c)
-      for (int j = 0; j < M; ++j) std::swap(A[(size_t)c * M + j], A[(size_t)p * M + j]);
-    const double piv = A[(size_t)c * M + c];
-    A[(size_t)c * M + c] = 1.0;
-    for (int j = 0; j < M; ++j) A[(size_t)c * M + j] /= piv;
-    for (int r = 0; r < M; ++r) {
-      if (r == c) continue;
-      const double f = A[(size_t)r * M + c];
-      if (f == 0.0) continue;
-      A[(size_t)r * M + c] = 0.0;
-      double* ar = &A[(size_t)r * M];
-      const double* ac = &A[(size_t)c * M];
-      for (int j = 0; j < M; ++j) ar[j] -= f * ac[j];
+    // Rn = D^{-1} R: the panel rows of the pivots now hold D^{-1}
+    for (int sidx = 0; sidx < cb; ++sidx)
+      for (int j = 0; j < M; ++j) {
+        if (j >= c0 && j < c0 + cb) continue;
+        double acc = 0.0;
+        for (int t = 0; t < cb; ++t) acc += A[(size_t)(c0 + sidx) * M + c0 + t] * A[(size_t)(c0 + t) * M + j];
+        Rn[(size_t)sidx * M + j] = acc;
+      }
+    auto trailing = [&](int t0) {
+      const int r0 = (int)((int64_t)M * t0 / nth), r1 = (int)((int64_t)M * (t0 + 1) / nth);
+      for (int r = r0; r < r1; ++r) {
+        if (r >= c0 && r < c0 + cb) continue;
+        double* ar = &A[(size_t)r * M];
+        for (int t = 0; t < cb; ++t) {
+          const double f = P0[(size_t)r * B + t];
+          if (f == 0.0) continue;
+          const double* rn = &Rn[(size_t)t * M];
+          for (int j = 0; j < c0; ++j) ar[j] -= f * rn[j];
+          for (int j = c0 + cb; j < M; ++j) ar[j] -= f * rn[j];
+        }
+      }
+    };
+    {
+      std::vector<std::thread> pool;
+      for (int t = 1; t < nth; ++t) pool.emplace_back(trailing, t);
+      trailing(0);
+      for (auto& th : pool) th.join();
     }
+    for (int sidx = 0; sidx < cb; ++sidx)
+      for (int j = 0; j < M; ++j)
+        if (j < c0 || j >= c0 + cb) A[(size_t)(c0 + sidx) * M + j] = Rn[(size_t)sidx * M + j];
   }
   for (int c = M - 1; c >= 0; --c)
     if (perm[c] != c)

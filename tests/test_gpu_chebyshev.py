@@ -130,6 +130,7 @@ def test_vcycle_and_solve(cheb):
         n = min(its, 10) + 1
         gh, oh = res["history"][:n], np.array(hist[:n])
         assert np.all(np.abs(gh - oh) <= 1e-6 * oh + 1e-9 * oh[0])
+        assert np.all(np.abs(res["history"][: its + 1] - np.array(hist)) <= 1e-6 * hist[0])
 
 
 def test_many_rhs_columns_match_oracle():

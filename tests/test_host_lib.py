@@ -300,3 +300,19 @@ def test_chebyshev_options_are_validated():
         assert e.value.code == vk.VK_EINVAL, kw
     H = vk.Hierarchy(2, 2, 3, smoother=vk.VK_SMOOTH_CHEBYSHEV, weighting=vk.VK_WEIGHT_NONE)
     assert H.level_info(1).cheb_lambda == 0.0  # no estimate before vk_patches_setup
+
+
+@pytest.mark.parametrize("k,n0", [(2, 4), (4, 4), (8, 2)])
+def test_coarse_inverse_matches_dense_inverse(k, n0):
+    """The blocked Gauss-Jordan of the coarsest bordered matrix against LAPACK's inverse of the
+    oracle's bordered matrix (several 32-pivot panels and a ragged last one at every size here)."""
+    H = vk.Hierarchy(k, n0, 2)
+    OH = th.THHierarchy(2, k, n0, 2, 1.0, fields.baseline_mms)
+    L0 = OH.levels[0]
+    z = L0.nullvec()
+    Kb = np.block([[L0.K.toarray(), z[:, None]], [z[None, :], np.zeros((1, 1))]])
+    ref = np.linalg.inv(Kb)[: L0.N, : L0.N]
+    got = H.coarse_inverse()
+    c = np.linalg.cond(Kb)
+    print(f"k={k}: N0={L0.N} cond {c:.1e} err {np.abs(got - ref).max() / np.abs(ref).max():.1e}")
+    assert np.abs(got - ref).max() <= 8 * Kb.shape[0] * np.finfo(float).eps * c * np.abs(ref).max()
