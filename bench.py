@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # file invalidates them (reported as null).
 # Sources: profiles/patch_apply_p4p3_64_fp64.md, profiles/many_rhs_sv_p3dp2_64.md
 MEASURED_TRAFFIC = {
-    ("patch_apply.hip", "1e8a2ebd31d75985", "p4p3-64", "fp64", 1): 540.7e6,
-    ("patch_gemm.hip", "83fec5634a94b9c4", "sv-p3dp2-64", "fp32", 64): 562.8e6,
+    ("patch_apply.hip", "6d321e57784babdb", "p4p3-64", "fp64", 1): 540.6e6,
+    ("patch_gemm.hip", "55e68640323c960e", "sv-p3dp2-64", "fp32", 64): 555.2e6,
 }
 
 
@@ -205,6 +205,65 @@ def paper_grid(args):
                 del H
 
 
+def stopping_study(args):
+    """Stopping-criteria study at the paper's settings (Sec. 4, stopping criteria): 5x5 coarsest mesh,
+    the paper's manufactured solution (zero pressure), unrestarted FGMRES from a zero guess, V(nu, nu).
+    The same system is solved with relative tolerances 1e-2 * 2^-i, i = 0, 1, ..., down to 1e-15 or
+    until a solve no longer converges within 100 iterations; after every solve the library measures the
+    relative H^1 velocity error and the mean-free L^2 pressure error.  The tolerance needed for a
+    quantity is the largest one from which on every stricter solve stays within 1 % of the error of
+    the strictest solve.  One JSON line per (k, l, smoother)."""
+    import numpy as np
+    import torch
+
+    import paper_2409_14222_amd as vk
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    nu = args.study_nu
+    smoothers = {"damped": (vk.VK_SMOOTH_DAMPED, vk.VK_WEIGHT_MULTIPLICITY),
+                 "chebyshev": (vk.VK_SMOOTH_CHEBYSHEV, vk.VK_WEIGHT_NONE)}
+    for k in [int(v) for v in args.grid_k.split(",")]:
+        for ell in [int(v) for v in args.grid_levels.split(",")]:
+            for name in args.study_smoothers.split(","):
+                sm, wt = smoothers[name]
+                H = vk.Hierarchy(k, 5, ell + 1, forcing=vk.VK_F_PAPER_MMS, smoother=sm, weighting=wt)
+                H.bind(max_restart=100).setup()
+                b = torch.tensor(H.rhs(), device="cuda")
+                x = torch.empty_like(b)
+                rows = []
+                i = 0
+                while True:
+                    rtol = 1e-2 * 2.0 ** -i
+                    if rtol < 1e-15:
+                        break
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    r = H.solve(b, x, restart=100, maxit=100, rtol=rtol, nu_pre=nu, nu_post=nu)
+                    torch.cuda.synchronize()
+                    ms = 1e3 * (time.perf_counter() - t0)
+                    if not r["converged"]:
+                        break
+                    eu, ep = H.solution_errors(x.cpu().numpy())
+                    rows.append({"rtol": rtol, "its": r["iterations"], "e_u": eu, "e_p": ep, "ms": ms})
+                    i += 1
+                out = {"k": k, "l": ell, "n": 5 << ell, "dofs": H.level_info(ell).n_free, "smoother": name,
+                       "nu": nu, "rows": rows}
+                if rows:
+                    for key, tag in (("e_u", "velocity"), ("e_p", "pressure")):
+                        ref = rows[-1][key]
+                        need = rows[-1]
+                        for row in reversed(rows):
+                            if row[key] <= 1.01 * ref:
+                                need = row
+                            else:
+                                break
+                        out[tag] = {"rtol": need["rtol"], "its": need["its"], "error": need[key],
+                                    "ms": need["ms"], "strictest_error": ref}
+                print(json.dumps(out), flush=True)
+                del H
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +288,10 @@ def main():
                     help="patch-sum weights; default: multiplicity for damped, none for chebyshev")
     ap.add_argument("--paper-grid", action="store_true",
                     help="iteration counts at the paper's settings (5x5 coarsest mesh, unrestarted FGMRES)")
+    ap.add_argument("--stopping-study", action="store_true",
+                    help="tolerance needed for discretisation-level errors (paper settings, --grid-k/--grid-levels)")
+    ap.add_argument("--study-nu", type=int, default=1)
+    ap.add_argument("--study-smoothers", default="damped,chebyshev")
     ap.add_argument("--grid-k", default="2,3,4,5,6")
     ap.add_argument("--grid-levels", default="1,2,3,4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -260,6 +323,9 @@ def main():
         return
     if args.paper_grid:
         paper_grid(args)
+        return
+    if args.stopping_study:
+        stopping_study(args)
         return
 
     import numpy as np

@@ -202,6 +202,14 @@ vk_status vk_level_csr(const vk_hierarchy* h, int level, int* h_rowptr, int* h_c
 vk_status vk_level_prolongation(const vk_hierarchy* h, int level, int* h_rowptr, int* h_col,
                                 double* h_val); /* P from level-1 to level, rows = level's DoFs */
 vk_status vk_level_patches(const vk_hierarchy* h, int level, int* h_ptr, int* h_dofs);
+/* Discretisation errors of a finest-level solution h_x (host, n_free values) against the
+ * manufactured solution of the problem's field (Sec. 4, stopping criteria): h_err[0] = the
+ * relative H^1 error of the velocity ||u - u_h||_1 / ||u||_1 (boundary nodes take the exact
+ * nodal values), h_err[1] = the L^2 error of the pressure after removing the L^2 mean of
+ * p - p_h (the exact pressures are zero).  Collapsed Gauss quadrature with k + 6 points per
+ * direction on every cell.  VK_EINVAL for VK_F_RANDOM (no exact solution). */
+vk_status vk_solution_errors(const vk_hierarchy* h, const double* h_x, double* h_err);
+
 /* The coarsest level's solve operator as computed at create (row-major n_free x n_free, host):
  * the leading block of the inverse of the bordered matrix [K_0 z; z^T 0], z the normalised
  * constant pressure (blocked Gauss-Jordan with partial pivoting in FP64). */

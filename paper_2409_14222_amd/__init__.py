@@ -131,6 +131,7 @@ _SIGS = {
     "vk_load_random": ([_c_int, _c_int, _c_int, _p, _p], _c_int),
     "vk_hessenberg_eigenvalues": ([_c_int, _p, _p, _p], _c_int),
     "vk_coarse_inverse": ([_p, _p], _c_int),
+    "vk_solution_errors": ([_p, _p, _p], _c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -223,6 +224,13 @@ class Hierarchy:
         ptr = np.empty(inf.n_patches + 1, np.int32); dofs = np.empty(inf.sum_n, np.int32)
         check(lib.vk_level_patches(self.h, level, _ptr(ptr), _ptr(dofs)))
         return ptr, dofs
+
+    def solution_errors(self, x):
+        """(relative H^1 velocity error, mean-free L^2 pressure error) of a finest-level solution (host array)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        err = np.empty(2)
+        check(lib.vk_solution_errors(self.h, _ptr(x), _ptr(err)))
+        return float(err[0]), float(err[1])
 
     def coarse_inverse(self):
         n = self.level_info(0).n_free

@@ -1054,6 +1054,15 @@ vk_status vk_level_patches(const vk_hierarchy* h, int level, int* ptr, int* dofs
   });
 }
 
+vk_status vk_solution_errors(const vk_hierarchy* h, const double* x, double* err) {
+  return guarded([&]() -> vk_status {
+    require(h && x && err, VK_EINVAL, "null argument");
+    require(h->pr.p.forcing != VK_F_RANDOM, VK_EINVAL, "the random forcing has no exact solution");
+    solution_errors(h->H.back(), h->pr, x, &err[0], &err[1]);
+    return VK_OK;
+  });
+}
+
 vk_status vk_coarse_inverse(const vk_hierarchy* h, double* out) {
   return guarded([&]() -> vk_status {
     require(h && out, VK_EINVAL, "null argument");

@@ -89,7 +89,7 @@ void setup_mesh(LevelHost& L) {
 }
 
 // exact velocity, forcing (returns dim components)
-static void field_u(const Problem& pr, const double* x, double* u) {
+void field_u(const Problem& pr, const double* x, double* u) {
   const double X = x[0], Y = x[1];
   switch (pr.p.forcing) {
     case VK_F_BASELINE_MMS:
@@ -109,6 +109,31 @@ static void field_u(const Problem& pr, const double* x, double* u) {
     }
     default:
       for (int c = 0; c < pr.p.dim; ++c) u[c] = 0.0;
+  }
+}
+
+// exact velocity gradient g[c * dim + d] = d u_c / d x_d of the manufactured fields (zero otherwise)
+void field_grad_u(const Problem& pr, const double* x, double* g) {
+  const double X = x[0], Y = x[1];
+  const double sx = std::sin(PI * X), cx = std::cos(PI * X), sy = std::sin(PI * Y), cy = std::cos(PI * Y);
+  switch (pr.p.forcing) {
+    case VK_F_BASELINE_MMS:
+      g[0] = PI * cx * sy;  g[1] = PI * sx * cy;
+      g[2] = -PI * sx * cy; g[3] = -PI * cx * sy;
+      break;
+    case VK_F_PAPER_MMS:
+      g[0] = PI * cx * cy;  g[1] = -PI * sx * sy;
+      g[2] = PI * sx * sy;  g[3] = -PI * cx * cy;
+      break;
+    case VK_F_CUBE_MMS: {
+      const double sz = std::sin(PI * x[2]), cz = std::cos(PI * x[2]);
+      g[0] = PI * cx * (cy - cz); g[1] = -PI * sx * sy;       g[2] = PI * sx * sz;
+      g[3] = PI * sx * sy;        g[4] = PI * cy * (cz - cx); g[5] = -PI * sy * sz;
+      g[6] = -PI * sz * sx;       g[7] = PI * sy * sz;        g[8] = PI * cz * (cx - cy);
+      break;
+    }
+    default:
+      for (int c = 0; c < pr.p.dim * pr.p.dim; ++c) g[c] = 0.0;
   }
 }
 
@@ -141,21 +166,13 @@ static inline void node_lattice(const Cell& c, const std::vector<int>& a, int di
   }
 }
 
-void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
-  const int dim = L.dim, k = L.k;
-  const double nu = pr.p.viscosity;
-  setup_mesh(L);
-  const int unit = L.unit;
-
-  const Basis vb = make_basis(dim, k), pb = make_basis(dim, k - 1);
-  const int nbv = vb.size(), nbp = pb.size();
-  const int nlv = nbv * dim;
-  const SimplexRule rule = simplex_rule(dim, k + 3);
-  const int nq = rule.npts;
-
-  // local -> global DoFs of every cell
+// local -> global DoFs of every cell (-1: Dirichlet velocity)
+void cell_dof_maps(const LevelHost& L, const Basis& vb, const Basis& pb, std::vector<int>& cvd,
+                   std::vector<int>& cpd) {
+  const int dim = L.dim, nbv = vb.size(), nbp = pb.size(), nlv = nbv * dim;
   const int ncell = (int)L.cells.size();
-  std::vector<int> cvd((size_t)ncell * nlv), cpd((size_t)ncell * nbp);
+  cvd.assign((size_t)ncell * nlv, 0);
+  cpd.assign((size_t)ncell * nbp, 0);
   for (int e = 0; e < ncell; ++e) {
     int G[3];
     for (int j = 0; j < nbv; ++j) {
@@ -171,6 +188,146 @@ void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
       cpd[(size_t)e * nbp + j] = L.pres_dof(G);
     }
   }
+}
+
+// Discretisation errors of a solution on level L (Sec. 4, stopping criteria): the relative H^1
+// error of the velocity (Dirichlet nodes carry the exact nodal values, as in the lifting) and the
+// L^2 error of the pressure after removing the L^2 mean of the difference, integrated with the
+// collapsed Gauss rule of k + 6 points per direction.
+void solution_errors(const LevelHost& L, const Problem& pr, const double* x, double* e_u, double* e_p) {
+  const int dim = L.dim, k = L.k, unit = L.unit;
+  const Basis vb = make_basis(dim, k), pb = make_basis(dim, k - 1);
+  const int nbv = vb.size(), nbp = pb.size(), nlv = nbv * dim;
+  const SimplexRule rule = simplex_rule(dim, k + 6);
+  const int nq = rule.npts;
+  std::vector<int> cvd, cpd;
+  cell_dof_maps(L, vb, pb, cvd, cpd);
+  std::vector<double> phv((size_t)nq * nbv), php((size_t)nq * nbp), dv((size_t)nq * nbv * (dim + 1));
+  for (int q = 0; q < nq; ++q) {
+    double kl[4], kl1[4];
+    for (int i = 0; i <= dim; ++i) {
+      kl[i] = k * rule.lam[q * (dim + 1) + i];
+      kl1[i] = (k - 1) * rule.lam[q * (dim + 1) + i];
+    }
+    vb.eval(kl, &phv[(size_t)q * nbv]);
+    pb.eval(kl1, &php[(size_t)q * nbp]);
+    vb.dlam(&rule.lam[q * (dim + 1)], &dv[(size_t)q * nbv * (dim + 1)]);
+  }
+  double e1 = 0, n1 = 0, ep_int = 0, ep2 = 0, area = 0;
+  std::vector<double> U(nlv), P(nbp);
+  for (int e = 0; e < (int)L.cells.size(); ++e) {
+    const Cell& C = L.cells[e];
+    double J[3][3], Ji[3][3];
+    for (int d = 0; d < dim; ++d)
+      for (int i = 0; i < dim; ++i) J[d][i] = (double)(C.v[i + 1][d] - C.v[0][d]) / unit;
+    double det;
+    if (dim == 2) {
+      det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      Ji[0][0] = J[1][1] / det; Ji[0][1] = -J[0][1] / det;
+      Ji[1][0] = -J[1][0] / det; Ji[1][1] = J[0][0] / det;
+    } else {
+      det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+            J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+      Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+      Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+      Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+      Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+      Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+      Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+      Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+      Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    }
+    const double adet = std::fabs(det);
+    double gl[4][3];
+    for (int d = 0; d < dim; ++d) {
+      double sgl = 0.0;
+      for (int i = 1; i <= dim; ++i) {
+        gl[i][d] = Ji[i - 1][d];
+        sgl += Ji[i - 1][d];
+      }
+      gl[0][d] = -sgl;
+    }
+    const int* vd = &cvd[(size_t)e * nlv];
+    const int* pd = &cpd[(size_t)e * nbp];
+    for (int j = 0; j < nbv; ++j) {
+      if (vd[j * dim] >= 0) {
+        for (int c = 0; c < dim; ++c) U[j * dim + c] = x[vd[j * dim + c]];
+      } else {
+        int G[3];
+        node_lattice(C, vb.nodes[j], dim, G);
+        double xn[3];
+        for (int d = 0; d < dim; ++d) xn[d] = (double)G[d] / (k * unit);
+        field_u(pr, xn, &U[j * dim]);
+      }
+    }
+    for (int p = 0; p < nbp; ++p) P[p] = x[pd[p]];
+    for (int q = 0; q < nq; ++q) {
+      const double w = rule.w[q] * adet;
+      double xq[3];
+      for (int d = 0; d < dim; ++d) {
+        double sx = C.v[0][d] / (double)unit;
+        for (int i = 1; i <= dim; ++i) sx += J[d][i - 1] * rule.lam[q * (dim + 1) + i];
+        xq[d] = sx;
+      }
+      double uh[3] = {0, 0, 0}, guh[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      const double* vq = &phv[(size_t)q * nbv];
+      const double* dq = &dv[(size_t)q * nbv * (dim + 1)];
+      for (int j = 0; j < nbv; ++j) {
+        double gphi[3];
+        for (int d = 0; d < dim; ++d) {
+          double sg = 0.0;
+          for (int i = 0; i <= dim; ++i) sg += dq[j * (dim + 1) + i] * gl[i][d];
+          gphi[d] = sg;
+        }
+        for (int c = 0; c < dim; ++c) {
+          uh[c] += U[j * dim + c] * vq[j];
+          for (int d = 0; d < dim; ++d) guh[c * dim + d] += U[j * dim + c] * gphi[d];
+        }
+      }
+      double ue[3], gue[9];
+      field_u(pr, xq, ue);
+      field_grad_u(pr, xq, gue);
+      double se = 0.0, sn = 0.0;
+      for (int c = 0; c < dim; ++c) {
+        se += (ue[c] - uh[c]) * (ue[c] - uh[c]);
+        sn += ue[c] * ue[c];
+        for (int d = 0; d < dim; ++d) {
+          se += (gue[c * dim + d] - guh[c * dim + d]) * (gue[c * dim + d] - guh[c * dim + d]);
+          sn += gue[c * dim + d] * gue[c * dim + d];
+        }
+      }
+      e1 += w * se;
+      n1 += w * sn;
+      double ph = 0.0;
+      const double* pq = &php[(size_t)q * nbp];
+      for (int p = 0; p < nbp; ++p) ph += P[p] * pq[p];
+      const double dp = 0.0 - ph;  // the manufactured pressures are zero
+      ep_int += w * dp;
+      ep2 += w * dp * dp;
+      area += w;
+    }
+  }
+  const double mean = ep_int / area;
+  *e_u = std::sqrt(e1 / n1);
+  *e_p = std::sqrt(std::max(ep2 - 2.0 * mean * ep_int + mean * mean * area, 0.0));
+}
+
+void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
+  const int dim = L.dim, k = L.k;
+  const double nu = pr.p.viscosity;
+  setup_mesh(L);
+  const int unit = L.unit;
+
+  const Basis vb = make_basis(dim, k), pb = make_basis(dim, k - 1);
+  const int nbv = vb.size(), nbp = pb.size();
+  const int nlv = nbv * dim;
+  const SimplexRule rule = simplex_rule(dim, k + 3);
+  const int nq = rule.npts;
+
+  const int ncell = (int)L.cells.size();
+  std::vector<int> cvd, cpd;
+  cell_dof_maps(L, vb, pb, cvd, cpd);
 
   // sparsity pattern: the element closure (all DoF pairs sharing a cell, no
   // pressure-pressure pairs); rows collected through DoF -> cells lists

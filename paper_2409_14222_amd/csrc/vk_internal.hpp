@@ -102,6 +102,11 @@ struct Problem {
 // cells, DoF numbering and counts of a level (dim, k, n, family set by the caller)
 void setup_mesh(LevelHost& L);
 void build_level(LevelHost& L, const Problem& pr, bool with_rhs);
+void cell_dof_maps(const LevelHost& L, const Basis& vb, const Basis& pb, std::vector<int>& cvd, std::vector<int>& cpd);
+void field_u(const Problem& pr, const double* x, double* u);
+void field_grad_u(const Problem& pr, const double* x, double* g);
+// relative H^1 velocity error and mean-free L^2 pressure error of x (free DoFs of L)
+void solution_errors(const LevelHost& L, const Problem& pr, const double* x, double* e_u, double* e_p);
 void build_prolongation(const LevelHost& coarse, LevelHost& fine);
 void build_patches(LevelHost& L, int construct, double omega, int store);
 // ordering, inverse map, relaxation scale and inverse storage of collected patch DoF lists

@@ -12,7 +12,7 @@ import pytest
 import scipy.sparse as sp
 
 import paper_2409_14222_amd as vk
-from oracle import fields, patches, solve, th
+from oracle import fields, norms, patches, solve, th
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -316,3 +316,36 @@ def test_coarse_inverse_matches_dense_inverse(k, n0):
     c = np.linalg.cond(Kb)
     print(f"k={k}: N0={L0.N} cond {c:.1e} err {np.abs(got - ref).max() / np.abs(ref).max():.1e}")
     assert np.abs(got - ref).max() <= 8 * Kb.shape[0] * np.finfo(float).eps * c * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("case", ["p2p1", "p4p3_paper", "p3p2_3d", "sv"])
+def test_solution_errors_match_oracle_norms(case):
+    """The library's discretisation-error norms against the oracle's, on the discrete solution
+    (errors near the discretisation level) and on a perturbed vector (large errors, both terms)."""
+    import scipy.sparse.linalg as spla
+    from oracle import sv
+    if case == "p2p1":
+        H = vk.Hierarchy(2, 4, 2); OH = th.THHierarchy(2, 2, 4, 2, 1.0, fields.baseline_mms); ferr = norms.errors
+    elif case == "p4p3_paper":
+        H = vk.Hierarchy(4, 2, 2, forcing=vk.VK_F_PAPER_MMS); OH = th.THHierarchy(2, 4, 2, 2, 1.0, fields.paper_mms)
+        ferr = norms.errors
+    elif case == "p3p2_3d":
+        H = vk.Hierarchy(2, 2, 2, dim=3, forcing=vk.VK_F_CUBE_MMS)
+        OH = th.THHierarchy(3, 2, 2, 2, 1.0, fields.cube_mms); ferr = norms.errors
+    else:
+        H = vk.Hierarchy(3, 2, 2, family=vk.VK_SV); OH = sv.SVHierarchy(3, 2, 2, 1.0, fields.baseline_mms)
+        ferr = lambda L, x: sv.errors(L, x)[:2]
+    L = OH.finest
+    z = L.nullvec()
+    b = solve.consistent_rhs(L)
+    Kb = sp.bmat([[L.K, sp.csr_matrix(z[:, None])], [sp.csr_matrix(z[None, :]), None]]).tocsc()
+    x = spla.spsolve(Kb, np.concatenate([b, [0.0]]))[: L.N]
+    rng = np.random.default_rng(2)
+    for v in (x, x + 0.05 * rng.standard_normal(L.N)):
+        got = H.solution_errors(v)
+        ref = ferr(L, v)
+        print(case, got, ref)
+        assert abs(got[0] - ref[0]) <= 1e-11 * ref[0] + 1e-15
+        assert abs(got[1] - ref[1]) <= 1e-11 * ref[1] + 1e-15
+    with pytest.raises(vk.VkError):
+        vk.Hierarchy(2, 2, 2, forcing=vk.VK_F_RANDOM, coeffs=np.ones((2, 2, 2))).solution_errors(np.zeros(10))
