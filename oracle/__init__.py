@@ -20,6 +20,7 @@ lagrange  equispaced P_k Lagrange bases on the reference simplex (barycentric pr
 mesh      structured simplicial meshes of the unit square / cube
 fields    manufactured solutions and forcing fields
 th        Taylor-Hood assembly: DoF numbering, K = [A B^T; B 0], rhs, transfers
+qk        Taylor-Hood (Q_k, Q_{k-1}) on squares: tensor bases, transfers, composite patches
 patches   composite ("topological") Vanka patches, Sec. 3.1
 vanka     additive subspace correction (Algorithm 1) as a damped smoother
 chebyshev its Chebyshev acceleration with a per-level Arnoldi eigenvalue estimate

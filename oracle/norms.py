@@ -13,7 +13,7 @@ from . import quad
 
 def errors(level, x):
     dim, k = level.dim, level.k
-    qp, qw = quad.simplex_rule(dim, k + 6)
+    qp, qw = level.quad_rule(k + 6)
     Pv, Gv, Pp = level.vb.eval(qp), level.vb.grad(qp), level.pb.eval(qp)
     F = level.field
     e1 = n1 = 0.0

@@ -75,6 +75,10 @@ class THLevel:
             out.append(tuple(int(g) for g in G))
         return out
 
+    def quad_rule(self, q):
+        """Quadrature on the reference cell with q Gauss points per direction."""
+        return quad.simplex_rule(self.dim, q)
+
     def cell_geometry(self, cell):
         v0 = np.array(cell[0], dtype=float) / self.n
         J = np.stack([np.array(cell[d + 1], dtype=float) / self.n - v0 for d in range(self.dim)], axis=1)
@@ -109,7 +113,7 @@ class THLevel:
 
     def _assemble(self):
         dim, k = self.dim, self.k
-        self._rule = quad.simplex_rule(dim, k + 3)
+        self._rule = self.quad_rule(k + 3)
         qp = self._rule[0]
         self._Gv = self.vb.grad(qp)
         self._Pp = self.pb.eval(qp)
