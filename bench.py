@@ -164,9 +164,9 @@ def serve_bench(args):
 
 
 def paper_grid(args):
-    """Iteration counts at the paper's experiment settings (Sec. 4): 5x5 coarsest mesh cut from top left
-    to bottom right, the paper's manufactured solution, zero initial guess, unrestarted FGMRES (at most
-    100 iterations) to a 1e-10 relative residual, V(nu, nu) with nu = 1..4, l = 1..4 refinements; for
+    """Iteration counts at the paper's experiment settings (Sec. 4): 5x5 coarsest mesh (cut from top
+    left to bottom right, or squares with --grid-family quad), the paper's manufactured solution, zero
+    initial guess, unrestarted FGMRES (at most 100 iterations) to a 1e-10 relative residual, V(nu, nu) with nu = 1..4, l = 1..4 refinements; for
     each order k and smoother (damped additive Vanka, omega 0.5, 1/multiplicity weights; Chebyshev on
     [lambda / 4, 1.1 lambda] with unweighted or 1/multiplicity-weighted patch sums).  One JSON line per
     (k, l, smoother) with the iteration counts, the solve times and the per-level estimates."""
@@ -180,11 +180,12 @@ def paper_grid(args):
     smoothers = [("damped", vk.VK_SMOOTH_DAMPED, vk.VK_WEIGHT_MULTIPLICITY),
                  ("chebyshev", vk.VK_SMOOTH_CHEBYSHEV, vk.VK_WEIGHT_NONE),
                  ("chebyshev-weighted", vk.VK_SMOOTH_CHEBYSHEV, vk.VK_WEIGHT_MULTIPLICITY)]
+    fam = vk.VK_TH_QUAD if args.grid_family == "quad" else vk.VK_TH
     for k in [int(v) for v in args.grid_k.split(",")]:
         for ell in [int(v) for v in args.grid_levels.split(",")]:
             for name, sm, wt in smoothers:
                 t0 = time.perf_counter()
-                H = vk.Hierarchy(k, 5, ell + 1, forcing=vk.VK_F_PAPER_MMS, smoother=sm, weighting=wt)
+                H = vk.Hierarchy(k, 5, ell + 1, forcing=vk.VK_F_PAPER_MMS, smoother=sm, weighting=wt, family=fam)
                 H.bind(max_restart=100).setup()
                 t_setup = time.perf_counter() - t0
                 b = torch.tensor(H.rhs(), device="cuda")
@@ -199,7 +200,8 @@ def paper_grid(args):
                     ms[nu] = 1e3 * (time.perf_counter() - t1)
                     its[nu] = r["iterations"] if r["converged"] else None
                 lam = [H.level_info(l).cheb_lambda for l in range(1, ell + 1)] if sm else []
-                print(json.dumps({"k": k, "l": ell, "n": 5 << ell, "dofs": H.level_info(ell).n_free,
+                print(json.dumps({"family": args.grid_family, "k": k, "l": ell, "n": 5 << ell,
+                                  "dofs": H.level_info(ell).n_free,
                                   "smoother": name, "iterations": its, "solve_ms": ms,
                                   "lambda": lam, "setup_s": t_setup}), flush=True)
                 del H
@@ -227,7 +229,8 @@ def stopping_study(args):
         for ell in [int(v) for v in args.grid_levels.split(",")]:
             for name in args.study_smoothers.split(","):
                 sm, wt = smoothers[name]
-                H = vk.Hierarchy(k, 5, ell + 1, forcing=vk.VK_F_PAPER_MMS, smoother=sm, weighting=wt)
+                H = vk.Hierarchy(k, 5, ell + 1, forcing=vk.VK_F_PAPER_MMS, smoother=sm, weighting=wt,
+                                 family=vk.VK_TH_QUAD if args.grid_family == "quad" else vk.VK_TH)
                 H.bind(max_restart=100).setup()
                 b = torch.tensor(H.rhs(), device="cuda")
                 x = torch.empty_like(b)
@@ -247,8 +250,8 @@ def stopping_study(args):
                     eu, ep = H.solution_errors(x.cpu().numpy())
                     rows.append({"rtol": rtol, "its": r["iterations"], "e_u": eu, "e_p": ep, "ms": ms})
                     i += 1
-                out = {"k": k, "l": ell, "n": 5 << ell, "dofs": H.level_info(ell).n_free, "smoother": name,
-                       "nu": nu, "rows": rows}
+                out = {"family": args.grid_family, "k": k, "l": ell, "n": 5 << ell,
+                       "dofs": H.level_info(ell).n_free, "smoother": name, "nu": nu, "rows": rows}
                 if rows:
                     for key, tag in (("e_u", "velocity"), ("e_p", "pressure")):
                         ref = rows[-1][key]
@@ -292,6 +295,8 @@ def main():
                     help="tolerance needed for discretisation-level errors (paper settings, --grid-k/--grid-levels)")
     ap.add_argument("--study-nu", type=int, default=1)
     ap.add_argument("--study-smoothers", default="damped,chebyshev")
+    ap.add_argument("--grid-family", default="tri", choices=["tri", "quad"],
+                    help="Taylor-Hood on the two-triangle mesh (P_k) or on squares (Q_k)")
     ap.add_argument("--grid-k", default="2,3,4,5,6")
     ap.add_argument("--grid-levels", default="1,2,3,4")
     ap.add_argument("--no-cpu-baseline", action="store_true")

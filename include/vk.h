@@ -60,7 +60,11 @@ enum {
 
 enum {
   VK_TH = 0, /* Taylor-Hood (P_k, P_{k-1}), continuous pressure */
-  VK_SV = 1  /* Scott-Vogelius (P_k, dP_{k-1}) on the barycentric refinement of each level (Sec. 2) */
+  VK_SV = 1, /* Scott-Vogelius (P_k, dP_{k-1}) on the barycentric refinement of each level (Sec. 2) */
+  VK_TH_QUAD = 2 /* Taylor-Hood (Q_k, Q_{k-1}) on the n x n mesh of squares (2D, 2 <= k <= 7): tensor
+                    equispaced Lagrange bases, the same free-DoF numbering as VK_TH (the Q_k nodes
+                    are the points of the P_k lattice), composite patches of vertices, edge
+                    interiors and cell interiors (Sec. 3.1) */
 };
 
 enum {
@@ -78,7 +82,7 @@ enum { VK_WEIGHT_MULTIPLICITY = 0, VK_WEIGHT_NONE = 1 };
 /* Problem statement (Sec. 2 weak form; Sec. 3 hierarchy; Sec. 4 mesh). */
 typedef struct vk_problem {
   int dim;          /* 2 (triangles) or 3 (Kuhn tetrahedra, k = 2 only) */
-  int family;       /* VK_TH, or VK_SV (2D, 2 <= k <= 4, VK_PATCH_MACRO, see below) */
+  int family;       /* VK_TH, VK_SV (2D, 2 <= k <= 4, VK_PATCH_MACRO) or VK_TH_QUAD (2D, 2 <= k <= 7) */
   int k;            /* velocity order, pressure order k-1; 2 <= k <= 6 in 2D */
   int n_coarse;     /* cells per direction on level 0 (>= 1) */
   int n_levels;     /* >= 2 */

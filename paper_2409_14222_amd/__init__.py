@@ -24,7 +24,7 @@ lib = ctypes.CDLL(LIBPATH)
 # ---------------------------------------------------------------- constants (include/vk.h)
 VK_OK, VK_NOT_CONVERGED = 0, 1
 VK_EINVAL, VK_ENOMEM, VK_EHIP, VK_ESINGULAR, VK_ENAN, VK_EBUSY, VK_ESTATE = -1, -2, -3, -4, -5, -6, -7
-VK_TH, VK_SV = 0, 1
+VK_TH, VK_SV, VK_TH_QUAD = 0, 1, 2
 VK_F_BASELINE_MMS, VK_F_PAPER_MMS, VK_F_RANDOM, VK_F_CUBE_MMS = 0, 1, 2, 3
 VK_PATCH_COMPOSITE, VK_PATCH_STAR, VK_PATCH_MACRO = 0, 1, 2
 VK_STORE_FP64, VK_STORE_FP32 = 0, 1

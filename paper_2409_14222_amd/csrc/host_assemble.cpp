@@ -75,6 +75,10 @@ void setup_mesh(LevelHost& L) {
     setup_mesh_sv(L);
     return;
   }
+  if (L.family == VK_TH_QUAD) {
+    setup_mesh_quad(L);
+    return;
+  }
   make_cells(L);
   L.unit = L.n;
   const int Mv = L.k * L.n, Mp = (L.k - 1) * L.n;
@@ -137,7 +141,7 @@ void field_grad_u(const Problem& pr, const double* x, double* g) {
   }
 }
 
-static void field_f(const Problem& pr, const double* x, double* f) {
+void field_f(const Problem& pr, const double* x, double* f) {
   const double nu = pr.p.viscosity;
   if (pr.p.forcing == VK_F_RANDOM) {
     const int M = pr.p.n_modes;
@@ -195,6 +199,10 @@ void cell_dof_maps(const LevelHost& L, const Basis& vb, const Basis& pb, std::ve
 // L^2 error of the pressure after removing the L^2 mean of the difference, integrated with the
 // collapsed Gauss rule of k + 6 points per direction.
 void solution_errors(const LevelHost& L, const Problem& pr, const double* x, double* e_u, double* e_p) {
+  if (L.family == VK_TH_QUAD) {
+    solution_errors_quad(L, pr, x, e_u, e_p);
+    return;
+  }
   const int dim = L.dim, k = L.k, unit = L.unit;
   const Basis vb = make_basis(dim, k), pb = make_basis(dim, k - 1);
   const int nbv = vb.size(), nbp = pb.size(), nlv = nbv * dim;
@@ -314,6 +322,10 @@ void solution_errors(const LevelHost& L, const Problem& pr, const double* x, dou
 }
 
 void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
+  if (L.family == VK_TH_QUAD) {
+    build_level_quad(L, pr, with_rhs);
+    return;
+  }
   const int dim = L.dim, k = L.k;
   const double nu = pr.p.viscosity;
   setup_mesh(L);
@@ -640,6 +652,10 @@ static void locate(int dim, int nc, int kk, const int* G, Cell& cell, double* kl
 void build_prolongation(const LevelHost& C, LevelHost& F) {
   if (F.family == VK_SV) {
     build_prolongation_sv(C, F);
+    return;
+  }
+  if (F.family == VK_TH_QUAD) {
+    build_prolongation_quad(C, F);
     return;
   }
   const int dim = F.dim;

@@ -10,6 +10,10 @@ namespace vk {
 // Gauss-Legendre nodes/weights on [0,1] by Newton iteration on the Legendre
 // polynomial P_q (three-term recurrence), started from the Chebyshev-like guess
 // cos(pi (i + 3/4) / (q + 1/2)).
+static void gauss_legendre01(int q, std::vector<double>& x, std::vector<double>& w);
+
+void gauss_legendre_01(int q, std::vector<double>& x, std::vector<double>& w) { gauss_legendre01(q, x, w); }
+
 static void gauss_legendre01(int q, std::vector<double>& x, std::vector<double>& w) {
   x.assign(q, 0.0);
   w.assign(q, 0.0);

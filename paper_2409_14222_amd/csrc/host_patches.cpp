@@ -53,6 +53,11 @@ void build_patches(LevelHost& L, int construct, double omega, int store) {
     build_patches_macro(L, omega, store);
     return;
   }
+  if (L.family == VK_TH_QUAD) {
+    require(construct == VK_PATCH_COMPOSITE, VK_EINVAL, "quadrilateral levels use composite patches");
+    build_patches_quad(L, omega, store);
+    return;
+  }
   require(L.family == VK_TH, VK_EINVAL, "Scott-Vogelius levels use macro patches");
   Builder B(L);
   const int n = L.n, k = L.k, km = k - 1;

@@ -105,8 +105,17 @@ void build_level(LevelHost& L, const Problem& pr, bool with_rhs);
 void cell_dof_maps(const LevelHost& L, const Basis& vb, const Basis& pb, std::vector<int>& cvd, std::vector<int>& cpd);
 void field_u(const Problem& pr, const double* x, double* u);
 void field_grad_u(const Problem& pr, const double* x, double* g);
+void field_f(const Problem& pr, const double* x, double* f);
 // relative H^1 velocity error and mean-free L^2 pressure error of x (free DoFs of L)
 void solution_errors(const LevelHost& L, const Problem& pr, const double* x, double* e_u, double* e_p);
+// Gauss-Legendre rule on [0, 1] (host_fem.cpp)
+void gauss_legendre_01(int q, std::vector<double>& x, std::vector<double>& w);
+// quadrilateral Taylor-Hood (host_quad.cpp)
+void setup_mesh_quad(LevelHost& L);
+void build_level_quad(LevelHost& L, const Problem& pr, bool with_rhs);
+void build_prolongation_quad(const LevelHost& coarse, LevelHost& fine);
+void build_patches_quad(LevelHost& L, double omega, int store);
+void solution_errors_quad(const LevelHost& L, const Problem& pr, const double* x, double* e_u, double* e_p);
 void build_prolongation(const LevelHost& coarse, LevelHost& fine);
 void build_patches(LevelHost& L, int construct, double omega, int store);
 // ordering, inverse map, relaxation scale and inverse storage of collected patch DoF lists

@@ -100,14 +100,43 @@ def p6p5():
     return H, OH, OV
 
 
+def _quad_fixture(k, n0, nl):
+    import paper_2409_14222_amd as vk
+    from oracle import fields, solve
+    print(f"[gpu] building Q{k}-Q{k - 1} {n0 << (nl - 1)}x{n0 << (nl - 1)} hierarchy", flush=True)
+    H = vk.Hierarchy(k, n0, nl, family=vk.VK_TH_QUAD).bind().setup()
+    OH, OV = solve.setup(2, k, n0, nl, 1.0, fields.baseline_mms, family="qk")
+    return H, OH, OV
+
+
+@pytest.fixture(scope="module")
+def q2q1():
+    """Q2-Q1 on 16x16 squares, levels 4/8/16: vertex patches of 51 DoFs."""
+    return _quad_fixture(2, 4, 3)
+
+
+@pytest.fixture(scope="module")
+def q4q3():
+    """Q4-Q3 on 8x8 squares, levels 2/4/8: vertex (163), edge and cell patches."""
+    return _quad_fixture(4, 2, 3)
+
+
+@pytest.fixture(scope="module")
+def q7q6():
+    """Q7-Q6 on 4x4 squares, levels 2/4: vertex stars of 451 DoFs (global-memory inversion)."""
+    return _quad_fixture(7, 2, 2)
+
+
 # relative solution difference allowed between two 1e-10-residual solves: Taylor-Hood 1e-8;
 # Scott-Vogelius 1e-6, since a relative rhs perturbation of 1e-11 moves the SV 16x16 solution by
 # 1.5e-6 (its small nonzero singular values), measured with a sparse direct solve.  High orders:
 # a random relative rhs perturbation of 1e-10 moves the P6-P5 8x8 solution by up to 1.7e-5 and the
 # P8-P7 4x4 solution by up to 7.3e-5 (sparse direct solves), so two 1e-10-residual solutions may
-# differ by twice that; iteration counts and residual histories are still compared tightly
-XTOL = {"p2p1": 1e-8, "p4p3": 1e-8, "p2p1_3d": 1e-8, "p3dp2_sv": 1e-6, "p6p5": 4e-5, "p8p7": 1.5e-4}
-ALL = ["p2p1", "p4p3", "p2p1_3d", "p3dp2_sv", "p6p5", "p8p7"]
+# differ by twice that; iteration counts and residual histories are still compared tightly.
+# Quadrilaterals, measured the same way: Q2-Q1 16x16 1.4e-7, Q4-Q3 8x8 9.0e-7, Q7-Q6 4x4 1.1e-5
+XTOL = {"p2p1": 1e-8, "p4p3": 1e-8, "p2p1_3d": 1e-8, "p3dp2_sv": 1e-6, "p6p5": 4e-5, "p8p7": 1.5e-4,
+        "q2q1": 3e-7, "q4q3": 2e-6, "q7q6": 2.2e-5}
+ALL = ["p2p1", "p4p3", "p2p1_3d", "p3dp2_sv", "p6p5", "p8p7", "q2q1", "q4q3", "q7q6"]
 
 
 def _cond_bound(S):

@@ -349,3 +349,49 @@ def test_solution_errors_match_oracle_norms(case):
         assert abs(got[1] - ref[1]) <= 1e-11 * ref[1] + 1e-15
     with pytest.raises(vk.VkError):
         vk.Hierarchy(2, 2, 2, forcing=vk.VK_F_RANDOM, coeffs=np.ones((2, 2, 2))).solution_errors(np.zeros(10))
+
+
+@pytest.mark.parametrize("k,n0,nl", [(2, 4, 3), (3, 2, 3), (5, 2, 2), (7, 2, 2)])
+def test_host_assembly_quad_matches_oracle(k, n0, nl):
+    """Quadrilateral Taylor-Hood: the library's host assembly, transfers and patches against the
+    oracle's (independent tensor bases and point location)."""
+    from oracle import qk
+    H = vk.Hierarchy(k, n0, nl, family=vk.VK_TH_QUAD)
+    OH = qk.QKHierarchy(k, n0, nl, 1.0, fields.baseline_mms)
+    for l in range(nl):
+        ol = OH.levels[l]
+        inf = H.level_info(l)
+        assert (inf.n_free, inf.nnz, inf.n_velocity) == (ol.N, ol.K.nnz, ol.nu_free)
+        X, kind = H.dof_coords(l)
+        OX, okind = ol.dof_coords()
+        assert np.array_equal(kind, okind) and np.abs(X - OX).max() < 1e-15
+        rp, col, val = H.csr(l)
+        assert np.array_equal(rp, ol.K.indptr) and np.array_equal(col, ol.K.indices)
+        rowmax = np.maximum.reduceat(np.abs(ol.K.data), ol.K.indptr[:-1])
+        assert np.all(np.abs(val - ol.K.data) <= _asm_bound(ol) * np.finfo(float).eps * np.repeat(rowmax, np.diff(ol.K.indptr)))
+        if l > 0:
+            prp, pcol, pval = H.prolongation(l)
+            P = OH.P[l]
+            assert np.array_equal(prp, P.indptr) and np.array_equal(pcol, P.indices)
+            assert np.abs(pval - P.data).max() <= 1e-14
+            ptr, dofs = H.patches(l)
+            op = patches.build_patches(ol)
+            assert [list(dofs[ptr[i]:ptr[i + 1]]) for i in range(len(op))] == [list(I) for I in op]
+    b = H.rhs()
+    ob = solve.consistent_rhs(OH.finest)
+    assert np.abs(b - ob).max() <= 1e-13 * np.abs(ob).max()
+
+
+def test_quad_errors_and_limits():
+    from oracle import qk
+    H = vk.Hierarchy(3, 2, 2, family=vk.VK_TH_QUAD, forcing=vk.VK_F_PAPER_MMS)
+    OH = qk.QKHierarchy(3, 2, 2, 1.0, fields.paper_mms)
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal(OH.finest.N) * 0.01
+    got, ref = H.solution_errors(x), norms.errors(OH.finest, x)
+    assert abs(got[0] - ref[0]) <= 1e-11 * ref[0] and abs(got[1] - ref[1]) <= 1e-11 * ref[1]
+    for kw in ({"k": 8}, {"k": 2, "dim": 3}, {"k": 3, "construct": vk.VK_PATCH_STAR}):
+        k = kw.pop("k")
+        with pytest.raises(vk.VkError) as e:
+            vk.Hierarchy(k, 2, 2, family=vk.VK_TH_QUAD, **kw)
+        assert e.value.code == vk.VK_EINVAL
