@@ -385,7 +385,7 @@ def main():
     def one_solve():
         if R == 1:
             return [H.solve(b, x, graphs=args.graphs)]
-        return H.solve_multi(b, x, R)[1]
+        return H.solve_multi(b, x, R, graphs=args.graphs)[1]
 
     for _ in range(args.warmup):
         one_solve()

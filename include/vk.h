@@ -263,7 +263,9 @@ vk_status vk_solve(vk_hierarchy* h, const double* d_b, double* d_x, const vk_sol
  * patches of at most 128 DoFs. */
 vk_status vk_smooth_multi(vk_hierarchy* h, int level, const double* d_B, double* d_X, int nrhs, int nsweeps);
 vk_status vk_vcycle_multi(vk_hierarchy* h, const double* d_R, double* d_E, int nrhs, int nu_pre, int nu_post);
-/* info: nrhs entries (caller-owned), one per column.  VK_NOT_CONVERGED if any column missed rtol. */
+/* info: nrhs entries (caller-owned), one per column.  VK_NOT_CONVERGED if any column missed rtol.
+ * use_graphs: every Arnoldi step processes all nrhs columns (finished ones included), so its
+ * kernel sequence depends on (step, nrhs, nu) only and is captured once and replayed. */
 vk_status vk_solve_multi(vk_hierarchy* h, const double* d_B, double* d_X, int nrhs, const vk_solve_opts* opts,
                          vk_solve_info* info);
 /* Finest-level right-hand side (consistent) of the smooth random forcing

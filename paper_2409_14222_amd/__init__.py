@@ -319,9 +319,9 @@ class Hierarchy:
     def vcycle_multi(self, R, E, nrhs, nu_pre=2, nu_post=2):
         check(lib.vk_vcycle_multi(self.h, _ptr(R), _ptr(E), nrhs, nu_pre, nu_post))
 
-    def solve_multi(self, B, X, nrhs, restart=30, maxit=100, rtol=1e-10, nu_pre=2, nu_post=2):
+    def solve_multi(self, B, X, nrhs, restart=30, maxit=100, rtol=1e-10, nu_pre=2, nu_post=2, graphs=False):
         """B, X: row-major [N][nrhs] device tensors.  Returns one result dict per column."""
-        opts = vk_solve_opts(restart, maxit, rtol, nu_pre, nu_post, 0)
+        opts = vk_solve_opts(restart, maxit, rtol, nu_pre, nu_post, int(graphs))
         infos = (vk_solve_info * nrhs)()
         status = check(lib.vk_solve_multi(self.h, _ptr(B), _ptr(X), nrhs, ctypes.byref(opts), infos))
         return status, [{"iterations": i.iterations, "converged": bool(i.converged), "rel_residual": i.rel_residual}

@@ -355,8 +355,9 @@ void arnoldi_step(vk_hierarchy* h, int j, const vk_solve_opts& o) {
 
 // The same step replayed from a HIP graph captured on first use (one graph
 // per (j, restart, nu_pre, nu_post); dropped when launch shapes change).
-void arnoldi_step_graph(vk_hierarchy* h, int j, const vk_solve_opts& o) {
-  const auto key = std::make_tuple(j, o.restart, o.nu_pre, o.nu_post);
+// Replays `step` from the graph cached under `key`, capturing it on first use.
+template <typename Step>
+void replay_graph(vk_hierarchy* h, const std::tuple<int, int, int, int, int>& key, Step&& step) {
   auto it = h->graphs.find(key);
   if (it == h->graphs.end()) {
     const hipStream_t s = h->stream;
@@ -365,7 +366,7 @@ void arnoldi_step_graph(vk_hierarchy* h, int j, const vk_solve_opts& o) {
     HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     h->capturing = true;
     try {
-      arnoldi_step(h, j, o);
+      step();
     } catch (...) {
       h->capturing = false;
       (void)hipStreamEndCapture(s, &g);
@@ -381,6 +382,10 @@ void arnoldi_step_graph(vk_hierarchy* h, int j, const vk_solve_opts& o) {
     it = h->graphs.emplace(key, ge).first;
   }
   HIPCHECK(hipGraphLaunch(it->second, h->stream));
+}
+
+void arnoldi_step_graph(vk_hierarchy* h, int j, const vk_solve_opts& o) {
+  replay_graph(h, std::make_tuple(j, o.restart, o.nu_pre, o.nu_post, 0), [&] { arnoldi_step(h, j, o); });
 }
 
 // FGMRES(m) preconditioned by one V-cycle (right preconditioning, stored Z).
@@ -681,19 +686,25 @@ vk_status fgmres_multi(vk_hierarchy* h, int R, const double* B, double* X, const
       nk[c] = 0;
     }
     for (int j = 0; j < m; ++j) {
-      const size_t NR = (size_t)N * R;
-      double* vj = h->V + j * NR;
-      double* zj = h->Z + j * NR;
-      double* w = h->V + (j + 1) * NR;
-      vcycle_multi(h, Lf, R, vj, zj, o.nu_pre, o.nu_post);
-      launch_spmm(0, N, F.nkg, F.kgrp, R, F.rowptr, F.col, F.val, zj, nullptr, w, s);
-      launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h->small, s);
-      launch_axpy_cols(N, R, j + 1, nullptr, -1.0, h->V, NR, h->small, w, s);
-      launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h->small + (size_t)(m + 2) * R, s);
-      launch_axpy_cols(N, R, j + 1, nullptr, -1.0, h->V, NR, h->small + (size_t)(m + 2) * R, w, s);
-      launch_dots_cols(N, R, 1, w, 0, w, h->partial, h->small + (size_t)2 * (m + 2) * R, s);
-      launch_div_sqrt_cols(N, R, w, h->small + (size_t)2 * (m + 2) * R, w, s);
-      check_launch();
+      auto step = [&] {
+        const size_t NR = (size_t)N * R;
+        double* vj = h->V + j * NR;
+        double* zj = h->Z + j * NR;
+        double* w = h->V + (j + 1) * NR;
+        vk::vcycle_multi(h, Lf, R, vj, zj, o.nu_pre, o.nu_post);
+        launch_spmm(0, N, F.nkg, F.kgrp, R, F.rowptr, F.col, F.val, zj, nullptr, w, s);
+        launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h->small, s);
+        launch_axpy_cols(N, R, j + 1, nullptr, -1.0, h->V, NR, h->small, w, s);
+        launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h->small + (size_t)(m + 2) * R, s);
+        launch_axpy_cols(N, R, j + 1, nullptr, -1.0, h->V, NR, h->small + (size_t)(m + 2) * R, w, s);
+        launch_dots_cols(N, R, 1, w, 0, w, h->partial, h->small + (size_t)2 * (m + 2) * R, s);
+        launch_div_sqrt_cols(N, R, w, h->small + (size_t)2 * (m + 2) * R, w, s);
+        check_launch();
+      };
+      // every step processes all R columns (finished ones too), so its kernel sequence depends on
+      // (j, R, nu) only and can be replayed
+      if (o.use_graphs) replay_graph(h, std::make_tuple(j, o.restart, o.nu_pre, o.nu_post, R), step);
+      else step();
       HIPCHECK(hipMemcpyAsync(hh.data(), h->small, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHECK(hipStreamSynchronize(s));
       bool still = false;
@@ -1245,7 +1256,6 @@ vk_status vk_solve_multi(vk_hierarchy* h, const double* B, double* X, int nrhs, 
     require(opts->restart >= 1 && opts->restart <= h->max_restart, VK_EINVAL, "restart exceeds the bound basis");
     require(opts->maxit >= 0 && opts->rtol >= 0 && opts->nu_pre >= 0 && opts->nu_post >= 0, VK_EINVAL,
             "bad solve options");
-    require(!opts->use_graphs, VK_EINVAL, "graph replay is implemented for the single-vector solve");
     return fgmres_multi(h, nrhs, B, X, *opts, info);
   });
 }

@@ -97,8 +97,9 @@ struct vk_hierarchy {
   int* singular = nullptr;
   std::vector<double> ybuf;
   std::vector<std::vector<int4>> meta_host;  // staging of the per-patch metadata uploads
-  // captured FGMRES iterations, keyed by (j, restart, nu_pre, nu_post)
-  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
+  // captured FGMRES iterations, keyed by (j, restart, nu_pre, nu_post, right-hand sides; 0 for the
+  // single-vector step)
+  std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;
   bool capturing = false;
   // kernel timing of the finest-level patch apply
   bool timing = false;
