@@ -287,6 +287,8 @@ typedef struct vk_tuning {
   int apply_nontemporal_small; /* same for the small patches */
   int apply_depth_large; /* symmetric tiled storage: tile steps of loads in flight per lane (2 or 4) */
   int apply_depth_small; /* same for the small patches */
+  int apply_merged;      /* 1: one launch over all patches with the large patches' shape (fewer
+                            launches on latency-bound coarse levels) */
 } vk_tuning;
 
 /* Autotuner (batching pattern of the path): times every candidate launch

@@ -55,7 +55,8 @@ class vk_level_info(ctypes.Structure):
 class vk_tuning(ctypes.Structure):
     _fields_ = [("k_lanes", _c_int), ("p_lanes", _c_int), ("pt_lanes", _c_int), ("apply_waves_large", _c_int),
                 ("apply_waves_small", _c_int), ("apply_nontemporal_large", _c_int),
-                ("apply_nontemporal_small", _c_int), ("apply_depth_large", _c_int), ("apply_depth_small", _c_int)]
+                ("apply_nontemporal_small", _c_int), ("apply_depth_large", _c_int), ("apply_depth_small", _c_int),
+                ("apply_merged", _c_int)]
 
 
 class vk_solve_opts(ctypes.Structure):

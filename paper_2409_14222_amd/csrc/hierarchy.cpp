@@ -159,12 +159,11 @@ void patch_apply(vk_hierarchy* h, int l, const double* t) {
     h->ev_free.pop_back();
     HIPCHECK(hipEventRecord(ev.first, h->stream));
   }
-  launch_patch_apply(h->fp32(), d.tri, d.max_n, d.waves_large, d.nt_large != 0, d.depth_large, d.n_large, d.meta,
-                     d.pdofs, d.inv, t, d.delta,
-                     h->stream);
-  launch_patch_apply(h->fp32(), d.tri, std::min(d.max_n, 64), d.waves_small, d.nt_small != 0, d.depth_small,
-                     d.J - d.n_large, d.meta + d.n_large, d.pdofs, d.inv,
-                     t, d.delta, h->stream);
+  launch_patch_apply(h->fp32(), d.tri, d.max_n, d.waves_large, d.nt_large != 0, d.depth_large,
+                     d.merged ? d.J : d.n_large, d.meta, d.pdofs, d.inv, t, d.delta, h->stream);
+  if (!d.merged)
+    launch_patch_apply(h->fp32(), d.tri, std::min(d.max_n, 64), d.waves_small, d.nt_small != 0, d.depth_small,
+                       d.J - d.n_large, d.meta + d.n_large, d.pdofs, d.inv, t, d.delta, h->stream);
   check_launch();
   if (timed) {
     HIPCHECK(hipEventRecord(ev.second, h->stream));
@@ -538,6 +537,35 @@ void autotune(vk_hierarchy* h, int reps) {
       (part == 0 ? d.nt_large : d.nt_small) = best_nt;
       (part == 0 ? d.depth_large : d.depth_small) = best_depth;
     }
+    // one launch over all patches instead of two (saves a launch where the level is latency-bound)
+    d.merged = 0;
+    if (d.n_large > 0 && d.n_large < d.J) {
+      const float split = time_ms(s, reps, [&] {
+        launch_patch_apply(h->fp32(), d.tri, d.max_n, d.waves_large, d.nt_large != 0, d.depth_large, d.n_large,
+                           d.meta, d.pdofs, d.inv, d.b, d.delta, s);
+        launch_patch_apply(h->fp32(), d.tri, std::min(d.max_n, 64), d.waves_small, d.nt_small != 0, d.depth_small,
+                           d.J - d.n_large, d.meta + d.n_large, d.pdofs, d.inv, d.b, d.delta, s);
+      });
+      float bm = 1e30f;
+      int mw = 1, mnt = 1, mdepth = 2;
+      for (int depth : {2, 4}) {
+        if (!d.tri && depth != 2) continue;
+        for (int nt = 1; nt >= 0; --nt)
+          for (int w : waves) {
+            const float t = time_ms(s, reps, [&] {
+              launch_patch_apply(h->fp32(), d.tri, d.max_n, w, nt != 0, depth, d.J, d.meta, d.pdofs, d.inv, d.b,
+                                 d.delta, s);
+            });
+            if (t < bm) { bm = t; mw = w; mnt = nt; mdepth = depth; }
+          }
+      }
+      if (bm < split * 0.97f) {
+        d.merged = 1;
+        d.waves_large = mw;
+        d.nt_large = mnt;
+        d.depth_large = mdepth;
+      }
+    }
   }
   check_launch();
 }
@@ -571,10 +599,11 @@ void smooth_multi(vk_hierarchy* h, int l, int R, const double* B, double* X, int
     }
     if (d.tri) {
       // bound for one right-hand side: [N][1] multivectors are plain vectors
-      launch_patch_apply(h->fp32(), true, d.max_n, d.waves_large, d.nt_large != 0, d.depth_large, d.n_large, d.meta,
-                         d.pdofs, d.inv, T, d.delta, s);
-      launch_patch_apply(h->fp32(), true, std::min(d.max_n, 64), d.waves_small, d.nt_small != 0, d.depth_small,
-                         d.J - d.n_large, d.meta + d.n_large, d.pdofs, d.inv, T, d.delta, s);
+      launch_patch_apply(h->fp32(), true, d.max_n, d.waves_large, d.nt_large != 0, d.depth_large,
+                         d.merged ? d.J : d.n_large, d.meta, d.pdofs, d.inv, T, d.delta, s);
+      if (!d.merged)
+        launch_patch_apply(h->fp32(), true, std::min(d.max_n, 64), d.waves_small, d.nt_small != 0, d.depth_small,
+                           d.J - d.n_large, d.meta + d.n_large, d.pdofs, d.inv, T, d.delta, s);
     } else {
       launch_patch_gemm(h->fp32(), d.n_large, d.max_n, d.meta, d.pdofs, d.inv, T, R, d.delta, s);
       launch_patch_gemm(h->fp32(), d.J - d.n_large, std::min(d.max_n, 64), d.meta + d.n_large, d.pdofs, d.inv, T, R,
@@ -1300,6 +1329,7 @@ vk_status vk_tuning_get(const vk_hierarchy* h, int level, vk_tuning* t) {
     t->apply_nontemporal_small = d.nt_small;
     t->apply_depth_large = d.depth_large;
     t->apply_depth_small = d.depth_small;
+    t->apply_merged = d.merged;
     return VK_OK;
   });
 }
@@ -1326,6 +1356,7 @@ vk_status vk_tuning_set(vk_hierarchy* h, int level, const vk_tuning* t) {
     d.nt_small = t->apply_nontemporal_small != 0;
     d.depth_large = t->apply_depth_large;
     d.depth_small = t->apply_depth_small;
+    d.merged = t->apply_merged != 0;
     return VK_OK;
   });
 }

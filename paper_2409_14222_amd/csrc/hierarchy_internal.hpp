@@ -53,6 +53,7 @@ struct DevLevel {
   int k_lanes = 32, p_lanes = 8, pt_lanes = 8, waves_large = 1, waves_small = 1, n_large = 0;
   int nt_large = 1, nt_small = 1;  // non-temporal (streaming) loads of the inverses
   int depth_large = 2, depth_small = 2;  // tile steps in flight (symmetric tiled storage)
+  int merged = 0;  // one apply launch over all patches with the large patches' shape
   int max_n = 0;
   int4* meta = nullptr;            // per patch in processing order: {first slot, n, inverse offset}
   bool tri = false;                // inverses in symmetric tiled storage (bound for one right-hand side)

@@ -335,10 +335,11 @@ def test_launch_shapes_do_not_change_results(fx, request):
     saved = [H.tuning(l) for l in range(len(OH.levels))]
     ref = torch.empty_like(r)
     H.vcycle(r, ref, 2, 2)
-    for lanes, waves, depth in ((4, 1, 2), (8, 2, 4), (16, 4, 2), (64, 1, 4), (32, 4, 4)):
+    for lanes, waves, depth, merged in ((4, 1, 2, 0), (8, 2, 4, 1), (16, 4, 2, 0), (64, 1, 4, 1), (32, 4, 4, 1)):
         for l in range(len(OH.levels)):
             H.set_tuning(l, k_lanes=lanes, p_lanes=lanes, pt_lanes=lanes, apply_waves_large=waves,
-                         apply_waves_small=waves, apply_depth_large=depth, apply_depth_small=depth)
+                         apply_waves_small=waves, apply_depth_large=depth, apply_depth_small=depth,
+                         apply_merged=merged)
         e = torch.empty_like(r)
         H.vcycle(r, e, 2, 2)
         assert torch.equal(e, ref), (lanes, waves)
