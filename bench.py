@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # file invalidates them (reported as null).
 # Sources: profiles/patch_apply_p4p3_64_fp64.md, profiles/many_rhs_sv_p3dp2_64.md
 MEASURED_TRAFFIC = {
-    ("patch_apply.hip", "6d321e57784babdb", "p4p3-64", "fp64", 1): 540.6e6,
+    ("patch_apply.hip", "6d321e57784babdb", "p4p3-64", "fp64", 1): 527.6e6,
     ("patch_gemm.hip", "55e68640323c960e", "sv-p3dp2-64", "fp32", 64): 555.2e6,
 }
 
