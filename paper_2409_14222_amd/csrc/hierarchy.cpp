@@ -722,12 +722,21 @@ vk_status fgmres_multi(vk_hierarchy* h, int R, const double* B, double* X, const
         double* w = h->V + (j + 1) * NR;
         vk::vcycle_multi(h, Lf, R, vj, zj, o.nu_pre, o.nu_post);
         launch_spmm(0, N, F.nkg, F.kgrp, R, F.rowptr, F.col, F.val, zj, nullptr, w, s);
-        launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h->small, s);
-        launch_axpy_cols(N, R, j + 1, nullptr, -1.0, h->V, NR, h->small, w, s);
-        launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h->small + (size_t)(m + 2) * R, s);
-        launch_axpy_cols(N, R, j + 1, nullptr, -1.0, h->V, NR, h->small + (size_t)(m + 2) * R, w, s);
-        launch_dots_cols(N, R, 1, w, 0, w, h->partial, h->small + (size_t)2 * (m + 2) * R, s);
-        launch_div_sqrt_cols(N, R, w, h->small + (size_t)2 * (m + 2) * R, w, s);
+        double* h1 = h->small;
+        double* h2 = h->small + (size_t)(m + 2) * R;
+        double* nn = h->small + (size_t)2 * (m + 2) * R;
+        launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h1, s);
+        if (j + 1 <= kFusedMaxNv) {
+          // CGS2 with each update fused into the next reduction (one read of the basis fewer)
+          launch_axpy_dots_cols(false, N, R, j + 1, -1.0, h->V, NR, h1, w, h->partial, h2, s);
+          launch_axpy_dots_cols(true, N, R, j + 1, -1.0, h->V, NR, h2, w, h->partial, nn, s);
+        } else {
+          launch_axpy_cols(N, R, j + 1, nullptr, -1.0, h->V, NR, h1, w, s);
+          launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h2, s);
+          launch_axpy_cols(N, R, j + 1, nullptr, -1.0, h->V, NR, h2, w, s);
+          launch_dots_cols(N, R, 1, w, 0, w, h->partial, nn, s);
+        }
+        launch_div_sqrt_cols(N, R, w, nn, w, s);
         check_launch();
       };
       // every step processes all R columns (finished ones too), so its kernel sequence depends on

@@ -371,6 +371,75 @@ void launch_axpy_cols(int n, int R, int nv, const int* nvc, double sign, const d
   axpy_cols_kernel<<<(n + rpb - 1) / rpb, 256, 0, s>>>(n, R, Rp, nv, nvc, sign, V, ldv, h, W);
 }
 
+// Fused CGS2 pass: W[i][c] += sign * sum_{v < nv} V_v[i][c] h[v][c] (the arithmetic of
+// axpy_cols_kernel), then the column dot products of the updated W with V_0..V_{nv-1}
+// (SELF: with W itself), so one pass reads the basis once instead of twice.  Block b sums
+// the rows of chunk b (the chunks of dots_partial_kernel) over 8 row lanes, lane rl taking
+// rows i0 + rl, i0 + rl + 8, ... in order, and combines the lanes by the fixed tree
+// ((0+1)+(2+3))+((4+5)+(6+7)); the chunk partials are summed in chunk order.  NV (8, 16 or
+// 32 >= nv) sizes the register arrays.
+template <bool SELF, int NV>
+__global__ void __launch_bounds__(512) axpy_dots_kernel(int n, int R, int nv, double sign,
+                                                        const double* __restrict__ V, int64_t ldv,
+                                                        const double* __restrict__ h, double* __restrict__ W,
+                                                        double* __restrict__ partial) {
+  constexpr int ND = SELF ? 1 : NV;
+  __shared__ double sh[ND][512];
+  const int c = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int chunk = (n + kColBlocks - 1) / kColBlocks;
+  const int i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  const int cl = c < R ? c : R - 1;
+  double hv[NV];
+#pragma unroll
+  for (int t = 0; t < NV; ++t) hv[t] = t < nv ? h[(int64_t)min(t, nv - 1) * R + cl] : 0.0;
+  double acc[ND];
+#pragma unroll
+  for (int t = 0; t < ND; ++t) acc[t] = 0.0;
+  for (int i = i0 + rl; i < i1; i += 8) {
+    const int64_t o = (int64_t)i * R + cl;
+    double x[NV];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) x[t] = V[(int64_t)min(t, nv - 1) * ldv + o];
+    double sacc = 0.0;
+#pragma unroll
+    for (int t = 0; t < NV; ++t)
+      if (t < nv) sacc += x[t] * hv[t];
+    const double w = W[o] + sign * sacc;
+    if (c < R) W[o] = w;
+    if (SELF) {
+      acc[0] += w * w;
+    } else {
+#pragma unroll
+      for (int t = 0; t < ND; ++t) acc[t] += x[t] * w;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < ND; ++t) sh[t][threadIdx.x] = acc[t];
+  __syncthreads();
+  if (rl == 0 && c < R)
+    for (int t = 0; t < ND && t < (SELF ? 1 : nv); ++t) {
+      const double* q = sh[t];
+      const double sv = ((q[c] + q[64 + c]) + (q[128 + c] + q[192 + c])) +
+                        ((q[256 + c] + q[320 + c]) + (q[384 + c] + q[448 + c]));
+      partial[((int64_t)t * kColBlocks + blockIdx.x) * 64 + c] = sv;
+    }
+}
+
+template <bool SELF>
+static void axpy_dots_launch(int n, int R, int nv, double sign, const double* V, int64_t ldv, const double* h,
+                             double* W, double* partial, hipStream_t s) {
+  if (nv <= 8) axpy_dots_kernel<SELF, 8><<<kColBlocks, 512, 0, s>>>(n, R, nv, sign, V, ldv, h, W, partial);
+  else if (nv <= 16) axpy_dots_kernel<SELF, 16><<<kColBlocks, 512, 0, s>>>(n, R, nv, sign, V, ldv, h, W, partial);
+  else axpy_dots_kernel<SELF, 32><<<kColBlocks, 512, 0, s>>>(n, R, nv, sign, V, ldv, h, W, partial);
+}
+
+void launch_axpy_dots_cols(bool self, int n, int R, int nv, double sign, const double* V, int64_t ldv,
+                           const double* h, double* W, double* partial, double* out, hipStream_t s) {
+  if (self) axpy_dots_launch<true>(n, R, nv, sign, V, ldv, h, W, partial, s);
+  else axpy_dots_launch<false>(n, R, nv, sign, V, ldv, h, W, partial, s);
+  dots_final_kernel<<<self ? 1 : nv, 64, 0, s>>>(R, partial, out);
+}
+
 // Y[i][c] = X[i][c] / sqrt(nn[c]) (nn[c] <= 0 gives 0: a finished or empty column)
 __global__ void __launch_bounds__(256) div_sqrt_cols_kernel(int64_t total, int R, const double* X,
                                                             const double* __restrict__ nn, double* Y) {
