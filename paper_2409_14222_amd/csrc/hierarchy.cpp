@@ -728,8 +728,8 @@ vk_status fgmres_multi(vk_hierarchy* h, int R, const double* B, double* X, const
         launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h1, s);
         if (j + 1 <= kFusedMaxNv) {
           // CGS2 with each update fused into the next reduction (one read of the basis fewer)
-          launch_axpy_dots_cols(false, N, R, j + 1, -1.0, h->V, NR, h1, w, h->partial, h2, s);
-          launch_axpy_dots_cols(true, N, R, j + 1, -1.0, h->V, NR, h2, w, h->partial, nn, s);
+          launch_axpy_dots_cols(false, N, R, j + 1, nullptr, -1.0, h->V, NR, h1, w, h->partial, h2, s);
+          launch_axpy_dots_cols(true, N, R, j + 1, nullptr, -1.0, h->V, NR, h2, w, h->partial, nn, s);
         } else {
           launch_axpy_cols(N, R, j + 1, nullptr, -1.0, h->V, NR, h1, w, s);
           launch_dots_cols(N, R, j + 1, h->V, NR, w, h->partial, h2, s);

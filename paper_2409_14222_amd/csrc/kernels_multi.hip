@@ -379,8 +379,8 @@ void launch_axpy_cols(int n, int R, int nv, const int* nvc, double sign, const d
 // ((0+1)+(2+3))+((4+5)+(6+7)); the chunk partials are summed in chunk order.  NV (8, 16 or
 // 32 >= nv) sizes the register arrays.
 template <bool SELF, int NV>
-__global__ void __launch_bounds__(512) axpy_dots_kernel(int n, int R, int nv, double sign,
-                                                        const double* __restrict__ V, int64_t ldv,
+__global__ void __launch_bounds__(512) axpy_dots_kernel(int n, int R, int nv, const int* __restrict__ nvc,
+                                                        double sign, const double* __restrict__ V, int64_t ldv,
                                                         const double* __restrict__ h, double* __restrict__ W,
                                                         double* __restrict__ partial) {
   constexpr int ND = SELF ? 1 : NV;
@@ -389,9 +389,10 @@ __global__ void __launch_bounds__(512) axpy_dots_kernel(int n, int R, int nv, do
   const int chunk = (n + kColBlocks - 1) / kColBlocks;
   const int i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
   const int cl = c < R ? c : R - 1;
+  const int mc = nvc ? nvc[cl] : nv;  // the column's own basis size (terms past it are multiplied by zero)
   double hv[NV];
 #pragma unroll
-  for (int t = 0; t < NV; ++t) hv[t] = t < nv ? h[(int64_t)min(t, nv - 1) * R + cl] : 0.0;
+  for (int t = 0; t < NV; ++t) hv[t] = (t < nv && t < mc) ? h[(int64_t)min(t, nv - 1) * R + cl] : 0.0;
   double acc[ND];
 #pragma unroll
   for (int t = 0; t < ND; ++t) acc[t] = 0.0;
@@ -426,17 +427,20 @@ __global__ void __launch_bounds__(512) axpy_dots_kernel(int n, int R, int nv, do
 }
 
 template <bool SELF>
-static void axpy_dots_launch(int n, int R, int nv, double sign, const double* V, int64_t ldv, const double* h,
-                             double* W, double* partial, hipStream_t s) {
-  if (nv <= 8) axpy_dots_kernel<SELF, 8><<<kColBlocks, 512, 0, s>>>(n, R, nv, sign, V, ldv, h, W, partial);
-  else if (nv <= 16) axpy_dots_kernel<SELF, 16><<<kColBlocks, 512, 0, s>>>(n, R, nv, sign, V, ldv, h, W, partial);
-  else axpy_dots_kernel<SELF, 32><<<kColBlocks, 512, 0, s>>>(n, R, nv, sign, V, ldv, h, W, partial);
+static void axpy_dots_launch(int n, int R, int nv, const int* nvc, double sign, const double* V, int64_t ldv,
+                             const double* h, double* W, double* partial, hipStream_t s) {
+  if (nv <= 8)
+    axpy_dots_kernel<SELF, 8><<<kColBlocks, 512, 0, s>>>(n, R, nv, nvc, sign, V, ldv, h, W, partial);
+  else if (nv <= 16)
+    axpy_dots_kernel<SELF, 16><<<kColBlocks, 512, 0, s>>>(n, R, nv, nvc, sign, V, ldv, h, W, partial);
+  else
+    axpy_dots_kernel<SELF, 32><<<kColBlocks, 512, 0, s>>>(n, R, nv, nvc, sign, V, ldv, h, W, partial);
 }
 
-void launch_axpy_dots_cols(bool self, int n, int R, int nv, double sign, const double* V, int64_t ldv,
-                           const double* h, double* W, double* partial, double* out, hipStream_t s) {
-  if (self) axpy_dots_launch<true>(n, R, nv, sign, V, ldv, h, W, partial, s);
-  else axpy_dots_launch<false>(n, R, nv, sign, V, ldv, h, W, partial, s);
+void launch_axpy_dots_cols(bool self, int n, int R, int nv, const int* nvc, double sign, const double* V,
+                           int64_t ldv, const double* h, double* W, double* partial, double* out, hipStream_t s) {
+  if (self) axpy_dots_launch<true>(n, R, nv, nvc, sign, V, ldv, h, W, partial, s);
+  else axpy_dots_launch<false>(n, R, nv, nvc, sign, V, ldv, h, W, partial, s);
   dots_final_kernel<<<self ? 1 : nv, 64, 0, s>>>(R, partial, out);
 }
 

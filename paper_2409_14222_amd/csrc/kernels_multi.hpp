@@ -28,10 +28,11 @@ void launch_dense_gemm(int N, int R, const double* M, const double* Rv, double* 
 constexpr int kColBlocks = 256;
 // largest basis the fused CGS2 pass holds in registers
 constexpr int kFusedMaxNv = 32;
-// W += sign * sum_v V_v h[v] for v < nv, then out[v][c] = <V_v, W>_c (self: out[0][c] = <W, W>_c), both
-// in the arithmetic and order of launch_axpy_cols and launch_dots_cols; nv <= kFusedMaxNv
-void launch_axpy_dots_cols(bool self, int n, int R, int nv, double sign, const double* V, int64_t ldv,
-                           const double* h, double* W, double* partial, double* out, hipStream_t s);
+// W += sign * sum_v V_v h[v] for v < nvc[c] (nvc == nullptr: nv), the arithmetic of launch_axpy_cols,
+// then out[v][c] = <V_v, W>_c for v < nv (self: out[0][c] = <W, W>_c) over the row chunks of
+// launch_dots_cols; nv <= kFusedMaxNv
+void launch_axpy_dots_cols(bool self, int n, int R, int nv, const int* nvc, double sign, const double* V,
+                           int64_t ldv, const double* h, double* W, double* partial, double* out, hipStream_t s);
 // out[v][c] = sum_i V_v[i][c] W[i][c], v < nv; partial holds nv * kColBlocks * 64 doubles
 void launch_dots_cols(int n, int R, int nv, const double* V, int64_t ldv, const double* W, double* partial,
                       double* out, hipStream_t s);

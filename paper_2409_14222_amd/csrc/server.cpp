@@ -381,13 +381,22 @@ void enqueue_arnoldi(Resident* r, int m, int nu_pre, int nu_post) {
   h2d(r, cip(r, CI_MASK), hip_(r, HI_ZERO), 64);
   launch_gather_slice(r->N, r->S, r->nvel, F.t, 0, cip(r, CI_MASK), cvp(r, CV_NU), cvp(r, CV_ONE), r->W, st);
   // CGS2 against v_0 .. v_j (per-column counts), norm, normalisation, store as v_{j+1}
-  launch_dots_cols(r->N, r->S, jmax + 1, h->V, slice, r->W, h->partial, h->small, st);
-  launch_axpy_cols(r->N, r->S, jmax + 1, cip(r, CI_NVC), -1.0, h->V, slice, h->small, r->W, st);
-  launch_dots_cols(r->N, r->S, jmax + 1, h->V, slice, r->W, h->partial, h->small + (size_t)(m + 2) * r->S, st);
-  launch_axpy_cols(r->N, r->S, jmax + 1, cip(r, CI_NVC), -1.0, h->V, slice, h->small + (size_t)(m + 2) * r->S,
-                   r->W, st);
+  double* h1 = h->small;
+  double* h2 = h->small + (size_t)(m + 2) * r->S;
   double* nn = h->small + (size_t)2 * (m + 2) * r->S;
-  launch_dots_cols(r->N, r->S, 1, r->W, 0, r->W, h->partial, nn, st);
+  launch_dots_cols(r->N, r->S, jmax + 1, h->V, slice, r->W, h->partial, h1, st);
+  if (jmax + 1 <= kFusedMaxNv) {
+    // each update fused with the following reduction (one read of the basis fewer per pass)
+    launch_axpy_dots_cols(false, r->N, r->S, jmax + 1, cip(r, CI_NVC), -1.0, h->V, slice, h1, r->W, h->partial, h2,
+                          st);
+    launch_axpy_dots_cols(true, r->N, r->S, jmax + 1, cip(r, CI_NVC), -1.0, h->V, slice, h2, r->W, h->partial, nn,
+                          st);
+  } else {
+    launch_axpy_cols(r->N, r->S, jmax + 1, cip(r, CI_NVC), -1.0, h->V, slice, h1, r->W, st);
+    launch_dots_cols(r->N, r->S, jmax + 1, h->V, slice, r->W, h->partial, h2, st);
+    launch_axpy_cols(r->N, r->S, jmax + 1, cip(r, CI_NVC), -1.0, h->V, slice, h2, r->W, st);
+    launch_dots_cols(r->N, r->S, 1, r->W, 0, r->W, h->partial, nn, st);
+  }
   launch_div_sqrt_cols(r->N, r->S, r->W, nn, r->W, st);
   launch_scatter_slice(r->N, r->S, r->nvel, r->W, cvp(r, CV_ONE), cvp(r, CV_ONE), cip(r, CI_JNEXT), h->V, slice, st);
   check_launch();
