@@ -43,12 +43,15 @@ def _build(k, n0, nl, family="th", weighting="none", store=0, max_rhs=1, seed=0)
     from oracle import fields, solve
     print(f"[gpu] chebyshev hierarchy k={k} n0={n0} levels={nl} {family} {weighting} store={store} "
           f"rhs={max_rhs}", flush=True)
-    fam = vk.VK_SV if family == "sv" else vk.VK_TH
+    fam = {"sv": vk.VK_SV, "qk": vk.VK_TH_QUAD}.get(family, vk.VK_TH)
     w = vk.VK_WEIGHT_NONE if weighting == "none" else vk.VK_WEIGHT_MULTIPLICITY
-    H = vk.Hierarchy(k, n0, nl, family=fam, store=store, smoother=vk.VK_SMOOTH_CHEBYSHEV, weighting=w,
-                     est_seed=seed).bind(max_rhs=max_rhs).setup()
-    OH, OV = solve.setup(2, k, n0, nl, 1.0, fields.baseline_mms, family=family, smoother="chebyshev",
-                         weighting=weighting, est_seed=seed)
+    dim = 3 if family == "3d" else 2
+    H = vk.Hierarchy(k, n0, nl, dim=dim, family=fam, store=store, smoother=vk.VK_SMOOTH_CHEBYSHEV, weighting=w,
+                     est_seed=seed, forcing=vk.VK_F_CUBE_MMS if dim == 3 else vk.VK_F_BASELINE_MMS)
+    H.bind(max_rhs=max_rhs).setup()
+    OH, OV = solve.setup(dim, k, n0, nl, 1.0, fields.cube_mms if dim == 3 else fields.baseline_mms,
+                         family="th" if family == "3d" else family, smoother="chebyshev", weighting=weighting,
+                         est_seed=seed)
     return H, OH, OV
 
 
@@ -57,6 +60,8 @@ CASES = {
     "p4p3": (4, 4, 3, "th", "none"),
     "p2p1_mult": (2, 4, 3, "th", "multiplicity"),
     "p3dp2_sv": (3, 4, 3, "sv", "none"),
+    "q3q2": (3, 4, 3, "qk", "none"),
+    "p2p1_3d": (2, 2, 3, "3d", "none"),
 }
 
 
@@ -123,7 +128,8 @@ def test_vcycle_and_solve(cheb):
     assert conv == bool(res["converged"])
     assert res["iterations"] == its
     if conv:
-        assert rel <= (1e-6 if name == "p3dp2_sv" else 1e-8)
+        # two 1e-10-residual solves may differ by the problem's sensitivity (see test_gpu_parity.XTOL)
+        assert rel <= {"p3dp2_sv": 1e-6, "q3q2": 1e-6}.get(name, 1e-8)
         # the first iterations agree closely; later ones may not: where the residual stagnates (P4-P3
         # with unweighted patches stalls near 1e-4 until the restart), FGMRES's residual estimate
         # amplifies the 1e-15 V-cycle differences by many orders
