@@ -366,7 +366,7 @@ def main():
     torch.cuda.synchronize()
     t_dev = time.perf_counter() - t0
     t0 = time.perf_counter()
-    tuning = H.autotune(reps=5)
+    tuning = H.autotune(reps=20)
     t_tune = time.perf_counter() - t0
     Lf = w["levels"] - 1
     info = H.level_info(Lf)
