@@ -42,6 +42,9 @@ def build_patches(level, construct="composite"):
     if construct == "macro":
         from .sv import macro_patches
         return macro_patches(level)
+    if getattr(level, "cell_type", "simplex") == "bdm":
+        from .bdm import build_patches as extended_patches
+        return extended_patches(level)
     if getattr(level, "cell_type", "simplex") == "quad":
         from .qk import build_patches as quad_patches
         return quad_patches(level)

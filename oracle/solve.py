@@ -16,6 +16,9 @@ def setup(dim, k, n0, nlevels, nu, field_factory, omega=0.5, nu_sweeps=2, constr
         from . import sv
         H = sv.SVHierarchy(k, n0, nlevels, nu, field_factory)
         construct = "macro"
+    elif family == "bdm":
+        from . import bdm
+        H = bdm.BDMHierarchy(k, n0, nlevels, nu, field_factory)
     elif family == "qk":
         from . import qk
         H = qk.QKHierarchy(k, n0, nlevels, nu, field_factory)
