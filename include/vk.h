@@ -64,7 +64,19 @@ enum {
   VK_TH_QUAD = 2 /* Taylor-Hood (Q_k, Q_{k-1}) on the n x n mesh of squares (2D, 2 <= k <= 7): tensor
                     equispaced Lagrange bases, the same free-DoF numbering as VK_TH (the Q_k nodes
                     are the points of the P_k lattice), composite patches of vertices, edge
-                    interiors and cell interiors (Sec. 3.1) */
+                    interiors and cell interiors (Sec. 3.1) */,
+  VK_BDM = 3 /* (BDM_k, dP_{k-1}) with the symmetric interior-penalty form (Sec. 2, the H(div)-L2
+                formulation; Case 3 of Sec. 3), 2D, 1 <= k <= 8, VK_F_PAPER_MMS only (its u.n and
+                tangential stress vanish on the boundary), VK_PATCH_EXTENDED.  Velocity DoFs are
+                moments: per interior edge e = (a, b) (a the endpoint of smaller index y (n+1) + x,
+                t = (b - a)/|b - a|, n_e = (t_y, -t_x)) the k + 1 moments |e|^-1 int_e v.n_e L_j(s),
+                L_j the shifted Legendre polynomials; per cell the k^2 - 1 moments |T|^-1 int_T v.q
+                against the Gram-Schmidt orthonormalisation of e_0 l_a, e_1 l_a, (-xi_2, xi_1) l_a
+                (l_a nodal P_{k-2}, the last for the nodes on the edge opposite the first vertex,
+                xi = n (x - centroid)), spanning the first-kind Nedelec space ND_{k-1}.  Numbering:
+                interior edges in ascending (index(a), index(b)) order, then cell interiors, then
+                the nodal P_{k-1} pressure cell by cell (cell 2 (j n + i) is the lower triangle of
+                square (i, j)).  Transfers: the natural embedding of the nested spaces (Sec. 3) */
 };
 
 enum {
@@ -74,7 +86,13 @@ enum {
   VK_F_CUBE_MMS = 3      /* 3D divergence-free sin/cos field, p = 0 */
 };
 
-enum { VK_PATCH_COMPOSITE = 0, VK_PATCH_STAR = 1, VK_PATCH_MACRO = 2 };
+enum {
+  VK_PATCH_COMPOSITE = 0,
+  VK_PATCH_STAR = 1,
+  VK_PATCH_MACRO = 2,
+  VK_PATCH_EXTENDED = 3 /* VK_BDM: one patch per cell with its pressure and the free velocity on the
+                           closure of the cell and of the cells sharing an edge with it (Sec. 3.1) */
+};
 enum { VK_STORE_FP64 = 0, VK_STORE_FP32 = 1 };
 enum { VK_SMOOTH_DAMPED = 0, VK_SMOOTH_CHEBYSHEV = 1 };
 enum { VK_WEIGHT_MULTIPLICITY = 0, VK_WEIGHT_NONE = 1 };
@@ -82,14 +100,18 @@ enum { VK_WEIGHT_MULTIPLICITY = 0, VK_WEIGHT_NONE = 1 };
 /* Problem statement (Sec. 2 weak form; Sec. 3 hierarchy; Sec. 4 mesh). */
 typedef struct vk_problem {
   int dim;          /* 2 (triangles) or 3 (Kuhn tetrahedra, k = 2 only) */
-  int family;       /* VK_TH, VK_SV (2D, 2 <= k <= 4, VK_PATCH_MACRO) or VK_TH_QUAD (2D, 2 <= k <= 7) */
-  int k;            /* velocity order, pressure order k-1; 2 <= k <= 6 in 2D */
+  int family;       /* VK_TH, VK_SV (2D, 2 <= k <= 4, VK_PATCH_MACRO), VK_TH_QUAD (2D, 2 <= k <= 7)
+                       or VK_BDM (2D, 1 <= k <= 8, VK_PATCH_EXTENDED) */
+  int k;            /* velocity order, pressure order k-1; 2 <= k <= 8 in 2D (VK_BDM: from 1) */
   int n_coarse;     /* cells per direction on level 0 (>= 1) */
   int n_levels;     /* >= 2 */
   double viscosity; /* nu > 0 in a(u,v) = 2 nu int eps(u):eps(v) */
   int forcing;      /* VK_F_* */
   int n_modes;      /* VK_F_RANDOM: modes per direction M (coefficients 2*M*M) */
   const double* h_forcing_coeffs; /* VK_F_RANDOM: g[c][a][b], copied at create */
+  double penalty;   /* VK_BDM: alpha of the penalty term 2 nu alpha h_e^-1 int [u]^t:[v]^t, which the
+                       paper leaves open; 0 selects 2 (k + 1)^2 (2.3 to 4.6 times the smallest value
+                       that keeps a_h coercive on these meshes); ignored by the other families */
 } vk_problem;
 
 /* Relaxation options (Sec. 3.1, Algorithm 1 as a damped smoother). */

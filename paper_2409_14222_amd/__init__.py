@@ -24,9 +24,9 @@ lib = ctypes.CDLL(LIBPATH)
 # ---------------------------------------------------------------- constants (include/vk.h)
 VK_OK, VK_NOT_CONVERGED = 0, 1
 VK_EINVAL, VK_ENOMEM, VK_EHIP, VK_ESINGULAR, VK_ENAN, VK_EBUSY, VK_ESTATE = -1, -2, -3, -4, -5, -6, -7
-VK_TH, VK_SV, VK_TH_QUAD = 0, 1, 2
+VK_TH, VK_SV, VK_TH_QUAD, VK_BDM = 0, 1, 2, 3
 VK_F_BASELINE_MMS, VK_F_PAPER_MMS, VK_F_RANDOM, VK_F_CUBE_MMS = 0, 1, 2, 3
-VK_PATCH_COMPOSITE, VK_PATCH_STAR, VK_PATCH_MACRO = 0, 1, 2
+VK_PATCH_COMPOSITE, VK_PATCH_STAR, VK_PATCH_MACRO, VK_PATCH_EXTENDED = 0, 1, 2, 3
 VK_STORE_FP64, VK_STORE_FP32 = 0, 1
 VK_SMOOTH_DAMPED, VK_SMOOTH_CHEBYSHEV = 0, 1
 VK_WEIGHT_MULTIPLICITY, VK_WEIGHT_NONE = 0, 1
@@ -37,7 +37,7 @@ _c_int, _c_dbl, _p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
 class vk_problem(ctypes.Structure):
     _fields_ = [("dim", _c_int), ("family", _c_int), ("k", _c_int), ("n_coarse", _c_int), ("n_levels", _c_int),
                 ("viscosity", _c_dbl), ("forcing", _c_int), ("n_modes", _c_int),
-                ("h_forcing_coeffs", ctypes.POINTER(_c_dbl))]
+                ("h_forcing_coeffs", ctypes.POINTER(_c_dbl)), ("penalty", _c_dbl)]
 
 
 class vk_patch_opts(ctypes.Structure):
@@ -176,9 +176,9 @@ class Hierarchy:
 
     def __init__(self, k, n_coarse, n_levels, dim=2, viscosity=1.0, forcing=VK_F_BASELINE_MMS, coeffs=None,
                  construct=None, store=VK_STORE_FP64, omega=0.5, family=VK_TH, smoother=VK_SMOOTH_DAMPED,
-                 weighting=VK_WEIGHT_MULTIPLICITY, est_steps=10, est_seed=0):
+                 weighting=VK_WEIGHT_MULTIPLICITY, est_steps=10, est_seed=0, penalty=0.0):
         if construct is None:
-            construct = VK_PATCH_MACRO if family == VK_SV else VK_PATCH_COMPOSITE
+            construct = {VK_SV: VK_PATCH_MACRO, VK_BDM: VK_PATCH_EXTENDED}.get(family, VK_PATCH_COMPOSITE)
         self._coeffs = None
         n_modes = 0
         cptr = None
@@ -186,7 +186,7 @@ class Hierarchy:
             self._coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
             n_modes = self._coeffs.shape[-1]
             cptr = self._coeffs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        self.prob = vk_problem(dim, family, k, n_coarse, n_levels, viscosity, forcing, n_modes, cptr)
+        self.prob = vk_problem(dim, family, k, n_coarse, n_levels, viscosity, forcing, n_modes, cptr, penalty)
         self.opts = vk_patch_opts(construct, store, omega, smoother, weighting, est_steps, est_seed)
         h = ctypes.c_void_p()
         check(lib.vk_hierarchy_create(ctypes.byref(self.prob), ctypes.byref(self.opts), ctypes.byref(h)))

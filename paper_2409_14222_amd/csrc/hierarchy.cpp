@@ -841,12 +841,19 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
     require(prob && opts && out, VK_EINVAL, "null argument");
     const vk_problem& p = *prob;
     require(p.dim == 2 || p.dim == 3, VK_EINVAL, "dim must be 2 or 3");
-    require(p.family == VK_TH || ((p.family == VK_SV || p.family == VK_TH_QUAD) && p.dim == 2), VK_EINVAL,
-            "unsupported family");
+    require(p.family == VK_TH ||
+                ((p.family == VK_SV || p.family == VK_TH_QUAD || p.family == VK_BDM) && p.dim == 2),
+            VK_EINVAL, "unsupported family");
     if (p.family == VK_SV) require(p.k >= 2 && p.k <= 4, VK_EINVAL, "Scott-Vogelius supports 2 <= k <= 4");
     if (p.family == VK_TH_QUAD)
       require(p.k >= 2 && p.k <= 7, VK_EINVAL, "quadrilateral Taylor-Hood supports 2 <= k <= 7");
-    require(p.k >= 2 && p.k <= (p.dim == 2 ? 8 : 2), VK_EINVAL, "unsupported order k");
+    if (p.family == VK_BDM) {
+      require(p.k >= 1 && p.k <= 8, VK_EINVAL, "BDM supports 1 <= k <= 8");
+      require(p.forcing == VK_F_PAPER_MMS, VK_EINVAL, "BDM levels take the paper's field (VK_F_PAPER_MMS)");
+      require(p.penalty >= 0 && std::isfinite(p.penalty), VK_EINVAL, "penalty must be >= 0 (0: default)");
+    } else {
+      require(p.k >= 2 && p.k <= (p.dim == 2 ? 8 : 2), VK_EINVAL, "unsupported order k");
+    }
     require(p.n_coarse >= 1 && p.n_levels >= 2 && p.n_levels <= 12, VK_EINVAL, "bad hierarchy size");
     require(p.viscosity > 0 && std::isfinite(p.viscosity), VK_EINVAL, "viscosity must be positive");
     require(opts->omega > 0 && std::isfinite(opts->omega), VK_EINVAL, "omega must be positive");
@@ -857,6 +864,8 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
     require(opts->est_steps >= 0 && opts->est_steps <= 200, VK_EINVAL, "est_steps must be in 0..200");
     if (p.family == VK_SV)
       require(opts->construct == VK_PATCH_MACRO, VK_EINVAL, "Scott-Vogelius levels use VK_PATCH_MACRO");
+    else if (p.family == VK_BDM)
+      require(opts->construct == VK_PATCH_EXTENDED, VK_EINVAL, "BDM levels use VK_PATCH_EXTENDED");
     else
       require(opts->construct == VK_PATCH_COMPOSITE || (opts->construct == VK_PATCH_STAR && p.dim == 2), VK_EINVAL,
               "bad patch construction");
@@ -1304,6 +1313,7 @@ vk_status vk_rhs_random(const vk_hierarchy* h, int n_modes, const double* coeffs
     require(h->H.back().dim == 2, VK_EINVAL, "random forcing is defined on the unit square");
     require(h->H.back().family != VK_TH_QUAD, VK_EINVAL,
             "quadrilateral levels take the random forcing at create (VK_F_RANDOM)");
+    require(h->H.back().family != VK_BDM, VK_EINVAL, "BDM levels take the paper's field only");
     require(n_modes >= 1 && n_modes <= 64, VK_EINVAL, "n_modes out of range");
     // zero boundary velocity: no lifting, pressure rows are zero, so the load is already
     // consistent (orthogonal to the constant pressure)

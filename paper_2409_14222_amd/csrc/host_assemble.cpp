@@ -79,6 +79,10 @@ void setup_mesh(LevelHost& L) {
     setup_mesh_quad(L);
     return;
   }
+  if (L.family == VK_BDM) {
+    setup_mesh_bdm(L);
+    return;
+  }
   make_cells(L);
   L.unit = L.n;
   const int Mv = L.k * L.n, Mp = (L.k - 1) * L.n;
@@ -203,6 +207,10 @@ void solution_errors(const LevelHost& L, const Problem& pr, const double* x, dou
     solution_errors_quad(L, pr, x, e_u, e_p);
     return;
   }
+  if (L.family == VK_BDM) {
+    solution_errors_bdm(L, pr, x, e_u, e_p);
+    return;
+  }
   const int dim = L.dim, k = L.k, unit = L.unit;
   const Basis vb = make_basis(dim, k), pb = make_basis(dim, k - 1);
   const int nbv = vb.size(), nbp = pb.size(), nlv = nbv * dim;
@@ -324,6 +332,10 @@ void solution_errors(const LevelHost& L, const Problem& pr, const double* x, dou
 void build_level(LevelHost& L, const Problem& pr, bool with_rhs) {
   if (L.family == VK_TH_QUAD) {
     build_level_quad(L, pr, with_rhs);
+    return;
+  }
+  if (L.family == VK_BDM) {
+    build_level_bdm(L, pr, with_rhs);
     return;
   }
   const int dim = L.dim, k = L.k;
@@ -658,6 +670,10 @@ void build_prolongation(const LevelHost& C, LevelHost& F) {
     build_prolongation_quad(C, F);
     return;
   }
+  if (F.family == VK_BDM) {
+    build_prolongation_bdm(C, F);
+    return;
+  }
   const int dim = F.dim;
   Csr P;
   P.nrows = F.N;
@@ -717,6 +733,10 @@ void build_prolongation(const LevelHost& C, LevelHost& F) {
 void dof_coords(const LevelHost& L, double* xyz, int* kind) {
   if (L.family == VK_SV) {
     dof_coords_sv(L, xyz, kind);
+    return;
+  }
+  if (L.family == VK_BDM) {
+    dof_coords_bdm(L, xyz, kind);
     return;
   }
   const int dim = L.dim, Mv = L.k * L.n, Mp = (L.k - 1) * L.n;

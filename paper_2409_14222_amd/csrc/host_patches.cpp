@@ -53,6 +53,12 @@ void build_patches(LevelHost& L, int construct, double omega, int store) {
     build_patches_macro(L, omega, store);
     return;
   }
+  if (L.family == VK_BDM) {
+    require(construct == VK_PATCH_EXTENDED, VK_EINVAL, "BDM levels use extended cell patches");
+    build_patches_bdm(L, omega, store);
+    return;
+  }
+  require(construct != VK_PATCH_EXTENDED, VK_EINVAL, "extended cell patches belong to BDM levels");
   if (L.family == VK_TH_QUAD) {
     require(construct == VK_PATCH_COMPOSITE, VK_EINVAL, "quadrilateral levels use composite patches");
     build_patches_quad(L, omega, store);

@@ -64,7 +64,7 @@ struct Cell {
 
 struct LevelHost {
   int dim = 2, k = 2, n = 0;
-  int family = VK_TH;        // VK_TH or VK_SV (barycentric sub-cells, discontinuous pressure)
+  int family = VK_TH;        // VK_TH, VK_SV (barycentric sub-cells), VK_TH_QUAD or VK_BDM
   int unit = 0;              // cell vertex coordinates are integers in units of 1/unit (n, or 3n for VK_SV)
   std::vector<int> vmap;     // VK_SV: velocity lattice point y * (k unit + 1) + x -> interior node or -1
   int N = 0, nvel = 0, npres = 0;
@@ -123,6 +123,14 @@ void finalize_patches(LevelHost& L, std::vector<std::vector<int>>& patches, doub
 void dof_coords(const LevelHost& L, double* xyz, int* kind);
 // load vector of the random forcing (zero boundary velocity) on the finest-level numbering of (family, k, n)
 void assemble_random_load(int family, int k, int n, int n_modes, const double* coeffs, double* out);
+
+// (BDM_k, dP_{k-1}) interior-penalty levels (host_bdm.cpp)
+void setup_mesh_bdm(LevelHost& L);
+void build_level_bdm(LevelHost& L, const Problem& pr, bool with_rhs);
+void build_prolongation_bdm(const LevelHost& coarse, LevelHost& fine);
+void build_patches_bdm(LevelHost& L, double omega, int store);
+void solution_errors_bdm(const LevelHost& L, const Problem& pr, const double* x, double* e_u, double* e_p);
+void dof_coords_bdm(const LevelHost& L, double* xyz, int* kind);
 
 // Scott-Vogelius levels (host_sv.cpp)
 void setup_mesh_sv(LevelHost& L);

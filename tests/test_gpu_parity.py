@@ -127,6 +127,39 @@ def q7q6():
     return _quad_fixture(7, 2, 2)
 
 
+def _bdm_fixture(k, n0, nl):
+    import paper_2409_14222_amd as vk
+    from oracle import fields, solve
+    print(f"[gpu] building BDM{k}-dP{k - 1} {n0 << (nl - 1)}x{n0 << (nl - 1)} hierarchy", flush=True)
+    H = vk.Hierarchy(k, n0, nl, family=vk.VK_BDM, forcing=vk.VK_F_PAPER_MMS).bind().setup()
+    OH, OV = solve.setup(2, k, n0, nl, 1.0, fields.paper_mms, family="bdm")
+    return H, OH, OV
+
+
+@pytest.fixture(scope="module")
+def bdm1():
+    """BDM1-dP0 with interior penalty on 8x8, levels 2/4/8: extended cell patches of up to 19 DoFs."""
+    return _bdm_fixture(1, 2, 3)
+
+
+@pytest.fixture(scope="module")
+def bdm2():
+    """BDM2-dP1 on 8x8, levels 2/4/8: extended cell patches of up to 42 DoFs."""
+    return _bdm_fixture(2, 2, 3)
+
+
+@pytest.fixture(scope="module")
+def bdm4():
+    """BDM4-dP3 on 8x8, levels 2/4/8: extended cell patches of up to 115 DoFs."""
+    return _bdm_fixture(4, 2, 3)
+
+
+@pytest.fixture(scope="module")
+def bdm8():
+    """BDM8-dP7 on 2x2, levels 1/2: extended cell patches of up to 333 DoFs (global-memory inversion)."""
+    return _bdm_fixture(8, 1, 2)
+
+
 # relative solution difference allowed between two 1e-10-residual solves: Taylor-Hood 1e-8;
 # Scott-Vogelius 1e-6, since a relative rhs perturbation of 1e-11 moves the SV 16x16 solution by
 # 1.5e-6 (its small nonzero singular values), measured with a sparse direct solve.  High orders:
@@ -134,9 +167,20 @@ def q7q6():
 # P8-P7 4x4 solution by up to 7.3e-5 (sparse direct solves), so two 1e-10-residual solutions may
 # differ by twice that; iteration counts and residual histories are still compared tightly.
 # Quadrilaterals, measured the same way: Q2-Q1 16x16 1.4e-7, Q4-Q3 8x8 9.0e-7, Q7-Q6 4x4 1.1e-5
+# BDM with interior penalty, the same way: BDM1 8x8 2.6e-9, BDM2 8x8 2.1e-8, BDM4 8x8 1.4e-7,
+# BDM8 2x2 9.9e-7
 XTOL = {"p2p1": 1e-8, "p4p3": 1e-8, "p2p1_3d": 1e-8, "p3dp2_sv": 1e-6, "p6p5": 4e-5, "p8p7": 1.5e-4,
-        "q2q1": 3e-7, "q4q3": 2e-6, "q7q6": 2.2e-5}
-ALL = ["p2p1", "p4p3", "p2p1_3d", "p3dp2_sv", "p6p5", "p8p7", "q2q1", "q4q3", "q7q6"]
+        "q2q1": 3e-7, "q4q3": 2e-6, "q7q6": 2.2e-5, "bdm1": 1e-8, "bdm2": 5e-8, "bdm4": 3e-7, "bdm8": 2e-6}
+ALL = ["p2p1", "p4p3", "p2p1_3d", "p3dp2_sv", "p6p5", "p8p7", "q2q1", "q4q3", "q7q6", "bdm1", "bdm2", "bdm4",
+       "bdm8"]
+
+
+def _assembly_terms(L):
+    """Roundings by which two independent assemblies of one entry may differ, in units of eps: the
+    (k + 3)^dim quadrature terms, and for BDM levels the dual-basis inversions (growing like k^2)."""
+    if getattr(L, "family", "") == "bdm":
+        return 2 * (L.k + 3) ** 2 + 50 * L.k ** 2
+    return 2 * (L.k + 3) ** L.dim
 
 
 def _cond_bound(S):
@@ -155,7 +199,7 @@ def test_spmv_and_transfers(fx, request):
         ref = L.K @ x
         # elementwise: summation roundoff (2 nnz_i eps) plus the assembly difference of two
         # independent assemblers (2 (k + 3)^dim eps, the quadrature sums of an entry)
-        cV = 2 * (L.k + 3) ** L.dim
+        cV = _assembly_terms(L)
         absK = abs(L.K)
         bound = (cV + 2 * np.diff(L.K.indptr)) * EPS * (absK @ np.abs(x))
         assert np.all(np.abs(_host(y) - ref) <= bound)
@@ -166,7 +210,8 @@ def test_spmv_and_transfers(fx, request):
             H.prolong_add(l, _dev(xc), ef)
             # the SV pressure transfer is an L^2 projection computed independently on each side
             # (clipped-polygon quadrature, local mass solves): entries agree to 2.5e-13 absolute
-            ptol = 2.5e-13 if fx == "p3dp2_sv" else 0.0
+            # BDM transfers apply independently computed dual bases: entries agree to 1e-13 k absolute
+            ptol = 2.5e-13 if fx == "p3dp2_sv" else (1e-13 * L.k if fx.startswith("bdm") else 0.0)
             pat = abs(P).sign()
             assert np.all(np.abs(_host(ef) - (x + P @ xc)) <=
                           1e-13 * (abs(P) @ np.abs(xc) + np.abs(x)) + ptol * (pat @ np.abs(xc)))

@@ -395,3 +395,60 @@ def test_quad_errors_and_limits():
         with pytest.raises(vk.VkError) as e:
             vk.Hierarchy(k, 2, 2, family=vk.VK_TH_QUAD, **kw)
         assert e.value.code == vk.VK_EINVAL
+
+
+@pytest.mark.parametrize("k,n0,nl", [(1, 2, 3), (2, 2, 3), (4, 2, 2), (8, 1, 2)])
+def test_host_assembly_bdm_matches_oracle(k, n0, nl):
+    """(BDM_k, dP_{k-1}) with interior penalty: the library's dual bases, edge terms, transfers and
+    extended patches against the oracle's (independent dual-basis construction: Gauss-Jordan on a
+    Lagrange local space versus numpy's inverse, and its own Gram-Schmidt of the interior tests)."""
+    from oracle import bdm
+    H = vk.Hierarchy(k, n0, nl, family=vk.VK_BDM, forcing=vk.VK_F_PAPER_MMS)
+    OH = bdm.BDMHierarchy(k, n0, nl, 1.0, fields.paper_mms)
+    # entries carry the rounding of two dual-basis inversions (condition growing with k)
+    tol = 1e-14 * k * k
+    for l in range(nl):
+        ol = OH.levels[l]
+        inf = H.level_info(l)
+        assert (inf.n_free, inf.nnz, inf.n_velocity) == (ol.N, ol.K.nnz, ol.nu_free)
+        rp, col, val = H.csr(l)
+        assert np.array_equal(rp, ol.K.indptr) and np.array_equal(col, ol.K.indices)
+        rowmax = np.maximum.reduceat(np.abs(ol.K.data), ol.K.indptr[:-1])
+        assert np.all(np.abs(val - ol.K.data) <= tol * np.repeat(rowmax, np.diff(ol.K.indptr)))
+        X, kind = H.dof_coords(l)
+        assert np.array_equal(kind, np.where(np.arange(ol.N) < ol.nu_free, 0, 2))
+        if l > 0:
+            prp, pcol, pval = H.prolongation(l)
+            P = OH.P[l]
+            assert np.array_equal(prp, P.indptr) and np.array_equal(pcol, P.indices)
+            assert np.abs(pval - P.data).max() <= tol
+            ptr, dofs = H.patches(l)
+            op = patches.build_patches(ol)
+            assert [list(dofs[ptr[i]:ptr[i + 1]]) for i in range(len(op))] == [list(I) for I in op]
+    b = H.rhs()
+    ob = solve.consistent_rhs(OH.finest)
+    assert np.abs(b - ob).max() <= tol * np.abs(ob).max()
+    rng = np.random.default_rng(k)
+    x = rng.standard_normal(OH.finest.N) * 0.01
+    got, ref = H.solution_errors(x), bdm.errors(OH.finest, x)
+    assert abs(got[0] - ref[0]) <= 1e-11 * ref[0] and abs(got[1] - ref[1]) <= 1e-11 * ref[1]
+
+
+def test_bdm_invalid_combinations_are_rejected():
+    for kw in ({"k": 9}, {"k": 0}, {"k": 2, "forcing": vk.VK_F_BASELINE_MMS},
+               {"k": 2, "construct": vk.VK_PATCH_COMPOSITE}, {"k": 2, "dim": 3}, {"k": 2, "penalty": -1.0}):
+        k = kw.pop("k")
+        kw.setdefault("forcing", vk.VK_F_PAPER_MMS)
+        with pytest.raises(vk.VkError) as e:
+            vk.Hierarchy(k, 2, 2, family=vk.VK_BDM, **kw)
+        assert e.value.code == vk.VK_EINVAL
+    with pytest.raises(vk.VkError):
+        vk.Hierarchy(2, 2, 2, construct=vk.VK_PATCH_EXTENDED)
+    # an explicit penalty reaches the edge terms: K changes, the volume-only pressure rows do not
+    H0 = vk.Hierarchy(2, 2, 2, family=vk.VK_BDM, forcing=vk.VK_F_PAPER_MMS)
+    H1 = vk.Hierarchy(2, 2, 2, family=vk.VK_BDM, forcing=vk.VK_F_PAPER_MMS, penalty=40.0)
+    from oracle import bdm
+    O1 = bdm.BDMLevel(2, 4, 1.0, fields.paper_mms(1.0), alpha=40.0)
+    rp, col, val = H1.csr(1)
+    assert np.abs(val - O1.K.data).max() <= 1e-12 * np.abs(O1.K.data).max()
+    assert np.abs(H0.csr(1)[2] - val).max() > 1.0
