@@ -33,6 +33,10 @@ WORKLOADS = {
                         desc="Scott-Vogelius P3-dP2 on the barycentric refinement of the 64x64 two-triangle mesh, "
                              "5 non-nested levels (4..64), macro-element Vanka (56 DoFs), 64 random smooth forcings "
                              "solved in lockstep, FP32 matrix-core patch GEMMs, V(2,2), omega 0.5, FGMRES(30) to 1e-10"),
+    "bdm4-80": dict(k=4, n0=5, levels=5, family="bdm",
+                    desc="BDM4-dP3 with symmetric interior penalty (alpha 2 (k+1)^2), 80x80 two-triangle mesh, "
+                         "5x5 coarsest mesh and 4 refinements (the paper's l = 4), extended cell Vanka (up to 115 "
+                         "DoFs), the paper's manufactured solution, V(2,2), omega 0.5, FGMRES(30) to 1e-10"),
 }
 HBM_PEAK_GBS = 8000.0
 
@@ -67,6 +71,8 @@ def cpu_sample(spec, iterations):
         g = synth.forcing_coeffs(synth.SEED)
         H, V = solve.setup(2, w["k"], w["n0"], w["levels"], 1.0, lambda nu: fields.random_sine_field(g, nu),
                            family="sv", **kw)
+    elif w.get("family") == "bdm":
+        H, V = solve.setup(2, w["k"], w["n0"], w["levels"], 1.0, fields.paper_mms, family="bdm", **kw)
     else:
         H, V = solve.setup(dim, w["k"], w["n0"], w["levels"], 1.0,
                            fields.cube_mms if dim == 3 else fields.baseline_mms, **kw)
@@ -165,7 +171,8 @@ def serve_bench(args):
 
 def paper_grid(args):
     """Iteration counts at the paper's experiment settings (Sec. 4): 5x5 coarsest mesh (cut from top
-    left to bottom right, or squares with --grid-family quad), the paper's manufactured solution, zero
+    left to bottom right; squares with --grid-family quad; BDM_k-dP_{k-1} with --grid-family bdm), the
+    paper's manufactured solution, zero
     initial guess, unrestarted FGMRES (at most 100 iterations) to a 1e-10 relative residual, V(nu, nu) with nu = 1..4, l = 1..4 refinements; for
     each order k and smoother (damped additive Vanka, omega 0.5, 1/multiplicity weights; Chebyshev on
     [lambda / 4, 1.1 lambda] with unweighted or 1/multiplicity-weighted patch sums).  One JSON line per
@@ -180,7 +187,7 @@ def paper_grid(args):
     smoothers = [("damped", vk.VK_SMOOTH_DAMPED, vk.VK_WEIGHT_MULTIPLICITY),
                  ("chebyshev", vk.VK_SMOOTH_CHEBYSHEV, vk.VK_WEIGHT_NONE),
                  ("chebyshev-weighted", vk.VK_SMOOTH_CHEBYSHEV, vk.VK_WEIGHT_MULTIPLICITY)]
-    fam = vk.VK_TH_QUAD if args.grid_family == "quad" else vk.VK_TH
+    fam = {"quad": vk.VK_TH_QUAD, "bdm": vk.VK_BDM}.get(args.grid_family, vk.VK_TH)
     for k in [int(v) for v in args.grid_k.split(",")]:
         for ell in [int(v) for v in args.grid_levels.split(",")]:
             for name, sm, wt in smoothers:
@@ -230,7 +237,7 @@ def stopping_study(args):
             for name in args.study_smoothers.split(","):
                 sm, wt = smoothers[name]
                 H = vk.Hierarchy(k, 5, ell + 1, forcing=vk.VK_F_PAPER_MMS, smoother=sm, weighting=wt,
-                                 family=vk.VK_TH_QUAD if args.grid_family == "quad" else vk.VK_TH)
+                                 family={"quad": vk.VK_TH_QUAD, "bdm": vk.VK_BDM}.get(args.grid_family, vk.VK_TH))
                 H.bind(max_restart=100).setup()
                 b = torch.tensor(H.rhs(), device="cuda")
                 x = torch.empty_like(b)
@@ -295,8 +302,9 @@ def main():
                     help="tolerance needed for discretisation-level errors (paper settings, --grid-k/--grid-levels)")
     ap.add_argument("--study-nu", type=int, default=1)
     ap.add_argument("--study-smoothers", default="damped,chebyshev")
-    ap.add_argument("--grid-family", default="tri", choices=["tri", "quad"],
-                    help="Taylor-Hood on the two-triangle mesh (P_k) or on squares (Q_k)")
+    ap.add_argument("--grid-family", default="tri", choices=["tri", "quad", "bdm"],
+                    help="Taylor-Hood on the two-triangle mesh (P_k) or on squares (Q_k), or BDM_k-dP_{k-1} "
+                         "with interior penalty on the two-triangle mesh")
     ap.add_argument("--grid-k", default="2,3,4,5,6")
     ap.add_argument("--grid-levels", default="1,2,3,4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -351,9 +359,13 @@ def main():
     cheb = args.smoother == "chebyshev"
     if args.weighting is None:
         args.weighting = "none" if cheb else "multiplicity"
+    fam = {"sv": vk.VK_SV, "bdm": vk.VK_BDM}.get(w.get("family"), vk.VK_TH)
+    if fam == vk.VK_BDM and args.nrhs != 1:
+        raise SystemExit("the BDM workload solves the paper's manufactured solution (--nrhs 1)")
     H = vk.Hierarchy(w["k"], w["n0"], w["levels"], dim=dim, store=store,
-                     forcing=vk.VK_F_CUBE_MMS if dim == 3 else vk.VK_F_BASELINE_MMS,
-                     family=vk.VK_SV if w.get("family") == "sv" else vk.VK_TH,
+                     forcing=vk.VK_F_CUBE_MMS if dim == 3 else (vk.VK_F_PAPER_MMS if fam == vk.VK_BDM
+                                                                else vk.VK_F_BASELINE_MMS),
+                     family=fam,
                      smoother=vk.VK_SMOOTH_CHEBYSHEV if cheb else vk.VK_SMOOTH_DAMPED,
                      weighting=vk.VK_WEIGHT_NONE if args.weighting == "none" else vk.VK_WEIGHT_MULTIPLICITY)
     t_host = time.perf_counter() - t0

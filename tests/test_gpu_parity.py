@@ -469,3 +469,34 @@ def test_mixed_precision_solve_sv(p3dp2_sv):
     assert res["converged"] and abs(res["iterations"] - its) <= 2
     assert np.linalg.norm(ob - L.K @ xg) <= 1.05e-10 * np.linalg.norm(ob)
     assert np.linalg.norm(xg - xo) <= XTOL["p3dp2_sv"] * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("fx", ["bdm2", "bdm8"])
+def test_bdm_many_rhs_and_fp32_inverses(fx, request):
+    """BDM levels through the many-right-hand-side path (FP64 patch GEMMs; FP32 matrix-core GEMMs with
+    FP32 inverses, including the column-major storage of patches above 224 DoFs for BDM8)."""
+    import paper_2409_14222_amd as vk
+    from oracle import solve
+    H64, OH, OV = request.getfixturevalue(fx)
+    L = OH.finest
+    b = solve.consistent_rhs(L)
+    xo, its, _, _ = solve.solve(OH, OV)
+    R = 3
+    Bm = np.stack([b * (c + 1) for c in range(R)], axis=1)
+    k, n0, nl = L.k, OH.levels[0].n, len(OH.levels)
+    for store in (vk.VK_STORE_FP64, vk.VK_STORE_FP32):
+        H = vk.Hierarchy(k, n0, nl, family=vk.VK_BDM, forcing=vk.VK_F_PAPER_MMS, store=store)
+        H.bind(max_rhs=R).setup()
+        X = torch.zeros((L.N, R), dtype=torch.float64, device="cuda")
+        _, res = H.solve_multi(_dev(Bm), X, R)
+        Xh = _host(X)
+        for c in range(R):
+            rel = np.linalg.norm(Xh[:, c] - (c + 1) * xo) / ((c + 1) * np.linalg.norm(xo))
+            print(f"[gpu] {fx} store {store} column {c}: its {res[c]['iterations']} (oracle {its}) diff {rel:.2e}")
+            assert res[c]["converged"] and res[c]["rel_residual"] <= 1e-10
+            if store == vk.VK_STORE_FP64:
+                assert res[c]["iterations"] == its
+            else:
+                assert abs(res[c]["iterations"] - its) <= 2
+            assert rel <= XTOL[fx]
+        del H
