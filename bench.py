@@ -44,9 +44,11 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE/WRITE_SIZE (scaled by a plain-copy calibration), keyed by the
 # source file of that kernel (its hash) and the workload; any change to that
 # file invalidates them (reported as null).
-# Sources: profiles/patch_apply_p4p3_64_fp64.md, profiles/many_rhs_sv_p3dp2_64.md
+# Sources: profiles/patch_apply_p4p3_64_fp64.md, profiles/many_rhs_sv_p3dp2_64.md,
+# profiles/patch_apply_bdm4_80_fp64.md
 MEASURED_TRAFFIC = {
     ("patch_apply.hip", "6d321e57784babdb", "p4p3-64", "fp64", 1): 527.6e6,
+    ("patch_apply.hip", "6d321e57784babdb", "bdm4-80", "fp64", 1): 813.9e6,
     ("patch_gemm.hip", "55e68640323c960e", "sv-p3dp2-64", "fp32", 64): 555.2e6,
 }
 
@@ -187,6 +189,8 @@ def paper_grid(args):
     smoothers = [("damped", vk.VK_SMOOTH_DAMPED, vk.VK_WEIGHT_MULTIPLICITY),
                  ("chebyshev", vk.VK_SMOOTH_CHEBYSHEV, vk.VK_WEIGHT_NONE),
                  ("chebyshev-weighted", vk.VK_SMOOTH_CHEBYSHEV, vk.VK_WEIGHT_MULTIPLICITY)]
+    keep = args.grid_smoothers.split(",")
+    smoothers = [s for s in smoothers if s[0] in keep]
     fam = {"quad": vk.VK_TH_QUAD, "bdm": vk.VK_BDM}.get(args.grid_family, vk.VK_TH)
     for k in [int(v) for v in args.grid_k.split(",")]:
         for ell in [int(v) for v in args.grid_levels.split(",")]:
@@ -300,6 +304,8 @@ def main():
                     help="iteration counts at the paper's settings (5x5 coarsest mesh, unrestarted FGMRES)")
     ap.add_argument("--stopping-study", action="store_true",
                     help="tolerance needed for discretisation-level errors (paper settings, --grid-k/--grid-levels)")
+    ap.add_argument("--grid-smoothers", default="damped,chebyshev,chebyshev-weighted",
+                    help="smoothers of --paper-grid")
     ap.add_argument("--study-nu", type=int, default=1)
     ap.add_argument("--study-smoothers", default="damped,chebyshev")
     ap.add_argument("--grid-family", default="tri", choices=["tri", "quad", "bdm"],

@@ -474,7 +474,8 @@ def test_mixed_precision_solve_sv(p3dp2_sv):
 @pytest.mark.parametrize("fx", ["bdm2", "bdm8"])
 def test_bdm_many_rhs_and_fp32_inverses(fx, request):
     """BDM levels through the many-right-hand-side path (FP64 patch GEMMs; FP32 matrix-core GEMMs with
-    FP32 inverses, including the column-major storage of patches above 224 DoFs for BDM8)."""
+    FP32 inverses, including the column-major storage of patches above 224 DoFs for BDM8).  FP64
+    inverses with many right-hand sides are limited to patches of 128 DoFs: BDM8 reports that."""
     import paper_2409_14222_amd as vk
     from oracle import solve
     H64, OH, OV = request.getfixturevalue(fx)
@@ -488,6 +489,12 @@ def test_bdm_many_rhs_and_fp32_inverses(fx, request):
         H = vk.Hierarchy(k, n0, nl, family=vk.VK_BDM, forcing=vk.VK_F_PAPER_MMS, store=store)
         H.bind(max_rhs=R).setup()
         X = torch.zeros((L.N, R), dtype=torch.float64, device="cuda")
+        if store == vk.VK_STORE_FP64 and H.level_info(nl - 1).max_n > 128:
+            with pytest.raises(vk.VkError) as e:
+                H.solve_multi(_dev(Bm), X, R)
+            assert e.value.code == vk.VK_EINVAL
+            del H
+            continue
         _, res = H.solve_multi(_dev(Bm), X, R)
         Xh = _host(X)
         for c in range(R):
