@@ -507,3 +507,26 @@ def test_bdm_many_rhs_and_fp32_inverses(fx, request):
                 assert abs(res[c]["iterations"] - its) <= 2
             assert rel <= XTOL[fx]
         del H
+
+
+@pytest.mark.parametrize("fx", ["bdm2", "bdm4"])
+def test_bdm_gpu_velocity_is_divergence_free(fx, request):
+    """The H(div)-L2 pair's defining property (Sec. 2, the theorem on the H(div)-conforming
+    discretisation): the discrete velocity the GPU solve returns is pointwise divergence-free,
+    evaluated cell by cell with the oracle's basis."""
+    from oracle import quad
+    H, OH, OV = request.getfixturevalue(fx)
+    L = OH.finest
+    x = torch.empty(L.N, dtype=torch.float64, device="cuda")
+    res = H.solve(_dev(H.rhs()), x)
+    assert res["converged"]
+    xg = _host(x)
+    qp, _ = quad.simplex_rule(2, 3)
+    worst = scale = 0.0
+    for ci, cell in enumerate(L.cells):
+        v0, J = L.cell_geometry(cell)
+        _, G = L.velocity(ci, xg, v0 + qp @ J.T)
+        worst = max(worst, np.abs(G[:, 0, 0] + G[:, 1, 1]).max())
+        scale = max(scale, np.abs(G).max())
+    print(f"[gpu] {fx}: max |div u_h| {worst:.2e} (max |grad u_h| {scale:.2e})")
+    assert worst <= 1e-9 * scale
