@@ -322,12 +322,34 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy (y = x), the reference for HBM counter scaling")
+    ap.add_argument("--stream-bandwidth", action="store_true",
+                    help="run only plain streaming kernels over 2 GiB (a read-only reduction and a copy) and "
+                         "print their HBM rates: the attainable bandwidth next to the 8 TB/s peak")
     ap.add_argument("--cpu-sample", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-iterations", type=int, default=0, help=argparse.SUPPRESS)
     args = ap.parse_args()
 
     if args.cpu_sample:
         print(json.dumps(cpu_sample(args.cpu_sample, args.cpu_iterations)))
+        return
+    if args.stream_bandwidth:
+        import torch
+        n = 256 * 1024 * 1024  # 2 GiB of float64
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        out = {}
+        for name, fn, nbytes in (("read (sum)", lambda: x.sum(), 8 * n), ("copy (y = x)", lambda: y.copy_(x), 16 * n)):
+            for _ in range(3):
+                fn()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(20):
+                fn()
+            b.record()
+            b.synchronize()
+            s_per = a.elapsed_time(b) / 20 / 1e3
+            out[name] = {"GB/s": nbytes / s_per / 1e9, "frac_of_8TBs": nbytes / s_per / 8e12}
+        print(json.dumps(out))
         return
     if args.copy_calibration:
         import torch
