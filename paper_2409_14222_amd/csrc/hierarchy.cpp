@@ -411,7 +411,22 @@ vk_status fgmres(vk_hierarchy* h, const double* b_in, double* x, const vk_solve_
     return VK_OK;
   }
   launch_copy(N, h->bb, h->r, s);
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hh(3 * (m + 2));
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+  // pinned slots for the Hessenberg read-back (allocated once, grown with the restart length)
+  const size_t col_elems = 3 * (size_t)(m + 2);
+  if (h->hh_pin_elems < 2 * col_elems) {
+    if (h->hh_pin) HIPCHECK(hipHostFree(h->hh_pin));
+    h->hh_pin = nullptr;
+    h->hh_pin_elems = 0;
+    HIPCHECK(hipHostMalloc((void**)&h->hh_pin, 2 * col_elems * sizeof(double)));
+    h->hh_pin_elems = 2 * col_elems;
+  }
+  for (auto& e : h->ev_copy)
+    if (!e) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  auto step = [&](int j) {
+    if (o.use_graphs) arnoldi_step_graph(h, j, o);
+    else arnoldi_step(h, j, o);
+  };
   double beta = bnorm;
   while (true) {
     beta = std::sqrt(dot_host(h, N, h->r, h->r));
@@ -423,11 +438,18 @@ vk_status fgmres(vk_hierarchy* h, const double* b_in, double* x, const vk_solve_
     g[0] = beta;
     launch_div(N, h->r, beta, h->V, s);
     int jlast = -1;
+    step(0);
     for (int j = 0; j < m; ++j) {
-      if (o.use_graphs) arnoldi_step_graph(h, j, o);
-      else arnoldi_step(h, j, o);
-      HIPCHECK(hipMemcpyAsync(hh.data(), h->small, 3 * (m + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHECK(hipStreamSynchronize(s));
+      // step j is enqueued; copy its Hessenberg column out, then (while the residual estimate is
+      // still far from the tolerance) enqueue step j + 1 before waiting for the copy.  Step j + 1
+      // depends only on device data, so the result is the same whether or not it runs ahead; if
+      // the cycle ends at j, its output (V[j + 2], Z[j + 1]) is simply not used.
+      double* hh = h->hh_pin + (size_t)(j & 1) * col_elems;
+      HIPCHECK(hipMemcpyAsync(hh, h->small, col_elems * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipEventRecord(h->ev_copy[j & 1], s));
+      const bool ahead = j + 1 < m && its + 1 < o.maxit && std::fabs(g[j]) > 100.0 * o.rtol * bnorm;
+      if (ahead) step(j + 1);
+      HIPCHECK(hipEventSynchronize(h->ev_copy[j & 1]));
       const double hn = std::sqrt(hh[2 * (m + 2)]);
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[(m + 2) + i];
       H[(size_t)(j + 1) * m + j] = hn;
@@ -449,6 +471,7 @@ vk_status fgmres(vk_hierarchy* h, const double* b_in, double* x, const vk_solve_
       jlast = j;
       if (info && info->h_history) info->h_history[its] = std::fabs(g[j + 1]);
       if (std::fabs(g[j + 1]) <= o.rtol * bnorm || its >= o.maxit || hn == 0.0) break;
+      if (!ahead && j + 1 < m) step(j + 1);
     }
     const int nk = jlast + 1;
     h->ybuf.assign(nk, 0.0);
@@ -929,6 +952,9 @@ vk_status vk_hierarchy_destroy(vk_hierarchy* h) {
     drop_graphs(h);
     for (auto& e : h->ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (auto& e : h->ev_pending) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto& e : h->ev_copy)
+      if (e) (void)hipEventDestroy(e);
+    if (h->hh_pin) (void)hipHostFree(h->hh_pin);
     delete h;
     return VK_OK;
   });

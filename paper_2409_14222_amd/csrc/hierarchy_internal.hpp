@@ -107,6 +107,11 @@ struct vk_hierarchy {
   int64_t t_launches = 0;
   double t_ms = 0.0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free, ev_pending;
+  // pinned read-back of the Hessenberg columns (two slots) and their copy-done events, so that
+  // the next Arnoldi step can be enqueued before the host has read the current one
+  double* hh_pin = nullptr;
+  size_t hh_pin_elems = 0;
+  hipEvent_t ev_copy[2] = {nullptr, nullptr};
 
   bool fp32() const { return opts.store == VK_STORE_FP32; }
   bool cheb() const { return opts.smoother == VK_SMOOTH_CHEBYSHEV; }
