@@ -1,0 +1,230 @@
+"""GPU parity at the benchmarked size: P4-P3 Taylor-Hood on the 64x64 two-triangle mesh, five
+levels (4x4 .. 64x64, 167,299 DoFs), in the launch configuration the benchmark times (autotuned
+shapes, one right-hand side, FP64 inverses in the symmetric tiled storage).
+
+The oracle is built at full size once per module (about half a minute of CPU) and compared:
+SpMV and transfers element by element, sampled patch inverses, one finest-level sweep as a
+whole vector, and the full FGMRES solve (iteration count, residual history, true residual with
+the oracle's matrix, solution, discretisation errors).
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(float).eps
+
+
+def _dev(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def headline():
+    import paper_2409_14222_amd as vk
+    from oracle import fields, solve
+    print("[gpu] full size: oracle P4-P3 64x64 hierarchy and smoothers", flush=True)
+    OH, OV = solve.setup(2, 4, 4, 5, 1.0, fields.baseline_mms)
+    print("[gpu] full size: library hierarchy, setup, autotune", flush=True)
+    side = torch.cuda.Stream()  # a non-default stream, as the benchmark binds (graph capture needs one)
+    with torch.cuda.stream(side):
+        H = vk.Hierarchy(4, 4, 5).bind(max_rhs=1).setup()
+    H.autotune(reps=3)
+    return H, OH, OV
+
+
+def _cond_bound_sampled(S, count=300, seed=11):
+    """max n_i cond(K_i) over a seeded sample of patches (plus the largest), times 4 for the rest."""
+    rng = np.random.default_rng(seed)
+    J = len(S.patches)
+    sizes = np.array([len(I) for I in S.patches])
+    picks = set(rng.integers(0, J, count).tolist()) | {int(np.argmax(sizes))}
+    return 4 * max(len(S.patches[i]) * np.linalg.cond(S.patch_matrix(i)) for i in picks)
+
+
+def test_full_spmv_and_transfers(headline):
+    H, OH, OV = headline
+    for l in (3, 4):
+        L = OH.levels[l]
+        x = synth.vector(L.N, 1200 + l)
+        y = torch.empty(L.N, dtype=torch.float64, device="cuda")
+        H.spmv(l, _dev(x), y)
+        cV = 2 * (L.k + 3) ** L.dim
+        bound = (cV + 2 * np.diff(L.K.indptr)) * EPS * (abs(L.K) @ np.abs(x))
+        assert np.all(np.abs(_host(y) - L.K @ x) <= bound)
+        P = OH.P[l]
+        xc = synth.vector(P.shape[1], 1300 + l)
+        ef = _dev(x)
+        H.prolong_add(l, _dev(xc), ef)
+        assert np.all(np.abs(_host(ef) - (x + P @ xc)) <= 1e-13 * (abs(P) @ np.abs(xc) + np.abs(x)))
+        rc = torch.empty(P.shape[1], dtype=torch.float64, device="cuda")
+        H.restrict(l, _dev(x), rc)
+        assert np.all(np.abs(_host(rc) - P.T @ x) <= 1e-13 * (abs(P.T) @ np.abs(x)))
+
+
+def test_full_patch_inverses_sampled(headline):
+    H, OH, OV = headline
+    l = 4
+    S = OV.smoothers[l]
+    rng = np.random.default_rng(12)
+    sizes = np.array([len(I) for I in S.patches])
+    picks = sorted(set(rng.integers(0, len(S.patches), 24).tolist()) |
+                   {0, len(S.patches) - 1, int(np.argmax(sizes)), int(np.argmin(sizes))})
+    for i in picks:
+        n = len(S.patches[i])
+        out = torch.empty(n * n, dtype=torch.float64, device="cuda")
+        H.patch_inverse(l, i, out)
+        X = _host(out).reshape(n, n, order="F")
+        Ki = S.patch_matrix(i)
+        Xo = sla.lu_solve(S.lu[i], np.eye(n))
+        c = np.linalg.cond(Ki)
+        assert np.abs(Ki @ X - np.eye(n)).max() <= 8 * n * EPS * c
+        assert np.abs(X - Xo).max() <= 8 * n * EPS * c * np.abs(Xo).max()
+
+
+def test_full_finest_sweep(headline):
+    H, OH, OV = headline
+    l = 4
+    L, S = OH.levels[l], OV.smoothers[l]
+    b, x0 = synth.vector(L.N, 1400), synth.vector(L.N, 1401)
+    x = _dev(x0)
+    H.smooth(l, _dev(b), x, 1)
+    ref = S.sweep(b, x0)
+    tol = 8 * EPS * _cond_bound_sampled(S)
+    err = _rel(_host(x), ref)
+    print(f"[gpu] full size sweep: rel err {err:.2e} (tol {tol:.1e})")
+    assert err <= tol
+
+
+def test_full_solve_matches_oracle(headline):
+    """The benchmarked solve.  Solution tolerance: a random relative rhs perturbation of 1e-10 moves
+    the P4-P3 solution by up to 4.4e-6 at 16x16 and 6.4e-6 at 32x32 (sparse direct solves, five
+    draws); allowing the same growth once more to 64x64, two 1e-10-residual solutions may differ by
+    2 x 1.5 x 6.4e-6 = 1.9e-5.  The iteration count, the residual history and the true residual are
+    the tight checks; the printed difference is typically many orders below the bound."""
+    from oracle import norms, solve
+    H, OH, OV = headline
+    L = OH.finest
+    b = H.rhs()
+    ob = solve.consistent_rhs(L)
+    assert np.abs(b - ob).max() <= 1e-13 * np.abs(ob).max()
+    x = torch.empty(L.N, dtype=torch.float64, device="cuda")
+    res = H.solve(_dev(b), x, history=True)
+    print("[gpu] full size: oracle FGMRES (about half a minute)", flush=True)
+    xo, its, hist, conv = solve.solve(OH, OV)
+    xg = _host(x)
+    diff = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    print(f"[gpu] full size: its gpu {res['iterations']} oracle {its}, rel res {res['rel_residual']:.2e}, "
+          f"solution diff {diff:.2e}")
+    assert res["converged"] and conv
+    assert res["iterations"] == its
+    assert res["rel_residual"] <= 1e-10
+    assert np.linalg.norm(ob - L.K @ xg) <= 1.05e-10 * np.linalg.norm(ob)
+    assert diff <= 1.9e-5
+    gh, oh = res["history"][: its + 1], np.array(hist)
+    n10 = min(its, 10) + 1
+    assert np.all(np.abs(gh[:n10] - oh[:n10]) <= 1e-6 * oh[:n10] + 1e-9 * oh[0])
+    assert np.all(np.abs(gh - oh) <= 1e-6 * oh[0])
+    # discretisation errors of the two solutions (library norms vs oracle norms)
+    eg, eo = H.solution_errors(xg), norms.errors(L, xo)
+    assert abs(eg[0] - eo[0]) <= 1e-6 * eo[0] and abs(eg[1] - eo[1]) <= 1e-6 * eo[1] + 1e-12
+    # graph replay of the Arnoldi steps gives the same bits as the eager solve
+    x2 = torch.empty_like(x)
+    H.solve(_dev(b), x2, graphs=True)
+    assert torch.equal(x, x2)
+
+
+@pytest.fixture(scope="module")
+def cube():
+    from oracle import fields, solve
+    print("[gpu] full size: oracle 3D P2-P1 16^3 hierarchy and smoothers (about a minute)", flush=True)
+    return solve.setup(3, 2, 4, 3, 1.0, fields.cube_mms)
+
+
+@pytest.mark.parametrize("store", ["fp64", "fp32"])
+def test_full_3d_solve(cube, store):
+    """3D P2-P1 on 16^3 cubes (94,286 DoFs, vertex stars up to 196 DoFs), as benchmarked: FP64
+    inverses must reproduce the oracle's iteration count; FP32-stored inverses (factored in FP64)
+    within two iterations, with the FP64 FGMRES still reaching 1e-10 against the oracle's matrix.
+    Solution tolerance for FP64: twice the measured sensitivity bound of the Taylor-Hood cases
+    (1.9e-5, see the 2D test); the FP32 solution differs from the FP64 one by its own 1e-10
+    residual, the same bound."""
+    import paper_2409_14222_amd as vk
+    from oracle import solve
+    OH, OV = cube
+    L = OH.finest
+    H = vk.Hierarchy(2, 4, 3, dim=3, forcing=vk.VK_F_CUBE_MMS,
+                     store=vk.VK_STORE_FP32 if store == "fp32" else vk.VK_STORE_FP64)
+    H.bind(max_rhs=1).setup()
+    H.autotune(reps=3)
+    b = H.rhs()
+    ob = solve.consistent_rhs(L)
+    assert np.abs(b - ob).max() <= 1e-13 * np.abs(ob).max()
+    x = torch.empty(L.N, dtype=torch.float64, device="cuda")
+    res = H.solve(_dev(b), x, history=True)
+    xo, its, hist, conv = solve.solve(OH, OV)
+    xg = _host(x)
+    diff = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    print(f"[gpu] full size 3D {store}: its gpu {res['iterations']} oracle {its}, "
+          f"rel res {res['rel_residual']:.2e}, solution diff {diff:.2e}")
+    assert res["converged"] and conv
+    if store == "fp64":
+        assert res["iterations"] == its
+        n10 = min(its, 10) + 1
+        gh, oh = res["history"][:n10], np.array(hist[:n10])
+        assert np.all(np.abs(gh - oh) <= 1e-6 * oh + 1e-9 * oh[0])
+    else:
+        assert abs(res["iterations"] - its) <= 2
+    assert np.linalg.norm(ob - L.K @ xg) <= 1.05e-10 * np.linalg.norm(ob)
+    assert diff <= 1.9e-5
+
+
+def test_full_sv_64_rhs_fp32():
+    """Scott-Vogelius P3-dP2 on the barycentric refinement of 64x64 (367,874 DoFs), 64 seeded random
+    forcings solved together with FP32 inverses on the matrix cores, as benchmarked.  The oracle
+    takes minutes to build at this size (its clipped-polygon pressure transfers), so the checks are
+    properties that hold at any size, with the oracle's parity shown at 16x16 elsewhere: every
+    column meets 1e-10 against the library's matrix recomputed on the CPU, and a right-hand side
+    gives bitwise the same solution and iteration count alone as in the batch."""
+    import scipy.sparse as sp
+
+    import paper_2409_14222_amd as vk
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        H = vk.Hierarchy(3, 4, 5, family=vk.VK_SV, store=vk.VK_STORE_FP32).bind(max_rhs=64).setup()
+    H.autotune(reps=3)
+    R = 64
+    cols = [H.rhs_random(synth.forcing_coeffs(synth.SEED + j)) for j in range(R)]
+    B = np.stack(cols, axis=1)
+    N = B.shape[0]
+    X = torch.empty((N, R), dtype=torch.float64, device="cuda")
+    _, infos = H.solve_multi(_dev(B), X, R)
+    Xh = _host(X)
+    rp, col, val = H.csr(4)
+    K = sp.csr_matrix((val, col, rp), shape=(N, N))
+    worst = 0.0
+    for c in range(R):
+        assert infos[c]["converged"]
+        rel = np.linalg.norm(B[:, c] - K @ Xh[:, c]) / np.linalg.norm(B[:, c])
+        worst = max(worst, rel)
+        assert rel <= 1.05e-10
+    print(f"[gpu] full size SV 64 RHS: iterations {np.mean([i['iterations'] for i in infos]):.1f}, "
+          f"worst true residual {worst:.2e}")
+    for c in (0, 37, 63):
+        x1 = torch.empty((N, 1), dtype=torch.float64, device="cuda")
+        _, i1 = H.solve_multi(_dev(B[:, c:c + 1]), x1, 1)
+        assert np.array_equal(_host(x1)[:, 0], Xh[:, c])
+        assert i1[0]["iterations"] == infos[c]["iterations"]
