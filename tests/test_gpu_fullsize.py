@@ -228,3 +228,51 @@ def test_full_sv_64_rhs_fp32():
         _, i1 = H.solve_multi(_dev(B[:, c:c + 1]), x1, 1)
         assert np.array_equal(_host(x1)[:, 0], Xh[:, c])
         assert i1[0]["iterations"] == infos[c]["iterations"]
+
+
+def test_full_bdm4_80_against_oracle_convergence():
+    """BDM4-dP3 with interior penalty on 80x80 (415,200 DoFs, the BDM benchmark): the oracle is too
+    slow to build at this size, so the GPU solve is tied to it through the discretisation error.
+    The oracle solves 10x10 and 20x20 directly; their errors fix the observed convergence rate,
+    which predicts the 80x80 errors two refinements on.  The GPU solution's errors must match the
+    prediction to 3 % (velocity) and 5 % (pressure): a wrong matrix, transfer or solve at full size
+    would not.  The solve also meets 1e-10 against the library's matrix recomputed on the CPU, up to
+    the rounding of that CPU product."""
+    import math
+
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+
+    import paper_2409_14222_amd as vk
+    from oracle import bdm, fields, solve
+    errs = []
+    for n in (10, 20):
+        L = bdm.BDMLevel(4, n, 1.0, fields.paper_mms(1.0))
+        z = L.nullvec()
+        b = solve.consistent_rhs(L)
+        Kb = sp.bmat([[L.K, sp.csr_matrix(z[:, None])], [sp.csr_matrix(z[None, :]), None]]).tocsc()
+        errs.append(bdm.errors(L, spla.spsolve(Kb, np.concatenate([b, [0.0]]))[:L.N]))
+    pred = [errs[1][q] * (errs[1][q] / errs[0][q]) ** 2 for q in (0, 1)]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        H = vk.Hierarchy(4, 5, 5, family=vk.VK_BDM, forcing=vk.VK_F_PAPER_MMS).bind(max_rhs=1).setup()
+    H.autotune(reps=3)
+    bh = H.rhs()
+    x = torch.empty(bh.shape[0], dtype=torch.float64, device="cuda")
+    res = H.solve(_dev(bh), x)
+    xg = _host(x)
+    e = H.solution_errors(xg)
+    rates = [math.log2(errs[0][q] / errs[1][q]) for q in (0, 1)]
+    print(f"[gpu] full size BDM4 80x80: its {res['iterations']}, rates {rates[0]:.3f} {rates[1]:.3f}, "
+          f"errors {e[0]:.4e} {e[1]:.4e}, predicted {pred[0]:.4e} {pred[1]:.4e}")
+    assert res["converged"]
+    rp, col, val = H.csr(4)
+    K = sp.csr_matrix((val, col, rp), shape=(len(rp) - 1,) * 2)
+    # the CPU product K x carries its own rounding: about sqrt(nnz_i) eps (|K| |x|)_i per row, which
+    # for this system is not small against 1e-10 ||b|| (the penalty and the h^-2 cancellation)
+    floor = EPS * np.linalg.norm(abs(K) @ np.abs(xg)) / np.linalg.norm(bh)
+    rel = np.linalg.norm(bh - K @ xg) / np.linalg.norm(bh)
+    print(f"[gpu] full size BDM4 80x80: CPU-recomputed residual {rel:.2e}, rounding scale {floor:.2e}")
+    assert rel <= 1.05e-10 + 2 * np.sqrt(np.diff(rp).max()) * floor
+    assert abs(e[0] - pred[0]) <= 0.03 * pred[0]
+    assert abs(e[1] - pred[1]) <= 0.05 * pred[1]
