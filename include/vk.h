@@ -25,8 +25,11 @@
  *  - Device memory is owned by the caller: the library reports how many bytes
  *    it needs (vk_hierarchy_workspace_bytes), the caller allocates one buffer
  *    and binds it together with a HIP stream (vk_hierarchy_bind).  The library
- *    never allocates or frees device memory.  All device work is enqueued on
- *    the bound stream; calls return without synchronising unless stated.
+ *    never allocates or frees device memory; vk_solve allocates a small pinned
+ *    host buffer (2 x 3 (restart + 2) doubles) on its first call for the
+ *    Hessenberg read-back, released by vk_hierarchy_destroy.  All device work
+ *    is enqueued on the bound stream; calls return without synchronising
+ *    unless stated.
  *  - Free-DoF numbering: velocity lattice points of the P_k lattice (spacing
  *    1/(k n)) that are not on the boundary, lexicographic with x fastest,
  *    components interleaved (dof = dim * idx + c); then all points of the
