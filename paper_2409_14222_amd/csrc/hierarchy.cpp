@@ -344,10 +344,17 @@ void arnoldi_step(vk_hierarchy* h, int j, const vk_solve_opts& o) {
   vcycle(h, h->L() - 1, vj, zj, o.nu_pre, o.nu_post);
   launch_csr(0, N, F.k_lanes, F.rowptr, F.col, F.val, zj, nullptr, w, s);
   launch_multidot(N, j + 1, h->V, N, w, h->partial, h->small, s);
-  launch_multiaxpy(N, j + 1, -1.0, h->V, N, h->small, w, s);
-  launch_multidot(N, j + 1, h->V, N, w, h->partial, h->small + (m + 2), s);
-  launch_multiaxpy(N, j + 1, -1.0, h->V, N, h->small + (m + 2), w, s);
-  launch_multidot(N, 1, w, 0, w, h->partial, h->small + 2 * (m + 2), s);
+  if (j + 1 <= kFusedMaxNv1) {
+    // CGS2 with each update fused into the following reduction (bitwise the unfused values)
+    launch_axpy_multidot(false, N, j + 1, -1.0, h->V, N, h->small, w, h->partial, h->small + (m + 2), s);
+    launch_axpy_multidot(true, N, j + 1, -1.0, h->V, N, h->small + (m + 2), w, h->partial,
+                         h->small + 2 * (m + 2), s);
+  } else {
+    launch_multiaxpy(N, j + 1, -1.0, h->V, N, h->small, w, s);
+    launch_multidot(N, j + 1, h->V, N, w, h->partial, h->small + (m + 2), s);
+    launch_multiaxpy(N, j + 1, -1.0, h->V, N, h->small + (m + 2), w, s);
+    launch_multidot(N, 1, w, 0, w, h->partial, h->small + 2 * (m + 2), s);
+  }
   launch_div_norm(N, w, h->small + 2 * (m + 2), s);
   check_launch();
 }

@@ -879,6 +879,66 @@ void launch_multiaxpy(int n, int nv, double sign, const double* V, int64_t ldv, 
   multiaxpy_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, nv, sign, V, ldv, h, w);
 }
 
+// w[i] += sign * sum_v V[v*ldv + i] * h[v] (the terms in v order, as multiaxpy_kernel), then the
+// block partials of the dots V_v . w (or of w . w for SELF) with the updated w, in the row order and
+// tree of multidot_partial_kernel: the fused pass gives bitwise the values of the two separate ones
+// and reads V once.  NV (8, 16 or 32 >= nv) sizes the register arrays.
+template <bool SELF, int NV>
+__global__ void __launch_bounds__(256) axpy_multidot_kernel(int n, int nv, double sign, const double* __restrict__ V,
+                                                            int64_t ldv, const double* __restrict__ h,
+                                                            double* __restrict__ w, double* __restrict__ partial) {
+  constexpr int ND = SELF ? 1 : NV;
+  __shared__ double sh[256];
+  double hv[NV];
+#pragma unroll
+  for (int t = 0; t < NV; ++t) hv[t] = t < nv ? h[t] : 0.0;
+  double acc[ND];
+#pragma unroll
+  for (int t = 0; t < ND; ++t) acc[t] = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += kReduceBlocks * 256) {
+    double x[NV];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) x[t] = t < nv ? V[(int64_t)t * ldv + i] : 0.0;
+    double sacc = 0.0;
+#pragma unroll
+    for (int t = 0; t < NV; ++t)
+      if (t < nv) sacc += x[t] * hv[t];
+    const double wi = w[i] + sign * sacc;
+    w[i] = wi;
+    if (SELF) {
+      acc[0] += wi * wi;
+    } else {
+#pragma unroll
+      for (int t = 0; t < ND; ++t) acc[t] += x[t] * wi;
+    }
+  }
+  const int nd = SELF ? 1 : nv;
+#pragma unroll
+  for (int t = 0; t < ND; ++t) {
+    if (t >= nd) break;  // uniform across the block
+    const double r = block_sum256(acc[t], sh);
+    if (threadIdx.x == 0) partial[t * kReduceBlocks + blockIdx.x] = r;
+  }
+}
+
+template <bool SELF>
+static void axpy_multidot_launch(int n, int nv, double sign, const double* V, int64_t ldv, const double* h,
+                                 double* w, double* partial, hipStream_t s) {
+  if (nv <= 8)
+    axpy_multidot_kernel<SELF, 8><<<kReduceBlocks, 256, 0, s>>>(n, nv, sign, V, ldv, h, w, partial);
+  else if (nv <= 16)
+    axpy_multidot_kernel<SELF, 16><<<kReduceBlocks, 256, 0, s>>>(n, nv, sign, V, ldv, h, w, partial);
+  else
+    axpy_multidot_kernel<SELF, 32><<<kReduceBlocks, 256, 0, s>>>(n, nv, sign, V, ldv, h, w, partial);
+}
+
+void launch_axpy_multidot(bool self, int n, int nv, double sign, const double* V, int64_t ldv, const double* h,
+                          double* w, double* partial, double* out, hipStream_t s) {
+  if (self) axpy_multidot_launch<true>(n, nv, sign, V, ldv, h, w, partial, s);
+  else axpy_multidot_launch<false>(n, nv, sign, V, ldv, h, w, partial, s);
+  reduce_final_kernel<<<self ? 1 : nv, 256, 0, s>>>(partial, out);
+}
+
 __global__ void __launch_bounds__(256) div_kernel(int n, const double* x, double a, double* y) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) y[i] = x[i] / a;

@@ -88,6 +88,12 @@ void launch_multidot(int n, int nv, const double* V, int64_t ldv, const double* 
 // w[i] += sign * sum_v V[v*ldv + i] * h[v]
 void launch_multiaxpy(int n, int nv, double sign, const double* V, int64_t ldv, const double* h, double* w,
                       hipStream_t s);
+// w[i] += sign * sum_v V[v*ldv + i] * h[v], then out[v] = V_v . w (v < nv), or out[0] = w . w when
+// self: one pass over V with the same values as launch_multiaxpy followed by launch_multidot.
+// nv <= kFusedMaxNv1.
+constexpr int kFusedMaxNv1 = 32;
+void launch_axpy_multidot(bool self, int n, int nv, double sign, const double* V, int64_t ldv, const double* h,
+                          double* w, double* partial, double* out, hipStream_t s);
 // y = x / alpha
 void launch_div(int n, const double* x, double alpha, double* y, hipStream_t s);
 // y = y / sqrt(nn[0]), nn a device scalar (squared norm)
