@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(512) axpy_dots_kernel(int n, int R, int nv, co
     const int64_t o = (int64_t)i * R + cl;
     double x[NV];
 #pragma unroll
-    for (int t = 0; t < NV; ++t) x[t] = V[(int64_t)min(t, nv - 1) * ldv + o];
+    for (int t = 0; t < NV; ++t) x[t] = t < nv ? V[(int64_t)t * ldv + o] : 0.0;  // nv is uniform
     double sacc = 0.0;
 #pragma unroll
     for (int t = 0; t < NV; ++t)
