@@ -155,6 +155,13 @@ def bdm4():
 
 
 @pytest.fixture(scope="module")
+def bdm6():
+    """BDM6-dP5 on 4x4, levels 1/2/4: interior extended patches of exactly 224 DoFs, the largest
+    size held in the symmetric tiled storage and inverted in registers."""
+    return _bdm_fixture(6, 1, 3)
+
+
+@pytest.fixture(scope="module")
 def bdm8():
     """BDM8-dP7 on 2x2, levels 1/2: extended cell patches of up to 333 DoFs (global-memory inversion)."""
     return _bdm_fixture(8, 1, 2)
@@ -168,11 +175,11 @@ def bdm8():
 # differ by twice that; iteration counts and residual histories are still compared tightly.
 # Quadrilaterals, measured the same way: Q2-Q1 16x16 1.4e-7, Q4-Q3 8x8 9.0e-7, Q7-Q6 4x4 1.1e-5
 # BDM with interior penalty, the same way: BDM1 8x8 2.6e-9, BDM2 8x8 2.1e-8, BDM4 8x8 1.4e-7,
-# BDM8 2x2 9.9e-7
+# BDM6 4x4 4.6e-7, BDM8 2x2 9.9e-7
 XTOL = {"p2p1": 1e-8, "p4p3": 1e-8, "p2p1_3d": 1e-8, "p3dp2_sv": 1e-6, "p6p5": 4e-5, "p8p7": 1.5e-4,
-        "q2q1": 3e-7, "q4q3": 2e-6, "q7q6": 2.2e-5, "bdm1": 1e-8, "bdm2": 5e-8, "bdm4": 3e-7, "bdm8": 2e-6}
+        "q2q1": 3e-7, "q4q3": 2e-6, "q7q6": 2.2e-5, "bdm1": 1e-8, "bdm2": 5e-8, "bdm4": 3e-7, "bdm6": 1e-6, "bdm8": 2e-6}
 ALL = ["p2p1", "p4p3", "p2p1_3d", "p3dp2_sv", "p6p5", "p8p7", "q2q1", "q4q3", "q7q6", "bdm1", "bdm2", "bdm4",
-       "bdm8"]
+       "bdm6", "bdm8"]
 
 
 def _assembly_terms(L):
