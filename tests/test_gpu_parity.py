@@ -537,3 +537,35 @@ def test_bdm_gpu_velocity_is_divergence_free(fx, request):
         scale = max(scale, np.abs(G).max())
     print(f"[gpu] {fx}: max |div u_h| {worst:.2e} (max |grad u_h| {scale:.2e})")
     assert worst <= 1e-9 * scale
+
+
+def test_bdm_mixed_precision_and_graphs(bdm4):
+    """BDM4-dP3 with FP32-stored inverses (factored in FP64): the FP64 FGMRES reaches 1e-10 against
+    the oracle's matrix within two iterations of the FP64 count; and graph replay of the Arnoldi
+    steps reproduces the eager FP64 solve bit for bit."""
+    import paper_2409_14222_amd as vk
+    from oracle import solve
+    H64, OH, OV = bdm4
+    L = OH.finest
+    ob = solve.consistent_rhs(L)
+    xo, its, _, _ = solve.solve(OH, OV)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        H = vk.Hierarchy(4, 2, 3, family=vk.VK_BDM, forcing=vk.VK_F_PAPER_MMS, store=vk.VK_STORE_FP32).bind().setup()
+        G = vk.Hierarchy(4, 2, 3, family=vk.VK_BDM, forcing=vk.VK_F_PAPER_MMS).bind().setup()
+    b = H.rhs()
+    x = torch.empty(L.N, dtype=torch.float64, device="cuda")
+    res = H.solve(_dev(b), x)
+    xg = _host(x)
+    print(f"[gpu] bdm4 fp32 inverses: its {res['iterations']} (fp64 oracle {its}), "
+          f"diff {np.linalg.norm(xg - xo) / np.linalg.norm(xo):.2e}")
+    assert res["converged"] and abs(res["iterations"] - its) <= 2
+    assert np.linalg.norm(ob - L.K @ xg) <= 1.05e-10 * np.linalg.norm(ob)
+    assert np.linalg.norm(xg - xo) <= XTOL["bdm4"] * np.linalg.norm(xo)
+    xe = torch.empty(L.N, dtype=torch.float64, device="cuda")
+    G.solve(_dev(b), xe)
+    for rep in range(2):
+        xr = torch.empty_like(xe)
+        G.solve(_dev(b), xr, graphs=True)
+        side.synchronize()
+        assert torch.equal(xr, xe), rep
