@@ -197,7 +197,8 @@ def test_full_sv_64_rhs_fp32():
     forcings solved together with FP32 inverses on the matrix cores, as benchmarked.  The oracle
     takes minutes to build at this size (its clipped-polygon pressure transfers), so the checks are
     properties that hold at any size, with the oracle's parity shown at 16x16 elsewhere: every
-    column meets 1e-10 against the library's matrix recomputed on the CPU, and a right-hand side
+    column meets 1e-10 against the library's matrix recomputed on the CPU (up to the rounding of
+    that product), and a right-hand side
     gives bitwise the same solution and iteration count alone as in the batch."""
     import scipy.sparse as sp
 
@@ -216,11 +217,14 @@ def test_full_sv_64_rhs_fp32():
     rp, col, val = H.csr(4)
     K = sp.csr_matrix((val, col, rp), shape=(N, N))
     worst = 0.0
+    row_terms = 2 * np.sqrt(np.diff(rp).max())
     for c in range(R):
         assert infos[c]["converged"]
         rel = np.linalg.norm(B[:, c] - K @ Xh[:, c]) / np.linalg.norm(B[:, c])
         worst = max(worst, rel)
-        assert rel <= 1.05e-10
+        # the CPU product carries its own rounding, about sqrt(nnz_i) eps (|K| |x|)_i per row
+        floor = EPS * np.linalg.norm(abs(K) @ np.abs(Xh[:, c])) / np.linalg.norm(B[:, c])
+        assert rel <= 1.05e-10 + row_terms * floor
     print(f"[gpu] full size SV 64 RHS: iterations {np.mean([i['iterations'] for i in infos]):.1f}, "
           f"worst true residual {worst:.2e}")
     for c in (0, 37, 63):
