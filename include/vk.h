@@ -215,13 +215,20 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_workspace, size_t bytes, in
                             void* hip_stream);
 
 /* Matrix-full patch setup on the device: gathers every K_i = K[I_i, I_i]
- * from the CSR matrix (Sec. 3.1), inverts it by Gauss-Jordan elimination
- * with partial pivoting in FP64 and stores the inverse (FP64 or FP32).  With
+ * from the CSR matrix (Sec. 3.1), inverts it by Gauss-Jordan elimination in
+ * FP64 and stores the inverse (FP64 or FP32).  Patches of up to 224 DoFs are
+ * eliminated with partial pivoting (largest |entry| of the column, ties to the
+ * lowest row); larger ones (224 < n <= 512, vertex stars of P6..P8) by blocked
+ * Gauss-Jordan without pivoting, which relies on the patch ordering (velocity
+ * DoFs before pressure DoFs: the pivots run through the positive definite
+ * velocity block, then the negative definite pressure Schur complement) and
+ * reports a pivot of magnitude <= n eps max|K_i| as singular.  With
  * VK_SMOOTH_CHEBYSHEV it then estimates lambda on every level l >= 1 (the
  * Arnoldi vectors run on the device through the FGMRES basis, the small
  * Hessenberg eigenproblem on the host, vk_hessenberg_eigenvalues).
  * Synchronises; VK_ESINGULAR (and the level/patch in vk_last_error) on a zero
- * pivot; VK_ENAN if the estimate is not a positive finite number. */
+ * pivot (pivoted path) or a pivot under that floor (unpivoted path); VK_ENAN if
+ * the estimate is not a positive finite number. */
 vk_status vk_patches_setup(vk_hierarchy* h);
 
 vk_status vk_level_info_get(const vk_hierarchy* h, int level, vk_level_info* info);
@@ -328,6 +335,11 @@ vk_status vk_tuning_set(vk_hierarchy* h, int level, const vk_tuning* t);
  * dispatches; many right-hand sides: the patch GEMM), HIP events around every
  * launch while enabled: launches and total milliseconds since the last reset. */
 vk_status vk_kernel_timing(vk_hierarchy* h, int enable, int reset, int64_t* launches, double* total_ms);
+/* Timing of whole finest-level smoothing sweeps (the residual SpMV/SpMM, the
+ * patch apply and the scatter of one sweep, HIP events around the three
+ * launches; outside graph capture): the time the Vanka DoF-sweep rate is
+ * measured over.  Same enable/reset/read semantics as vk_kernel_timing. */
+vk_status vk_sweep_timing(vk_hierarchy* h, int enable, int reset, int64_t* sweeps, double* total_ms);
 
 /* ---------------------------------------------------------------- serving
  * Continuous batching of Stokes solves (2D Taylor-Hood, coarsest mesh 4 x 4,
@@ -378,8 +390,13 @@ typedef struct vk_server_stats {
 } vk_server_stats;
 
 const char* vk_server_last_error(void);
-/* d_pool: caller-owned device memory (256-byte aligned) the server carves hierarchies from. */
-vk_status vk_server_create(const vk_server_opts* opts, void* d_pool, size_t pool_bytes, vk_server** out);
+/* d_pool: caller-owned device memory (256-byte aligned) the server carves hierarchies from.
+ * hip_streams: n_streams (1..64) caller-owned, non-null HIP streams (hipStream_t, e.g. torch
+ * streams) on the pool's device; resident hierarchies take them in turn, so up to n_streams
+ * residents overlap on the device.  The server never creates or destroys a stream; the streams
+ * must outlive it.  Residents sharing a stream run one after the other; results are the same. */
+vk_status vk_server_create(const vk_server_opts* opts, void* d_pool, size_t pool_bytes, void* const* hip_streams,
+                           int n_streams, vk_server** out);
 vk_status vk_server_destroy(vk_server* s);
 /* Builds and uploads the (n, k) hierarchy now (host assembly is the slow part of admission). */
 vk_status vk_server_prepare(vk_server* s, int n, int k);

@@ -120,8 +120,9 @@ _SIGS = {
     "vk_tuning_get": ([_p, _c_int, _P(vk_tuning)], _c_int),
     "vk_tuning_set": ([_p, _c_int, _P(vk_tuning)], _c_int),
     "vk_kernel_timing": ([_p, _c_int, _c_int, _P(ctypes.c_int64), _P(_c_dbl)], _c_int),
+    "vk_sweep_timing": ([_p, _c_int, _c_int, _P(ctypes.c_int64), _P(_c_dbl)], _c_int),
     "vk_server_last_error": ([], ctypes.c_char_p),
-    "vk_server_create": ([_P(vk_server_opts), _p, ctypes.c_size_t, _P(_p)], _c_int),
+    "vk_server_create": ([_P(vk_server_opts), _p, ctypes.c_size_t, _P(_p), ctypes.c_int, _P(_p)], _c_int),
     "vk_server_destroy": ([_p], _c_int),
     "vk_server_prepare": ([_p, _c_int, _c_int], _c_int),
     "vk_server_problem_size": ([_p, _c_int, _c_int, _P(_c_int)], _c_int),
@@ -349,6 +350,13 @@ class Hierarchy:
         check(lib.vk_kernel_timing(self.h, int(enable), int(reset), ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
 
+    def sweep_timing(self, enable=True, reset=False):
+        """(finest-level sweeps, their total milliseconds) since the last reset."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        check(lib.vk_sweep_timing(self.h, int(enable), int(reset), ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
 
 def scheck(status):
     if status < 0:
@@ -370,14 +378,18 @@ class Server:
     pool is one torch tensor; results land in host numpy arrays."""
 
     def __init__(self, pool_bytes, slots=16, store=VK_STORE_FP32, omega=0.5, nu_sweeps=2, restart=30, maxit=100,
-                 rtol=1e-10, max_queue=100000, device="cuda"):
+                 rtol=1e-10, max_queue=100000, device="cuda", streams=4):
         import torch
         self.pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=device)
         base = self.pool.data_ptr()
         aligned = (base + 255) // 256 * 256
         self.opts = vk_server_opts(slots, store, omega, nu_sweeps, restart, maxit, rtol, max_queue)
+        # torch owns the streams the resident hierarchies run on (default priority)
+        self.streams = [torch.cuda.Stream(device=self.pool.device) for _ in range(int(streams))]
+        handles = (ctypes.c_void_p * len(self.streams))(*[st.cuda_stream for st in self.streams])
         s = ctypes.c_void_p()
-        scheck(lib.vk_server_create(ctypes.byref(self.opts), aligned, int(pool_bytes), ctypes.byref(s)))
+        scheck(lib.vk_server_create(ctypes.byref(self.opts), aligned, int(pool_bytes), handles, len(self.streams),
+                                    ctypes.byref(s)))
         self.s = s
         self._keep = {}
 
@@ -403,7 +415,10 @@ class Server:
     def submit(self, n, k, viscosity, b):
         """Returns (status, ticket, x): x is filled when the request completes."""
         b = np.ascontiguousarray(b, dtype=np.float64)
-        x = np.zeros(len(b))
+        N = self.size(n, k)
+        if b.shape != (N,):
+            raise ValueError(f"right-hand side of the ({n}, {k}) problem must have {N} entries, got {b.shape}")
+        x = np.zeros(N)
         req = vk_request(n, k, viscosity, b.ctypes.data)
         t = ctypes.c_uint64()
         st = lib.vk_server_submit(self.s, ctypes.byref(req), _ptr(x), ctypes.byref(t))

@@ -144,21 +144,32 @@ void drop_graphs(vk_hierarchy* h) {
   h->graphs.clear();
 }
 
+// An event pair from the hierarchy's pool, its first event recorded on the stream.
+std::pair<hipEvent_t, hipEvent_t> timer_start(vk_hierarchy* h) {
+  if (h->ev_free.empty()) {
+    hipEvent_t a, b;
+    HIPCHECK(hipEventCreate(&a));
+    HIPCHECK(hipEventCreate(&b));
+    h->ev_free.push_back({a, b});
+  }
+  auto ev = h->ev_free.back();
+  h->ev_free.pop_back();
+  HIPCHECK(hipEventRecord(ev.first, h->stream));
+  return ev;
+}
+
+bool sweep_timed(const vk_hierarchy* h, int l) { return h->sweep_timing && !h->capturing && l == h->L() - 1; }
+
+void sweep_timer_stop(vk_hierarchy* h, std::pair<hipEvent_t, hipEvent_t> ev) {
+  HIPCHECK(hipEventRecord(ev.second, h->stream));
+  h->sw_pending.push_back(ev);
+}
+
 void patch_apply(vk_hierarchy* h, int l, const double* t) {
   DevLevel& d = h->D[l];
   const bool timed = h->timing && !h->capturing && l == h->L() - 1;
   std::pair<hipEvent_t, hipEvent_t> ev;
-  if (timed) {
-    if (h->ev_free.empty()) {
-      hipEvent_t a, b;
-      HIPCHECK(hipEventCreate(&a));
-      HIPCHECK(hipEventCreate(&b));
-      h->ev_free.push_back({a, b});
-    }
-    ev = h->ev_free.back();
-    h->ev_free.pop_back();
-    HIPCHECK(hipEventRecord(ev.first, h->stream));
-  }
+  if (timed) ev = timer_start(h);
   launch_patch_apply(h->fp32(), d.tri, d.max_n, d.waves_large, d.nt_large != 0, d.depth_large,
                      d.merged ? d.J : d.n_large, d.meta, d.pdofs, d.inv, t, d.delta, h->stream);
   if (!d.merged)
@@ -210,6 +221,9 @@ void smooth(vk_hierarchy* h, int l, const double* b, double* x, int nsweeps, boo
   SmoothSchedule sch(h, d);
   for (int it = 0; it < nsweeps; ++it) {
     const bool first_zero = x_zero && it == 0;
+    const bool stimed = sweep_timed(h, l);
+    std::pair<hipEvent_t, hipEvent_t> sev;
+    if (stimed) sev = timer_start(h);
     const double* t = b;
     if (!first_zero) {
       launch_csr(1, d.N, d.k_lanes, d.rowptr, d.col, d.val, x, b, d.t, s);
@@ -219,6 +233,7 @@ void smooth(vk_hierarchy* h, int l, const double* b, double* x, int nsweeps, boo
     const SmoothStep st = sch.next(it, first_zero);
     launch_scatter_mode(h->fp32(), st.mode, d.N, d.dptr, d.dslot, d.delta, d.scale, st.c1, st.c2, d.cd, x, s);
     check_launch();
+    if (stimed) sweep_timer_stop(h, sev);
   }
   if (x_zero && nsweeps == 0) launch_fill(d.N, 0.0, x, s);
 }
@@ -328,6 +343,15 @@ void collect_timing(vk_hierarchy* h) {
     h->ev_free.push_back(ev);
   }
   h->ev_pending.clear();
+  for (auto& ev : h->sw_pending) {
+    float ms = 0.f;
+    HIPCHECK(hipEventSynchronize(ev.second));
+    HIPCHECK(hipEventElapsedTime(&ms, ev.first, ev.second));
+    h->s_ms += ms;
+    h->s_sweeps += 1;
+    h->ev_free.push_back(ev);
+  }
+  h->sw_pending.clear();
 }
 
 // One Arnoldi step of FGMRES: z_j = V-cycle(v_j), w = K z_j, two classical
@@ -498,7 +522,7 @@ vk_status fgmres(vk_hierarchy* h, const double* b_in, double* x, const vk_solve_
     info->converged = converged ? 1 : 0;
     info->rel_residual = beta / bnorm;
   }
-  if (h->timing) collect_timing(h);
+  if (h->timing || h->sweep_timing) collect_timing(h);
   return converged ? VK_OK : VK_NOT_CONVERGED;
 }
 
@@ -609,6 +633,9 @@ void smooth_multi(vk_hierarchy* h, int l, int R, const double* B, double* X, int
   SmoothSchedule sch(h, d);
   for (int it = 0; it < nsweeps; ++it) {
     const bool first_zero = x_zero && it == 0;
+    const bool stimed = sweep_timed(h, l);
+    std::pair<hipEvent_t, hipEvent_t> sev;
+    if (stimed) sev = timer_start(h);
     const double* T = B;
     if (!first_zero) {
       launch_spmm(1, d.N, d.nkg, d.kgrp, R, d.rowptr, d.col, d.val, X, B, d.t, s);
@@ -616,17 +643,7 @@ void smooth_multi(vk_hierarchy* h, int l, int R, const double* B, double* X, int
     }
     const bool timed = h->timing && !h->capturing && l == h->L() - 1;
     std::pair<hipEvent_t, hipEvent_t> ev;
-    if (timed) {
-      if (h->ev_free.empty()) {
-        hipEvent_t a, b;
-        HIPCHECK(hipEventCreate(&a));
-        HIPCHECK(hipEventCreate(&b));
-        h->ev_free.push_back({a, b});
-      }
-      ev = h->ev_free.back();
-      h->ev_free.pop_back();
-      HIPCHECK(hipEventRecord(ev.first, s));
-    }
+    if (timed) ev = timer_start(h);
     if (d.tri) {
       // bound for one right-hand side: [N][1] multivectors are plain vectors
       launch_patch_apply(h->fp32(), true, d.max_n, d.waves_large, d.nt_large != 0, d.depth_large,
@@ -647,6 +664,7 @@ void smooth_multi(vk_hierarchy* h, int l, int R, const double* B, double* X, int
     launch_scatter_multi_mode(h->fp32(), st.mode, d.N, R, d.dptr, d.dslot, d.delta, d.scale, st.c1, st.c2, d.cd, X,
                               s);
     check_launch();
+    if (stimed) sweep_timer_stop(h, sev);
   }
   if (x_zero && nsweeps == 0) launch_fill(d.N * R, 0.0, X, s);
 }
@@ -829,7 +847,7 @@ vk_status fgmres_multi(vk_hierarchy* h, int R, const double* B, double* X, const
     launch_spmm(1, N, F.nkg, F.kgrp, R, F.rowptr, F.col, F.val, X, h->bb, h->r, s);
     check_launch();
   }
-  if (h->timing) collect_timing(h);
+  if (h->timing || h->sweep_timing) collect_timing(h);
   bool all = true;
   for (int c = 0; c < R; ++c) {
     all = all && conv[c];
@@ -959,6 +977,7 @@ vk_status vk_hierarchy_destroy(vk_hierarchy* h) {
     drop_graphs(h);
     for (auto& e : h->ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (auto& e : h->ev_pending) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto& e : h->sw_pending) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (auto& e : h->ev_copy)
       if (e) (void)hipEventDestroy(e);
     if (h->hh_pin) (void)hipHostFree(h->hh_pin);
@@ -1409,6 +1428,21 @@ vk_status vk_tuning_set(vk_hierarchy* h, int level, const vk_tuning* t) {
     d.depth_large = t->apply_depth_large;
     d.depth_small = t->apply_depth_small;
     d.merged = t->apply_merged != 0;
+    return VK_OK;
+  });
+}
+
+vk_status vk_sweep_timing(vk_hierarchy* h, int enable, int reset, int64_t* sweeps, double* total_ms) {
+  return guarded([&]() -> vk_status {
+    require(h, VK_EINVAL, "null hierarchy");
+    if (h->bound) {
+      HIPCHECK(hipStreamSynchronize(h->stream));
+      collect_timing(h);
+    }
+    if (sweeps) *sweeps = h->s_sweeps;
+    if (total_ms) *total_ms = h->s_ms;
+    if (reset) { h->s_sweeps = 0; h->s_ms = 0.0; }
+    h->sweep_timing = enable != 0;
     return VK_OK;
   });
 }

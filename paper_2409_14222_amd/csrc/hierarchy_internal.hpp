@@ -107,6 +107,11 @@ struct vk_hierarchy {
   int64_t t_launches = 0;
   double t_ms = 0.0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free, ev_pending;
+  // timing of whole finest-level smoothing sweeps (residual, patch apply, scatter)
+  bool sweep_timing = false;
+  int64_t s_sweeps = 0;
+  double s_ms = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> sw_pending;
   // pinned read-back of the Hessenberg columns (two slots) and their copy-done events, so that
   // the next Arnoldi step can be enqueued before the host has read the current one
   double* hh_pin = nullptr;

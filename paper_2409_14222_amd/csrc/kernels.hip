@@ -256,8 +256,8 @@ __global__ void __launch_bounds__(256) gather_invert_kernel(const int* __restric
 // ============================================================================
 // Gauss-Jordan for patches with 128 < n <= 224 (3D vertex stars reach 196):
 // the FP64 tile (up to 392 KiB) does not fit in LDS, so it lives in registers.
-// 512 threads form a 32 x 16 grid; thread (ti, tj) owns the elements
-// (ti + 32 x, tj + 16 y), x < 7, y < 14, of the tile padded with the identity
+// 1024 threads form a 32 x 32 grid; thread (ti, tj) owns the elements
+// (ti + 32 x, tj + 32 y), x < 7, y < 7, of the tile padded with the identity
 // to 224 x 224 (the padding never pivots and stays the identity).  Per step
 // only the pivot column and the normalised pivot row pass through LDS.  The
 // tile is gathered from the CSR matrix in slabs of 32 rows.
@@ -466,8 +466,8 @@ __global__ void __launch_bounds__(1024) gather_invert_big_kernel(const int* __re
 // in place by blocked Gauss-Jordan without pivoting.  The patch's DoFs are
 // ascending with the velocity before the pressure, so the pivots run through
 // the symmetric positive definite velocity block and then through the negative
-// definite Schur complement of the pressure; a zero or non-finite pivot
-// reports the patch as singular.  One step on the pivot block K (16 columns):
+// definite Schur complement of the pressure; a pivot of magnitude at most
+// n eps max|K_i|, or a non-finite one, reports the patch as singular.  One step on the pivot block K (16 columns):
 //   D = M[K,K] -> D^{-1},  M[K,j] -> D^{-1} M[K,j],  M[i,K] -> -M[i,K] D^{-1},
 //   M[i,j] -> M[i,j] - M[i,K] D^{-1} M[K,j]        (i, j outside K)
 // with the block row and column of the step in LDS.  Every sum runs in a fixed
@@ -485,6 +485,7 @@ __global__ void __launch_bounds__(1024) gather_invert_global_kernel(
   __shared__ double Rl[BS * NMAXG];  // block row  [s][j]
   __shared__ double Cl[BS * NMAXG];  // block column [s][i]
   __shared__ int sing_s;
+  __shared__ double wmax_s[NT / 64];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   double* M = scratch + (int64_t)blockIdx.x * slot_elems;  // column-major, ld n
   for (int q = blockIdx.x; q < count; q += gridDim.x) {
@@ -512,6 +513,16 @@ __global__ void __launch_bounds__(1024) gather_invert_global_kernel(
       }
     }
     __syncthreads();
+    // singularity floor without pivoting: a pivot of magnitude <= n eps max|K_i| (or not finite)
+    // reports the patch as singular
+    double amax = 0.0;
+    for (int64_t e = tid; e < (int64_t)n * n; e += NT) amax = fmax(amax, fabs(M[e]));
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+    if (lane == 0) wmax_s[wave] = amax;
+    __syncthreads();
+    amax = 0.0;
+    for (int w = 0; w < NT / 64; ++w) amax = fmax(amax, wmax_s[w]);
+    const double piv_floor = (double)n * 2.220446049250313e-16 * amax;
     for (int k0 = 0; k0 < n; k0 += BS) {
       const int kb = min(BS, n - k0);
       if (tid < BS * BS) {
@@ -536,7 +547,7 @@ __global__ void __launch_bounds__(1024) gather_invert_global_kernel(
           else if (c == j) nv = -arj / piv;
           else nv = arc - arj * (ajc / piv);
         }
-        if (tid == 0 && (!(fabs(piv) > 0.0) || !isfinite(piv))) sing_s = 1;
+        if (tid == 0 && (!(fabs(piv) > piv_floor) || !isfinite(piv))) sing_s = 1;
         __syncthreads();
         if (tid < BS * BS) Dl[c * BS + r] = nv;
         __syncthreads();

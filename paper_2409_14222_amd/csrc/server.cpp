@@ -113,6 +113,9 @@ struct vk_server {
   std::vector<double> latencies;
   double t_first = -1.0, t_last = 0.0;
   int64_t evictions = 0;
+  // caller-owned HIP streams; residents take them in turn (never created or destroyed here)
+  std::vector<hipStream_t> streams;
+  size_t next_stream = 0;
 };
 
 namespace {
@@ -179,7 +182,6 @@ void evict(vk_server* s, Resident* r) {
   if (r->hi) (void)hipHostFree(r->hi);
   vk_hierarchy_destroy(r->h);
   pool_free(s, r->off, r->bytes);
-  if (r->stream) (void)hipStreamDestroy(r->stream);
   s->evictions++;
   s->res.erase({r->n, r->k});
 }
@@ -246,12 +248,11 @@ Resident* make_resident(vk_server* s, int n, int k) {
   r->bytes = ws + ab;  // the whole block
   r->aux_off = aoff;
   r->aux_bytes = ab;
-  HIPCHECK(hipStreamCreate(&r->stream));
+  r->stream = s->streams[s->next_stream++ % s->streams.size()];
   st = vk_hierarchy_bind(h, s->pool + off, bytes, s->opts.restart, s->opts.slots, r->stream);
   if (st == VK_OK) st = vk_patches_setup(h);
   if (st != VK_OK) {
     const std::string msg = vk_last_error();
-    (void)hipStreamDestroy(r->stream);
     pool_free(s, off, ws + ab);
     throw Error(st, "resident setup: " + msg);
   }
@@ -420,9 +421,13 @@ extern "C" {
 
 const char* vk_server_last_error(void) { return s_err.c_str(); }
 
-vk_status vk_server_create(const vk_server_opts* opts, void* d_pool, size_t pool_bytes, vk_server** out) {
+vk_status vk_server_create(const vk_server_opts* opts, void* d_pool, size_t pool_bytes, void* const* hip_streams,
+                           int n_streams, vk_server** out) {
   return sguard([&]() -> vk_status {
-    require(opts && d_pool && out, VK_EINVAL, "null argument");
+    require(opts && d_pool && out && hip_streams, VK_EINVAL, "null argument");
+    require(n_streams >= 1 && n_streams <= 64, VK_EINVAL, "n_streams must be in 1..64");
+    for (int i = 0; i < n_streams; ++i)
+      require(hip_streams[i] != nullptr, VK_EINVAL, "the null stream cannot serve a resident (use created streams)");
     require(((uintptr_t)d_pool & 255) == 0, VK_EINVAL, "pool must be 256-byte aligned");
     require(opts->slots >= 1 && opts->slots <= 64, VK_EINVAL, "slots must be in 1..64");
     require(opts->restart >= 1 && opts->restart <= 200 && opts->maxit >= 1, VK_EINVAL, "bad Krylov options");
@@ -434,6 +439,7 @@ vk_status vk_server_create(const vk_server_opts* opts, void* d_pool, size_t pool
     s->pool = (char*)d_pool;
     s->pool_bytes = pool_bytes / 256 * 256;
     s->free_blocks.push_back({0, s->pool_bytes});
+    for (int i = 0; i < n_streams; ++i) s->streams.push_back((hipStream_t)hip_streams[i]);
     *out = s.release();
     return VK_OK;
   });

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 import scipy.linalg as sla
 
+import oracle_history
 import synth
 
 torch = pytest.importorskip("torch")
@@ -96,25 +97,41 @@ def test_full_patch_inverses_sampled(headline):
 
 
 def test_full_finest_sweep(headline):
+    """One finest-level sweep from a random start, measured on the correction x - x0 (1e-13 of its
+    largest entry), and the same for two sweeps."""
     H, OH, OV = headline
     l = 4
     L, S = OH.levels[l], OV.smoothers[l]
     b, x0 = synth.vector(L.N, 1400), synth.vector(L.N, 1401)
     x = _dev(x0)
     H.smooth(l, _dev(b), x, 1)
-    ref = S.sweep(b, x0)
-    tol = 8 * EPS * _cond_bound_sampled(S)
-    err = _rel(_host(x), ref)
-    print(f"[gpu] full size sweep: rel err {err:.2e} (tol {tol:.1e})")
-    assert err <= tol
+    x1 = S.sweep(b, x0)
+    err = _rel(_host(x) - x0, x1 - x0)
+    x = _dev(x0)
+    H.smooth(l, _dev(b), x, 2)
+    err2 = _rel(_host(x) - x0, S.sweep(b, x1) - x0)
+    print(f"[measure] full size sweep: correction rel err {err:.2e}, two sweeps {err2:.2e}")
+    assert err <= 1e-13
+    assert err2 <= 2e-13
+
+
+def test_full_vcycle(headline):
+    """One V(2,2) cycle of the five-level hierarchy from zero: 1e-12 of the largest entry."""
+    H, OH, OV = headline
+    L = OH.finest
+    r = synth.vector(L.N, 1402)
+    e = torch.empty(L.N, dtype=torch.float64, device="cuda")
+    H.vcycle(_dev(r), e, 2, 2)
+    err = _rel(_host(e), OV.apply(r))
+    print(f"[measure] full size V-cycle: rel err {err:.2e}")
+    assert err <= 1e-12
 
 
 def test_full_solve_matches_oracle(headline):
-    """The benchmarked solve.  Solution tolerance: a random relative rhs perturbation of 1e-10 moves
-    the P4-P3 solution by up to 4.4e-6 at 16x16 and 6.4e-6 at 32x32 (sparse direct solves, five
-    draws); allowing the same growth once more to 64x64, two 1e-10-residual solutions may differ by
-    2 x 1.5 x 6.4e-6 = 1.9e-5.  The iteration count, the residual history and the true residual are
-    the tight checks; the printed difference is typically many orders below the bound."""
+    """The benchmarked solve: equal iteration counts, residual histories at every iteration, the
+    true residual with the oracle's matrix, and the solution within 1e-9 of the oracle's (the two
+    runs follow one Krylov trajectory; any two 1e-10-residual solutions could differ by far more,
+    up to 2e-5 for this problem's conditioning, so the bound tests that the trajectories agree)."""
     from oracle import norms, solve
     H, OH, OV = headline
     L = OH.finest
@@ -133,11 +150,8 @@ def test_full_solve_matches_oracle(headline):
     assert res["iterations"] == its
     assert res["rel_residual"] <= 1e-10
     assert np.linalg.norm(ob - L.K @ xg) <= 1.05e-10 * np.linalg.norm(ob)
-    assert diff <= 1.9e-5
-    gh, oh = res["history"][: its + 1], np.array(hist)
-    n10 = min(its, 10) + 1
-    assert np.all(np.abs(gh[:n10] - oh[:n10]) <= 1e-6 * oh[:n10] + 1e-9 * oh[0])
-    assert np.all(np.abs(gh - oh) <= 1e-6 * oh[0])
+    assert diff <= 1e-9
+    oracle_history.check("full size P4-P3", res["history"][: its + 1], hist, L, OV.apply)
     # discretisation errors of the two solutions (library norms vs oracle norms)
     eg, eo = H.solution_errors(xg), norms.errors(L, xo)
     assert abs(eg[0] - eo[0]) <= 1e-6 * eo[0] and abs(eg[1] - eo[1]) <= 1e-6 * eo[1] + 1e-12
@@ -157,11 +171,11 @@ def cube():
 @pytest.mark.parametrize("store", ["fp64", "fp32"])
 def test_full_3d_solve(cube, store):
     """3D P2-P1 on 16^3 cubes (94,286 DoFs, vertex stars up to 196 DoFs), as benchmarked: FP64
-    inverses must reproduce the oracle's iteration count; FP32-stored inverses (factored in FP64)
-    within two iterations, with the FP64 FGMRES still reaching 1e-10 against the oracle's matrix.
-    Solution tolerance for FP64: twice the measured sensitivity bound of the Taylor-Hood cases
-    (1.9e-5, see the 2D test); the FP32 solution differs from the FP64 one by its own 1e-10
-    residual, the same bound."""
+    and FP32-stored inverses (factored in FP64) both reproduce the oracle's iteration count, with
+    the FP64 FGMRES reaching 1e-10 against the oracle's matrix.  Solution: FP64 within 1e-9 of the
+    oracle (one Krylov trajectory); FP32 inverses change the preconditioner at the 1e-7 level, so
+    that solution differs from the oracle's by its own 1e-10 residual times the conditioning,
+    measured at 1.3e-13 and bounded by 1e-8."""
     import paper_2409_14222_amd as vk
     from oracle import solve
     OH, OV = cube
@@ -181,15 +195,11 @@ def test_full_3d_solve(cube, store):
     print(f"[gpu] full size 3D {store}: its gpu {res['iterations']} oracle {its}, "
           f"rel res {res['rel_residual']:.2e}, solution diff {diff:.2e}")
     assert res["converged"] and conv
+    assert res["iterations"] == its
     if store == "fp64":
-        assert res["iterations"] == its
-        n10 = min(its, 10) + 1
-        gh, oh = res["history"][:n10], np.array(hist[:n10])
-        assert np.all(np.abs(gh - oh) <= 1e-6 * oh + 1e-9 * oh[0])
-    else:
-        assert abs(res["iterations"] - its) <= 2
+        oracle_history.check("full size 3D", res["history"], hist, L, OV.apply)
     assert np.linalg.norm(ob - L.K @ xg) <= 1.05e-10 * np.linalg.norm(ob)
-    assert diff <= 1.9e-5
+    assert diff <= (1e-9 if store == "fp64" else 1e-8)
 
 
 def test_full_sv_64_rhs_fp32():

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 import scipy.linalg as sla
 
+import oracle_history
 import synth
 
 torch = pytest.importorskip("torch")
@@ -178,6 +179,9 @@ def bdm8():
 # BDM6 4x4 4.6e-7, BDM8 2x2 9.9e-7
 XTOL = {"p2p1": 1e-8, "p4p3": 1e-8, "p2p1_3d": 1e-8, "p3dp2_sv": 1e-6, "p6p5": 4e-5, "p8p7": 1.5e-4,
         "q2q1": 3e-7, "q4q3": 2e-6, "q7q6": 2.2e-5, "bdm1": 1e-8, "bdm2": 5e-8, "bdm4": 3e-7, "bdm6": 1e-6, "bdm8": 2e-6}
+# the GPU and oracle FP64 solves follow one Krylov trajectory (equal counts, histories checked), so their
+# solutions agree far more closely than two arbitrary 1e-10-residual solutions: 1e-9 for every fixture
+TRAJ_TOL = 1e-9
 ALL = ["p2p1", "p4p3", "p2p1_3d", "p3dp2_sv", "p6p5", "p8p7", "q2q1", "q4q3", "q7q6", "bdm1", "bdm2", "bdm4",
        "bdm6", "bdm8"]
 
@@ -271,6 +275,13 @@ def test_patch_inverses(fx, request):
         assert np.abs(X - Xo).max() <= 8 * n * EPS * c * np.abs(Xo).max()
 
 
+# one sweep and one V-cycle, measured on the correction (the change of x, or e from zero): the
+# survey's parity protocol asks 1e-13 per sweep and 1e-12 per V-cycle, relative to the largest
+# entry of the oracle's correction
+SWEEP_TOL = 1e-13
+VCYCLE_TOL = 1e-12
+
+
 @pytest.mark.parametrize("fx", ALL)
 def test_one_sweep(fx, request):
     H, OH, OV = request.getfixturevalue(fx)
@@ -279,15 +290,16 @@ def test_one_sweep(fx, request):
         b, x0 = synth.vector(L.N, 300 + l), synth.vector(L.N, 400 + l)
         x = _dev(x0)
         H.smooth(l, _dev(b), x, 1)
-        ref = S.sweep(b, x0)
-        tol = 8 * EPS * _cond_bound(S)
-        err = _rel(_host(x), ref)
-        print(f"[gpu] {fx} level {l}: sweep rel err {err:.2e} (tol {tol:.1e})")
-        assert err <= tol
+        d_ref = S.sweep(b, x0) - x0
+        err = _rel(_host(x) - x0, d_ref)
         # two sweeps in a row
         x = _dev(x0)
         H.smooth(l, _dev(b), x, 2)
-        assert _rel(_host(x), S.sweep(b, S.sweep(b, x0))) <= 2 * tol
+        d2_ref = S.sweep(b, S.sweep(b, x0)) - x0
+        err2 = _rel(_host(x) - x0, d2_ref)
+        print(f"[measure] {fx} level {l}: sweep correction rel err {err:.2e}, two sweeps {err2:.2e}")
+        assert err <= SWEEP_TOL
+        assert err2 <= 2 * SWEEP_TOL
 
 
 def test_coarse_solve(p4p3):
@@ -313,10 +325,9 @@ def test_vcycle(fx, request):
     e = torch.empty(L.N, dtype=torch.float64, device="cuda")
     H.vcycle(_dev(r), e, 2, 2)
     ref = OV.apply(r)
-    tol = 32 * EPS * max(_cond_bound(S) for S in OV.smoothers[1:])
     err = _rel(_host(e), ref)
-    print(f"[gpu] {fx}: V-cycle rel err {err:.2e} (tol {tol:.1e})")
-    assert err <= tol
+    print(f"[measure] {fx}: V-cycle rel err {err:.2e}")
+    assert err <= VCYCLE_TOL
     # deterministic: a second application is bitwise identical
     e2 = torch.empty_like(e)
     H.vcycle(_dev(r), e2, 2, 2)
@@ -343,14 +354,13 @@ def test_solve_matches_oracle(fx, request):
     true_res = np.linalg.norm(ob - L.K @ xg) / np.linalg.norm(ob)
     assert res["rel_residual"] <= 1e-10
     assert true_res <= 1.05e-10
-    assert np.linalg.norm(xg - xo) <= XTOL[fx] * np.linalg.norm(xo)
-    # residual histories: the first ten iterations agree tightly; later ones to 1e-6 of the initial
-    # residual, since where FGMRES stagnates (P8-P7 near 1e-7 of it) its residual estimate amplifies
-    # the 1e-14 V-cycle differences by many orders
-    gh, oh = res["history"][: its + 1], np.array(hist)
-    n10 = min(its, 10) + 1
-    assert np.all(np.abs(gh[:n10] - oh[:n10]) <= 1e-6 * oh[:n10] + 1e-9 * oh[0])
-    assert np.all(np.abs(gh - oh) <= 1e-6 * oh[0])
+    diff = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    print(f"[measure] {fx}: solution diff {diff:.2e} (trajectory bound {TRAJ_TOL:.0e}; any two 1e-10 solutions "
+          f"may differ by {XTOL[fx]:.1e})")
+    assert diff <= TRAJ_TOL
+    # residual histories, every iteration: relative 1e-6 plus 1e-9 of the initial residual, or the
+    # oracle's own sensitivity to 1e-13 perturbations where that is larger (P8-P7)
+    oracle_history.check(fx, res["history"][: its + 1], hist, L, OV.apply)
     # bitwise reproducible
     x2 = torch.empty_like(x)
     H.solve(_dev(b), x2)
@@ -372,7 +382,7 @@ def test_mixed_precision_solve(p4p3):
     ob = solve.consistent_rhs(L)
     print(f"[gpu] mixed: its {res['iterations']} (fp64 oracle {its}), diff {np.linalg.norm(xg - xo) / np.linalg.norm(xo):.2e}")
     assert res["converged"]
-    assert abs(res["iterations"] - its) <= 2
+    assert res["iterations"] == its
     assert res["rel_residual"] <= 1e-10
     assert np.linalg.norm(ob - L.K @ xg) <= 1.05e-10 * np.linalg.norm(ob)
     assert np.linalg.norm(xg - xo) <= 1e-8 * np.linalg.norm(xo)
@@ -439,7 +449,7 @@ def test_mixed_precision_solve_3d(p2p1_3d):
     xg = _host(x)
     ob = solve.consistent_rhs(L)
     print(f"[gpu] 3D mixed: its {res['iterations']} (fp64 oracle {its}), diff {np.linalg.norm(xg - xo) / np.linalg.norm(xo):.2e}")
-    assert res["converged"] and abs(res["iterations"] - its) <= 2
+    assert res["converged"] and res["iterations"] == its
     assert res["rel_residual"] <= 1e-10
     assert np.linalg.norm(ob - L.K @ xg) <= 1.05e-10 * np.linalg.norm(ob)
 
@@ -473,7 +483,7 @@ def test_mixed_precision_solve_sv(p3dp2_sv):
     ob = solve.consistent_rhs(L)
     print(f"[gpu] SV mixed: its {res['iterations']} (fp64 oracle {its}), "
           f"diff {np.linalg.norm(xg - xo) / np.linalg.norm(xo):.2e}")
-    assert res["converged"] and abs(res["iterations"] - its) <= 2
+    assert res["converged"] and res["iterations"] == its
     assert np.linalg.norm(ob - L.K @ xg) <= 1.05e-10 * np.linalg.norm(ob)
     assert np.linalg.norm(xg - xo) <= XTOL["p3dp2_sv"] * np.linalg.norm(xo)
 
@@ -508,10 +518,11 @@ def test_bdm_many_rhs_and_fp32_inverses(fx, request):
             rel = np.linalg.norm(Xh[:, c] - (c + 1) * xo) / ((c + 1) * np.linalg.norm(xo))
             print(f"[gpu] {fx} store {store} column {c}: its {res[c]['iterations']} (oracle {its}) diff {rel:.2e}")
             assert res[c]["converged"] and res[c]["rel_residual"] <= 1e-10
-            if store == vk.VK_STORE_FP64:
-                assert res[c]["iterations"] == its
-            else:
-                assert abs(res[c]["iterations"] - its) <= 2
+            # FP32-stored inverses change the preconditioner, by up to eps32 cond(K_i) in a local solve;
+            # the BDM8 patches have cond(K_i) = 1.6e9, so that change is O(1) in some directions and
+            # costs one FGMRES iteration (14 against 13); every other FP32 case keeps the FP64 count
+            allowed = 1 if (store == vk.VK_STORE_FP32 and fx == "bdm8") else 0
+            assert abs(res[c]["iterations"] - its) <= allowed
             assert rel <= XTOL[fx]
         del H
 
@@ -541,7 +552,7 @@ def test_bdm_gpu_velocity_is_divergence_free(fx, request):
 
 def test_bdm_mixed_precision_and_graphs(bdm4):
     """BDM4-dP3 with FP32-stored inverses (factored in FP64): the FP64 FGMRES reaches 1e-10 against
-    the oracle's matrix within two iterations of the FP64 count; and graph replay of the Arnoldi
+    the oracle's matrix in the FP64 oracle's iteration count; and graph replay of the Arnoldi
     steps reproduces the eager FP64 solve bit for bit."""
     import paper_2409_14222_amd as vk
     from oracle import solve
@@ -559,7 +570,7 @@ def test_bdm_mixed_precision_and_graphs(bdm4):
     xg = _host(x)
     print(f"[gpu] bdm4 fp32 inverses: its {res['iterations']} (fp64 oracle {its}), "
           f"diff {np.linalg.norm(xg - xo) / np.linalg.norm(xo):.2e}")
-    assert res["converged"] and abs(res["iterations"] - its) <= 2
+    assert res["converged"] and res["iterations"] == its
     assert np.linalg.norm(ob - L.K @ xg) <= 1.05e-10 * np.linalg.norm(ob)
     assert np.linalg.norm(xg - xo) <= XTOL["bdm4"] * np.linalg.norm(xo)
     xe = torch.empty(L.N, dtype=torch.float64, device="cuda")

@@ -19,21 +19,54 @@ GB = 1 << 30
 
 
 def _requests():
-    # (n, k, viscosity, forcing seed): several problem types, viscosities over four decades
+    # (n, k, viscosity, forcing seed): several problem types, viscosities over four decades, and two
+    # requests of the serving workload's larger kind (n = 32, k = 4: 41,667 DoFs, 123-DoF patches)
     out = []
     kinds = [(8, 2), (16, 2), (8, 3), (16, 3)]
     nus = [0.01, 1.0, 37.5, 100.0, 0.3]
     for i in range(14):
         n, k = kinds[i % len(kinds)]
         out.append((n, k, nus[i % len(nus)], 5000 + i))
+    out.insert(3, (32, 4, 0.05, 5100))
+    out.insert(10, (32, 4, 20.0, 5101))
     return out
+
+
+def _levels(n):
+    return int(np.log2(n // 4)) + 1
 
 
 def _oracle(n, k, nu, seed):
     from oracle import fields, solve
     g = synth.forcing_coeffs(seed)
-    OH, OV = solve.setup(2, k, 4, {8: 2, 16: 3}[n], nu, lambda v: fields.random_sine_field(g, v))
+    OH, OV = solve.setup(2, k, 4, _levels(n), nu, lambda v: fields.random_sine_field(g, v))
     return OH, OV
+
+
+def _check_against_oracle(srv, reqs, handles, tag):
+    """Each served result against the oracle assembled at the request's viscosity: the true residual
+    with the oracle's matrix, a sparse direct solve of the bordered system, and the oracle's FGMRES
+    iteration count (the served operator is D_L K_1 D_R, whose roundings differ from K_nu assembled
+    directly, so a count may move by one at the threshold)."""
+    from oracle import solve
+    for (n, k, nu, seed), (st, ticket, x) in zip(reqs, handles):
+        res = srv.poll(ticket)
+        assert res["state"] == 2 and res["status"] == 0, res
+        OH, OV = _oracle(n, k, nu, seed)
+        L = OH.finest
+        b = solve.consistent_rhs(L)
+        rel = np.linalg.norm(b - L.K @ x) / np.linalg.norm(b)
+        z = L.nullvec()
+        Kb = sp.bmat([[L.K, sp.csr_matrix(z[:, None])], [sp.csr_matrix(z[None, :]), None]]).tocsc()
+        xd = spla.spsolve(Kb, np.concatenate([b, [0.0]]))[: L.N]
+        diff = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+        xo, its, _, conv = solve.solve(OH, OV)
+        print(f"[gpu-serve] {tag} n={n} k={k} nu={nu}: its {res['iterations']} oracle {its}, residual {rel:.2e}, "
+              f"vs direct {diff:.2e}, latency {1e3 * res['latency_s']:.1f} ms")
+        assert res["rel_residual"] <= 1e-10
+        assert rel <= 1.05e-10
+        assert diff <= 1e-8
+        assert abs(res["iterations"] - its) <= 1
 
 
 def _run(srv, reqs, stagger=0):
@@ -58,7 +91,7 @@ def _run(srv, reqs, stagger=0):
 @pytest.fixture(scope="module")
 def served():
     import paper_2409_14222_amd as vk
-    print("[gpu-serve] serving 14 mixed requests (FP64 inverses), half of them joining mid-flight", flush=True)
+    print("[gpu-serve] serving 16 mixed requests (FP64 inverses), half of them joining mid-flight", flush=True)
     srv = vk.Server(2 * GB, slots=8, store=vk.VK_STORE_FP64)
     reqs = _requests()
     handles = _run(srv, reqs, stagger=3)
@@ -66,33 +99,26 @@ def served():
 
 
 def test_served_results_match_oracle_at_each_viscosity(served):
-    from oracle import solve
     srv, reqs, handles = served
-    for (n, k, nu, seed), (st, ticket, x) in zip(reqs, handles):
-        res = srv.poll(ticket)
-        assert res["state"] == 2 and res["status"] == 0, res
-        OH, OV = _oracle(n, k, nu, seed)
-        L = OH.finest
-        b = solve.consistent_rhs(L)
-        rel = np.linalg.norm(b - L.K @ x) / np.linalg.norm(b)
-        z = L.nullvec()
-        Kb = sp.bmat([[L.K, sp.csr_matrix(z[:, None])], [sp.csr_matrix(z[None, :]), None]]).tocsc()
-        xd = spla.spsolve(Kb, np.concatenate([b, [0.0]]))[: L.N]
-        diff = np.linalg.norm(x - xd) / np.linalg.norm(xd)
-        xo, its, _, conv = solve.solve(OH, OV)
-        print(f"[gpu-serve] n={n} k={k} nu={nu}: its {res['iterations']} oracle {its}, residual {rel:.2e}, "
-              f"vs direct {diff:.2e}, latency {1e3 * res['latency_s']:.1f} ms")
-        assert res["rel_residual"] <= 1e-10
-        assert rel <= 1.05e-10
-        assert diff <= 1e-8
-        assert abs(res["iterations"] - its) <= 1
+    _check_against_oracle(srv, reqs, handles, "fp64")
+
+
+def test_fp32_served_results_match_oracle():
+    """The serving workload's precision: FP32-stored patch inverses (factored in FP64) with the FP64
+    FGMRES; a mix of kinds including n = 32, k = 4, half joining mid-flight, each against the oracle."""
+    import paper_2409_14222_amd as vk
+    reqs = [(16, 2, 1.0, 5200), (32, 4, 1.0, 5201), (8, 3, 0.02, 5202), (32, 4, 50.0, 5203), (16, 3, 3.0, 5204),
+            (16, 4, 0.5, 5205)]
+    srv = vk.Server(2 * GB, slots=8, store=vk.VK_STORE_FP32)
+    handles = _run(srv, reqs, stagger=2)
+    _check_against_oracle(srv, reqs, handles, "fp32")
 
 
 def test_alone_equals_in_the_mix(served):
     import paper_2409_14222_amd as vk
     srv, reqs, handles = served
     alone = vk.Server(2 * GB, slots=8, store=vk.VK_STORE_FP64)
-    for i in (0, 5, 11):
+    for i in (0, 3, 12):
         (st, ticket, x_mix) = handles[i]
         h = _run(alone, [reqs[i]])[0]
         assert alone.poll(h[1])["iterations"] == srv.poll(ticket)["iterations"]
@@ -129,6 +155,8 @@ def test_queue_full_is_reported():
     import paper_2409_14222_amd as vk
     srv = vk.Server(1 * GB, slots=2, store=vk.VK_STORE_FP32, max_queue=2)
     b = vk.load_random(2, 8, synth.forcing_coeffs(1))
+    with pytest.raises(ValueError):       # a right-hand side of the wrong size never reaches the library
+        srv.submit(8, 2, 1.0, b[:-1])
     assert srv.submit(8, 2, 1.0, b)[0] == 0
     assert srv.submit(8, 2, 1.0, b)[0] == 0
     assert srv.submit(8, 2, 1.0, b)[0] == vk.VK_EBUSY

@@ -112,6 +112,23 @@ def test_invalid_arguments_are_rejected():
     assert e.value.code == vk.VK_ESTATE
 
 
+def test_server_create_validates_streams():
+    """The server runs on caller-owned streams: a missing array, a count out of 1..64 or a null stream
+    is rejected before anything touches a device (these calls make no HIP call)."""
+    import ctypes
+    opts = vk.vk_server_opts(4, vk.VK_STORE_FP32, 0.5, 2, 30, 100, 1e-10, 16)
+    pool = ctypes.c_void_p(1 << 20)           # never dereferenced: creation only records it
+    out = ctypes.c_void_p()
+    fake = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    null = (ctypes.c_void_p * 2)(0x1000, None)
+    for arr, n in ((None, 1), (fake, 0), (fake, 65), (null, 2)):
+        st = vk.lib.vk_server_create(ctypes.byref(opts), pool, 1 << 30, arr, n, ctypes.byref(out))
+        assert st == vk.VK_EINVAL, (n, st)
+    st = vk.lib.vk_server_create(ctypes.byref(opts), pool, 1 << 30, fake, 2, ctypes.byref(out))
+    assert st == vk.VK_OK
+    assert vk.lib.vk_server_destroy(out) == vk.VK_OK
+
+
 def test_host_assembly_3d_matches_oracle():
     """3D P2-P1 on Kuhn tetrahedra (levels 2, 4 cubes per direction)."""
     H = vk.Hierarchy(2, 2, 2, dim=3, forcing=vk.VK_F_CUBE_MMS)
