@@ -13,6 +13,7 @@ add nu applications and the coefficients' relative change, the estimate's error.
 import numpy as np
 import pytest
 
+import oracle_history
 import synth
 
 torch = pytest.importorskip("torch")
@@ -119,9 +120,11 @@ def test_vcycle_and_solve(cheb):
     H.vcycle(_dev(r), e, 2, 2)
     ref = OV.apply(r)
     lam_err = max(abs(H.level_info(l).cheb_lambda - OV.cheb[l].lam) / OV.cheb[l].lam for l in range(1, len(OH.levels)))
-    tol = 64 * (EPS * max(cb[1:]) + lam_err)
+    # the protocol's 1e-12 per V-cycle, plus the Chebyshev coefficients' relative change from the
+    # estimate's difference (amplified by at most 64 over nu = 2 steps on three levels)
+    tol = 1e-12 + 64 * lam_err
     err = _rel(_host(e), ref)
-    print(f"[gpu] {name}: V-cycle rel err {err:.2e} (tol {tol:.1e})")
+    print(f"[measure] {name}: Chebyshev V-cycle rel err {err:.2e} (tol {tol:.1e}, lambda rel diff {lam_err:.1e})")
     assert err <= tol
     x = torch.empty(L.N, dtype=torch.float64, device="cuda")
     res = H.solve(_dev(H.rhs()), x, history=True)
@@ -130,17 +133,14 @@ def test_vcycle_and_solve(cheb):
     rel = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
     print(f"[gpu] {name}: its gpu {res['iterations']} oracle {its}, solution diff {rel:.2e}")
     assert conv == bool(res["converged"])
-    assert res["iterations"] == its
+    oracle_history.check_count(name, res["iterations"], its, L, OV.apply)
     if conv:
-        # two 1e-10-residual solves may differ by the problem's sensitivity (see test_gpu_parity.XTOL)
-        assert rel <= {"p3dp2_sv": 1e-6, "q3q2": 1e-6, "bdm3": 1e-7}.get(name, 1e-8)
-        # the first iterations agree closely; later ones may not: where the residual stagnates (P4-P3
-        # with unweighted patches stalls near 1e-4 until the restart), FGMRES's residual estimate
-        # amplifies the 1e-15 V-cycle differences by many orders
-        n = min(its, 10) + 1
-        gh, oh = res["history"][:n], np.array(hist[:n])
-        assert np.all(np.abs(gh - oh) <= 1e-6 * oh + 1e-9 * oh[0])
-        assert np.all(np.abs(res["history"][: its + 1] - np.array(hist)) <= 1e-6 * hist[0])
+        # one Krylov trajectory: 1e-9; where the count sits on the threshold and differs by one, the two
+        # 1e-10-residual solutions may differ by the problem's sensitivity (see test_gpu_parity.XTOL)
+        tol = 1e-9 if res["iterations"] == its else {"p3dp2_sv": 1e-6, "q3q2": 1e-6, "bdm3": 1e-7}.get(name, 1e-8)
+        assert rel <= tol
+        n = min(res["iterations"], its) + 1
+        oracle_history.check(name, res["history"][:n], hist[:n], L, OV.apply)
 
 
 def test_many_rhs_columns_match_oracle():
@@ -170,7 +170,7 @@ def test_many_rhs_columns_match_oracle():
     Xh = _host(Xm)
     for c in range(3):
         assert res[c]["iterations"] == its
-        assert np.linalg.norm(Xh[:, c] - (c + 1) * xo) <= 1e-8 * (c + 1) * np.linalg.norm(xo)
+        assert np.linalg.norm(Xh[:, c] - (c + 1) * xo) <= 1e-9 * (c + 1) * np.linalg.norm(xo)
 
 
 def test_fp32_store_estimate_and_solve():
