@@ -275,6 +275,21 @@ vk_status vk_prolong_add(vk_hierarchy* h, int level, const double* d_ec, double*
  *   x += d;  rho = rho'
  * so the error is multiplied by T_nsweeps((theta - W B K) / delta) / T_nsweeps(sigma). */
 vk_status vk_smooth(vk_hierarchy* h, int level, const double* d_b, double* d_x, int nsweeps);
+/* vk_smooth for callers that cannot allocate device memory at call time (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same sweeps and kernels, bitwise the same result, with the
+ * sweep's scratch (residual, patch corrections, Chebyshev direction) taken
+ * from a fixed static device array of 32 MiB held by each GPU the library runs
+ * on, instead of the hierarchy's workspace.  The hierarchy must be bound and
+ * set up (its matrix and inverses stay in the caller's workspace).  No
+ * allocation of any kind; VK_EINVAL (with the sizes in vk_last_error) if the
+ * level needs more than 32 MiB: 8 N + s sum n (+ 8 N for Chebyshev) bytes, each
+ * piece rounded up to 256, s = 8 (FP64) or 4 (FP32 inverses); the P4-P3 64x64
+ * finest level needs 12.4 MB.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one device (two streams, two threads) race and must be
+ * serialised by the caller.  Nothing in the array needs to start at zero; it
+ * keeps the last call's contents.  Kernel and sweep timing are not recorded. */
+vk_status vk_smooth_noalloc(vk_hierarchy* h, int level, const double* d_b, double* d_x, int nsweeps);
 /* Coarsest-level solve of the bordered system [K_0 z; z^T 0][e; mu] = [r; 0]. */
 vk_status vk_coarse_solve(vk_hierarchy* h, const double* d_r, double* d_e);
 /* One V(nu_pre, nu_post) cycle on the finest level with zero initial guess: d_e = B d_r. */

@@ -109,6 +109,7 @@ _SIGS = {
     "vk_restrict": ([_p, _c_int, _p, _p], _c_int),
     "vk_prolong_add": ([_p, _c_int, _p, _p], _c_int),
     "vk_smooth": ([_p, _c_int, _p, _p, _c_int], _c_int),
+    "vk_smooth_noalloc": ([_p, _c_int, _p, _p, _c_int], _c_int),
     "vk_coarse_solve": ([_p, _p, _p], _c_int),
     "vk_vcycle": ([_p, _p, _p, _c_int, _c_int], _c_int),
     "vk_solve": ([_p, _p, _p, _P(vk_solve_opts), _P(vk_solve_info)], _c_int),
@@ -291,6 +292,10 @@ class Hierarchy:
 
     def smooth(self, level, b, x, nsweeps):
         check(lib.vk_smooth(self.h, level, _ptr(b), _ptr(x), nsweeps))
+
+    def smooth_noalloc(self, level, b, x, nsweeps):
+        """vk_smooth with the sweep scratch in the library's fixed per-device array (allocates nothing)."""
+        check(lib.vk_smooth_noalloc(self.h, level, _ptr(b), _ptr(x), nsweeps))
 
     def coarse_solve(self, r, e):
         check(lib.vk_coarse_solve(self.h, _ptr(r), _ptr(e)))

@@ -1012,6 +1012,7 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_r
       carve(h->H, h->fp32(), &tmp, dry, max_restart, max_rhs, cheb_steps(h));
     }
     require(bytes >= dry.off, VK_ENOMEM, "workspace too small");
+    HIPCHECK(hipGetDevice(&h->device));
     h->stream = (hipStream_t)stream;
     h->max_restart = max_restart;
     h->max_rhs = max_rhs;
@@ -1290,6 +1291,52 @@ vk_status vk_smooth(vk_hierarchy* h, int level, const double* b, double* x, int 
     require_ready(h);
     require(b && x && nsweeps >= 0, VK_EINVAL, "bad argument");
     require_level(h, level, 1);
+    smooth(h, level, b, x, nsweeps, false);
+    return VK_OK;
+  });
+}
+
+vk_status vk_smooth_noalloc(vk_hierarchy* h, int level, const double* b, double* x, int nsweeps) {
+  return guarded([&]() -> vk_status {
+    require(h != nullptr, VK_EINVAL, "null hierarchy");
+    require(b && x && nsweeps >= 0, VK_EINVAL, "bad argument");
+    require_level(h, level, 1);
+    // the sweep's scratch: residual t [N], patch corrections [sum n] (stored precision),
+    // Chebyshev direction [N]; each piece 256-byte aligned
+    const LevelHost& L = h->H[level];
+    const size_t es = h->fp32() ? sizeof(float) : sizeof(double);
+    auto up256 = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t t_bytes = up256((size_t)L.N * sizeof(double));
+    const size_t d_bytes = up256(L.pdofs.size() * es);
+    const size_t c_bytes = h->cheb() ? up256((size_t)L.N * sizeof(double)) : 0;
+    require(t_bytes + d_bytes + c_bytes <= kNoAllocScratchBytes, VK_EINVAL,
+            "level " + std::to_string(level) + " needs " + std::to_string(t_bytes + d_bytes + c_bytes) +
+                " bytes of sweep scratch; vk_smooth_noalloc holds at most " + std::to_string(kNoAllocScratchBytes));
+    require_ready(h);
+    char* base = (char*)noalloc_scratch(h->device);
+    DevLevel& d = h->D[level];
+    // point the level's sweep buffers at the fixed scratch for this call (restored on every exit);
+    // no timing events either (creating them would allocate)
+    struct Swap {
+      DevLevel& d;
+      vk_hierarchy* h;
+      double* t;
+      void* delta;
+      double* cd;
+      bool timing, sweep_timing;
+      ~Swap() {
+        d.t = t;
+        d.delta = delta;
+        d.cd = cd;
+        h->timing = timing;
+        h->sweep_timing = sweep_timing;
+      }
+    } guard{d, h, d.t, d.delta, d.cd, h->timing, h->sweep_timing};
+    h->timing = false;
+    h->sweep_timing = false;
+    d.t = (double*)base;
+    d.delta = base + t_bytes;
+    d.cd = h->cheb() ? (double*)(base + t_bytes + d_bytes) : nullptr;
     smooth(h, level, b, x, nsweeps, false);
     return VK_OK;
   });

@@ -27,6 +27,10 @@ constexpr int kClassLimit[kClasses] = {32, 64, 128, 224, 512};
 // column-major (the symmetric tiled storage is limited to 224)
 constexpr int kBigSlots = 256;
 constexpr int kTiledMaxN = 224;
+// the fixed per-device scratch of the allocation-free smoothing call (vk_smooth_noalloc)
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+// its address on `device` (looked up once per device with that device current)
+void* noalloc_scratch(int device);
 
 struct DevLevel {
   int N = 0, nvel = 0, J = 0;
@@ -87,6 +91,7 @@ struct vk_hierarchy {
   std::vector<std::vector<int>> class_lists;  // per level: ids of class 0, then 1, then 2
   bool bound = false, ready = false;
   hipStream_t stream = nullptr;
+  int device = -1;  // current device at bind (where the workspace lives)
   int max_restart = 0;
   int max_rhs = 1;
   int *nvc = nullptr, *mask = nullptr;  // per-column iteration counts / active flags (multi-RHS)

@@ -129,6 +129,17 @@ def test_server_create_validates_streams():
     assert vk.lib.vk_server_destroy(out) == vk.VK_OK
 
 
+def test_noalloc_smoothing_rejects_levels_beyond_its_scratch():
+    """The allocation-free smoothing call holds 32 MiB of sweep scratch per GPU: the P4-P3 128x128
+    finest level (670,211 DoFs, 5.5 M patch slots: 49.6 MB) is refused with VK_EINVAL before any
+    device work; a level that fits gets past the size check to the state check (not bound)."""
+    H = vk.Hierarchy(4, 4, 6)
+    st = vk.lib.vk_smooth_noalloc(H.h, 5, 1 << 20, 1 << 21, 1)
+    assert st == vk.VK_EINVAL
+    assert "needs" in vk.lib.vk_last_error().decode()
+    assert vk.lib.vk_smooth_noalloc(H.h, 4, 1 << 20, 1 << 21, 1) == vk.VK_ESTATE
+
+
 def test_host_assembly_3d_matches_oracle():
     """3D P2-P1 on Kuhn tetrahedra (levels 2, 4 cubes per direction)."""
     H = vk.Hierarchy(2, 2, 2, dim=3, forcing=vk.VK_F_CUBE_MMS)
