@@ -502,14 +502,20 @@ def main():
     sweep_s = sweep_ms / 1e3
 
     # dominant kernel: finest-level additive patch apply (a GEMM over R columns when R > 1).  With
-    # one right-hand side the inverses are read from the symmetric tiled storage (the 8 x 8 tiles
-    # on and below the diagonal), with several from the full column-major storage (sum n^2)
+    # one right-hand side the method needs each symmetric inverse's triangle, sum n (n + 1) / 2
+    # entries (the algorithmic bytes); the tiled storage the kernel reads holds more (whole 8 x 8
+    # diagonal tiles, zero rows below n: inv_elems_tri, reported beside it).  With several
+    # right-hand sides the full column-major inverses are read (sum n^2)
     s = 4 if store == vk.VK_STORE_FP32 else 8
-    inv_bytes = (info.inv_elems_tri if R == 1 else info.sum_n2) * s
-    apply_bytes = inv_bytes + info.sum_n * 4 + info.sum_n * R * (8 + s)
+    tri_entries = (info.sum_n2 + info.sum_n) // 2
+    inv_bytes = (tri_entries if R == 1 else info.sum_n2) * s
+    vec_bytes = info.sum_n * 4 + info.sum_n * R * (8 + s)
+    apply_bytes = inv_bytes + vec_bytes
+    stored_bytes = (info.inv_elems_tri if R == 1 else info.sum_n2) * s + vec_bytes
     apply_flops = 2.0 * info.sum_n2 * R
     avg_s = kms / 1e3 / max(launches, 1)
     src = "patch_apply.hip" if R == 1 else "patch_gemm.hip"
+    traffic = MEASURED_TRAFFIC.get((src, kernel_source_hash(src), args.workload, args.store, R))
     achieved = apply_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
     out = {
         "metric": "Stokes solves/s to 1e-10 rel. residual",
@@ -535,11 +541,13 @@ def main():
         "finest_sweep_us": 1e6 * sweep_s / max(n_sweeps, 1),
         "setup_s": {"host_assembly": t_host, "device_upload_gather_invert": t_dev, "autotune": t_tune},
         "tuning": tuning,
-        "roofline": {"kernel": "patch_apply_kernel (finest level)", "bound": "hbm", "achieved": achieved,
+        "roofline": {"kernel": "patch_apply_tri_kernel (finest level)", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": MEASURED_TRAFFIC.get((src, kernel_source_hash(src), args.workload, args.store, R)),
-                     "algorithmic_bytes_per_launch": apply_bytes, "avg_launch_us": avg_s * 1e6,
-                     "launches": launches},
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": apply_bytes, "stored_bytes_per_launch": stored_bytes,
+                     "stored_over_algorithmic": stored_bytes / apply_bytes,
+                     "traffic_over_algorithmic": traffic / apply_bytes if traffic else None,
+                     "avg_launch_us": avg_s * 1e6, "launches": launches},
     }
     if R > 1:
         peak_tf = 157.3  # FP32 dense matrix-core (and vector) peak of MI355X
