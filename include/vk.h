@@ -328,7 +328,8 @@ typedef struct vk_tuning {
   int k_lanes;           /* lanes per CSR row of K (4, 8, 16, 32, 64) */
   int p_lanes;           /* lanes per row of the prolongation from level-1 */
   int pt_lanes;          /* lanes per row of its transpose (restriction) */
-  int apply_waves_large; /* wavefronts per patch, patches with more than 64 DoFs (1, 2, 4) */
+  int apply_waves_large; /* wavefronts per patch, patches with more than 64 DoFs (1, 2, 4; also 8, 16
+                            on levels with the symmetric tiled storage) */
   int apply_waves_small; /* wavefronts per patch, the others */
   int apply_nontemporal_large; /* 1: stream the large patches' inverses with non-temporal loads */
   int apply_nontemporal_small; /* same for the small patches */
@@ -345,6 +346,13 @@ vk_status vk_autotune(vk_hierarchy* h, int reps);
 vk_status vk_tuning_get(const vk_hierarchy* h, int level, vk_tuning* t);
 /* Pins launch shapes (e.g. a cached autotuner result); VK_EINVAL on unsupported values. */
 vk_status vk_tuning_set(vk_hierarchy* h, int level, const vk_tuning* t);
+/* The autotuner with a tuning cache (a text file at `path`, host): if the file holds shapes for
+ * every level under this hierarchy's key (device architecture and CU count, problem, patch
+ * construction, storage, smoother, weights, max right-hand sides), they are set and *hit = 1;
+ * otherwise vk_autotune runs and its shapes are appended to the file (created if missing),
+ * *hit = 0.  Lines of other keys are kept; a later line of a key overrides an earlier one.
+ * VK_EINVAL if the file cannot be written. */
+vk_status vk_autotune_cached(vk_hierarchy* h, int reps, const char* path, int* hit);
 
 /* Timing of the finest-level patch apply (single vector: the two size-class
  * dispatches; many right-hand sides: the patch GEMM), HIP events around every

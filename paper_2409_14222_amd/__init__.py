@@ -118,6 +118,7 @@ _SIGS = {
     "vk_solve_multi": ([_p, _p, _p, _c_int, _P(vk_solve_opts), _p], _c_int),
     "vk_rhs_random": ([_p, _c_int, _p, _p], _c_int),
     "vk_autotune": ([_p, _c_int], _c_int),
+    "vk_autotune_cached": ([_p, _c_int, ctypes.c_char_p, _P(_c_int)], _c_int),
     "vk_tuning_get": ([_p, _c_int, _P(vk_tuning)], _c_int),
     "vk_tuning_set": ([_p, _c_int, _P(vk_tuning)], _c_int),
     "vk_kernel_timing": ([_p, _c_int, _c_int, _P(ctypes.c_int64), _P(_c_dbl)], _c_int),
@@ -334,8 +335,15 @@ class Hierarchy:
         return status, [{"iterations": i.iterations, "converged": bool(i.converged), "rel_residual": i.rel_residual}
                         for i in infos]
 
-    def autotune(self, reps=5):
-        check(lib.vk_autotune(self.h, reps))
+    def autotune(self, reps=5, cache=None):
+        """Autotune the launch shapes; with `cache` (a file path) reuse the shapes stored there for
+        this hierarchy and device, or store the new ones.  Returns the per-level shapes."""
+        if cache is None:
+            check(lib.vk_autotune(self.h, reps))
+        else:
+            hit = ctypes.c_int()
+            check(lib.vk_autotune_cached(self.h, reps, os.fsencode(cache), ctypes.byref(hit)))
+            self.tuning_cache_hit = bool(hit.value)
         return [self.tuning(l) for l in range(self.n_levels)]
 
     def tuning(self, level):

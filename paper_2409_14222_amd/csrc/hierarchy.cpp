@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -371,8 +372,7 @@ void arnoldi_step(vk_hierarchy* h, int j, const vk_solve_opts& o) {
   if (j + 1 <= kFusedMaxNv1) {
     // CGS2 with each update fused into the following reduction (bitwise the unfused values)
     launch_axpy_multidot(false, N, j + 1, -1.0, h->V, N, h->small, w, h->partial, h->small + (m + 2), s);
-    launch_axpy_multidot(true, N, j + 1, -1.0, h->V, N, h->small + (m + 2), w, h->partial,
-                         h->small + 2 * (m + 2), s);
+    launch_axpy_multidot(true, N, j + 1, -1.0, h->V, N, h->small + (m + 2), w, h->partial, h->small + 2 * (m + 2), s);
   } else {
     launch_multiaxpy(N, j + 1, -1.0, h->V, N, h->small, w, s);
     launch_multidot(N, j + 1, h->V, N, w, h->partial, h->small + (m + 2), s);
@@ -550,7 +550,7 @@ float time_ms(hipStream_t s, int reps, Fn&& fn) {
 void autotune(vk_hierarchy* h, int reps) {
   const hipStream_t s = h->stream;
   const int lanes[5] = {4, 8, 16, 32, 64};
-  const int waves[3] = {1, 2, 4};
+  const int waves[5] = {1, 2, 4, 8, 16};  // 8 and 16 only for the tiled apply
   for (int l = 0; l < h->L(); ++l) {
     DevLevel& d = h->D[l];
     launch_fill(d.N, 1.0, d.b, s);
@@ -580,6 +580,7 @@ void autotune(vk_hierarchy* h, int reps) {
         if (!d.tri && depth != 2) continue;  // the column-major apply has a fixed depth
         for (int nt = 1; nt >= 0; --nt)
           for (int w : waves) {
+            if (!d.tri && w > 4) continue;
             const float t = time_ms(s, reps, [&] {
               launch_patch_apply(h->fp32(), d.tri, part == 0 ? d.max_n : std::min(d.max_n, 64), w, nt != 0, depth,
                                  count, d.meta + first, d.pdofs, d.inv, d.b, d.delta, s);
@@ -606,6 +607,7 @@ void autotune(vk_hierarchy* h, int reps) {
         if (!d.tri && depth != 2) continue;
         for (int nt = 1; nt >= 0; --nt)
           for (int w : waves) {
+            if (!d.tri && w > 4) continue;
             const float t = time_ms(s, reps, [&] {
               launch_patch_apply(h->fp32(), d.tri, d.max_n, w, nt != 0, depth, d.J, d.meta, d.pdofs, d.inv, d.b,
                                  d.delta, s);
@@ -1432,6 +1434,83 @@ vk_status vk_autotune(vk_hierarchy* h, int reps) {
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Key of a hierarchy in the tuning cache: what fixes the shapes the autotuner can pick and the
+// data they run on (problem, patches, storage, right-hand sides) and the device they ran on.
+std::string tuning_key(const vk_hierarchy* h) {
+  hipDeviceProp_t prop{};
+  HIPCHECK(hipGetDeviceProperties(&prop, h->device));
+  std::string arch = prop.gcnArchName;
+  for (char& ch : arch)
+    if (ch == ' ') ch = '_';
+  const vk_problem& p = h->pr.p;
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s|dim%d|fam%d|k%d|n%d|L%d|pen%.17g|con%d|st%d|sm%d|w%d|rhs%d|cu%d", arch.c_str(),
+                p.dim, p.family, p.k, p.n_coarse, p.n_levels, p.penalty, h->opts.construct, h->opts.store,
+                h->opts.smoother, h->opts.weighting, h->max_rhs, prop.multiProcessorCount);
+  return buf;
+}
+
+}  // namespace
+
+extern "C" {
+
+vk_status vk_autotune_cached(vk_hierarchy* h, int reps, const char* path, int* hit) {
+  return guarded([&]() -> vk_status {
+    require_ready(h);
+    require(path && *path, VK_EINVAL, "empty tuning cache path");
+    require(reps >= 1 && reps <= 1000, VK_EINVAL, "reps out of range");
+    const std::string key = tuning_key(h);
+    const int L = h->L();
+    std::vector<vk_tuning> found(L);
+    std::vector<char> have(L, 0);
+    if (FILE* f = std::fopen(path, "r")) {
+      char line[1024];
+      while (std::fgets(line, sizeof line, f)) {
+        char k[512];
+        int lv = -1;
+        vk_tuning t{};
+        const int nread = std::sscanf(line, "%511s %d %d %d %d %d %d %d %d %d %d %d", k, &lv, &t.k_lanes, &t.p_lanes,
+                                      &t.pt_lanes, &t.apply_waves_large, &t.apply_waves_small,
+                                      &t.apply_nontemporal_large, &t.apply_nontemporal_small, &t.apply_depth_large,
+                                      &t.apply_depth_small, &t.apply_merged);
+        if (nread == 12 && key == k && lv >= 0 && lv < L) {  // later lines of a key replace earlier ones
+          found[lv] = t;
+          have[lv] = 1;
+        }
+      }
+      std::fclose(f);
+    }
+    bool all = true;
+    for (int l = 0; l < L; ++l) all = all && have[l];
+    if (all) {
+      for (int l = 0; l < L; ++l) {
+        const vk_status st = vk_tuning_set(h, l, &found[l]);
+        if (st != VK_OK) { all = false; break; }  // an entry this build does not accept: tune afresh
+      }
+    }
+    if (hit) *hit = all ? 1 : 0;
+    if (all) return VK_OK;
+    drop_graphs(h);
+    autotune(h, reps);
+    FILE* f = std::fopen(path, "a");
+    require(f != nullptr, VK_EINVAL, std::string("cannot append to the tuning cache ") + path);
+    for (int l = 0; l < L; ++l) {
+      vk_tuning t{};
+      (void)vk_tuning_get(h, l, &t);
+      std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d\n", key.c_str(), l, t.k_lanes, t.p_lanes, t.pt_lanes,
+                   t.apply_waves_large, t.apply_waves_small, t.apply_nontemporal_large, t.apply_nontemporal_small,
+                   t.apply_depth_large, t.apply_depth_small, t.apply_merged);
+    }
+    const bool ok = std::fclose(f) == 0;
+    require(ok, VK_EINVAL, std::string("cannot write the tuning cache ") + path);
+    return VK_OK;
+  });
+}
+
 vk_status vk_tuning_get(const vk_hierarchy* h, int level, vk_tuning* t) {
   return guarded([&]() -> vk_status {
     require(h && t, VK_EINVAL, "null argument");
@@ -1458,9 +1537,11 @@ vk_status vk_tuning_set(vk_hierarchy* h, int level, const vk_tuning* t) {
     require(h->bound, VK_ESTATE, "hierarchy is not bound");
     require_level(h, level, 0);
     auto okl = [](int v) { return v == 4 || v == 8 || v == 16 || v == 32 || v == 64; };
-    auto okw = [](int v) { return v == 1 || v == 2 || v == 4; };
+    const bool tiled = level > 0 && h->D[level].tri;
+    auto okw = [tiled](int v) { return v == 1 || v == 2 || v == 4 || (tiled && (v == 8 || v == 16)); };
     require(okl(t->k_lanes) && okl(t->p_lanes) && okl(t->pt_lanes), VK_EINVAL, "lanes must be 4, 8, 16, 32 or 64");
-    require(okw(t->apply_waves_large) && okw(t->apply_waves_small), VK_EINVAL, "waves must be 1, 2 or 4");
+    require(okw(t->apply_waves_large) && okw(t->apply_waves_small), VK_EINVAL,
+            "waves must be 1, 2 or 4 (also 8 or 16 on levels with the tiled inverse storage)");
     auto okd = [](int v) { return v == 2 || v == 4; };
     require(okd(t->apply_depth_large) && okd(t->apply_depth_small), VK_EINVAL, "depth must be 2 or 4");
     drop_graphs(h);

@@ -174,37 +174,59 @@ __global__ void __launch_bounds__(256) scatter_multi_kernel(int N, int R, int Rp
   scatter_store<MODE>(scale[d] * s, c1, c2, X, DV, (int64_t)d * R + c);
 }
 
-// R > 32: one DoF per wave, made wave-uniform so that the slot list comes by scalar loads; the
-// slot rows of delta are read 8 at a time (the last batch padded with its final slot times zero;
-// delta is finite), summed in the same ascending order.
+// R > 32: four DoFs per wave, made wave-uniform so that the slot lists come by scalar loads; the
+// first 8 slot rows of delta of all four DoFs are loaded together (32 loads in flight), further
+// ones 8 at a time (a batch padded with its final slot times zero; delta is finite), each DoF
+// summed in ascending slot order.
 template <typename TD, int MODE>
 __global__ void __launch_bounds__(256) scatter_wave_kernel(int N, int R, const int* __restrict__ dptr,
                                                            const int* __restrict__ dslot,
                                                            const TD* __restrict__ delta,
                                                            const double* __restrict__ scale, double c1, double c2,
                                                            double* __restrict__ DV, double* __restrict__ X) {
-  const int d = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (d >= N) return;
+  constexpr int DPW = 4;  // DoFs per wave: the first 8 slot rows of all of them are in flight together
+  const int d0 = __builtin_amdgcn_readfirstlane((blockIdx.x * 4 + (threadIdx.x >> 6)) * DPW);
+  if (d0 >= N) return;
   const int c = threadIdx.x & 63;
   const int cl = c < R ? c : R - 1;
-  const int q0 = __builtin_amdgcn_readfirstlane(dptr[d]), q1 = __builtin_amdgcn_readfirstlane(dptr[d + 1]);
-  double s = 0.0;
-  for (int q = q0; q < q1; q += 8) {
-    double v[8];
+  int q0[DPW], q1[DPW];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = (double)delta[(int64_t)dslot[min(q + u, q1 - 1)] * R + cl];
+  for (int j = 0; j < DPW; ++j) {
+    const int d = min(d0 + j, N - 1);
+    q0[j] = __builtin_amdgcn_readfirstlane(dptr[d]);
+    q1[j] = __builtin_amdgcn_readfirstlane(dptr[d + 1]);
+  }
+  double v[DPW][8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s += v[u] * (q + u < q1 ? 1.0 : 0.0);
+  for (int j = 0; j < DPW; ++j)
+#pragma unroll
+    for (int u = 0; u < 8; ++u)  // a DoF without slots (none in the patch constructions here) reads slot 0, masked
+      v[j][u] = (double)delta[(int64_t)dslot[q1[j] > q0[j] ? min(q0[j] + u, q1[j] - 1) : 0] * R + cl];
+  double s[DPW];
+#pragma unroll
+  for (int j = 0; j < DPW; ++j) {
+    s[j] = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[j] += v[j][u] * (q0[j] + u < q1[j] ? 1.0 : 0.0);
+    for (int q = q0[j] + 8; q < q1[j]; q += 8) {  // DoFs in more than 8 patches
+      double w[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) w[u] = (double)delta[(int64_t)dslot[min(q + u, q1[j] - 1)] * R + cl];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[j] += w[u] * (q + u < q1[j] ? 1.0 : 0.0);
+    }
   }
   if (c >= R) return;
-  scatter_store<MODE>(scale[d] * s, c1, c2, X, DV, (int64_t)d * R + c);
+#pragma unroll
+  for (int j = 0; j < DPW; ++j)
+    if (d0 + j < N) scatter_store<MODE>(scale[d0 + j] * s[j], c1, c2, X, DV, (int64_t)(d0 + j) * R + c);
 }
 
 template <typename TD, int MODE>
 void scatter_multi_launch(int N, int R, const int* dptr, const int* dslot, const void* delta, const double* scale,
                           double c1, double c2, double* DV, double* X, hipStream_t s) {
   if (R > 32) {
-    const int grid = (N + 3) / 4;
+    const int grid = (N + 15) / 16;  // 4 waves of 4 DoFs
     if (grid == 0) return;
     scatter_wave_kernel<TD, MODE><<<grid, 256, 0, s>>>(N, R, dptr, dslot, (const TD*)delta, scale, c1, c2, DV, X);
     return;

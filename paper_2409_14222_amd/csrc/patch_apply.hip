@@ -276,6 +276,9 @@ static void apply_tri_waves(int waves, int count, size_t lds, const int4* meta, 
   switch (waves) {
     case 1: patch_apply_tri_kernel<TS, 1, NT, U><<<count, 64, lds, s>>>(meta, pdofs, inv, t, delta); break;
     case 2: patch_apply_tri_kernel<TS, 2, NT, U><<<count, 128, lds, s>>>(meta, pdofs, inv, t, delta); break;
+    // 8 and 16 waves: fewer tile steps per patch, for latency-bound small levels
+    case 8: patch_apply_tri_kernel<TS, 8, NT, U><<<count, 512, lds, s>>>(meta, pdofs, inv, t, delta); break;
+    case 16: patch_apply_tri_kernel<TS, 16, NT, U><<<count, 1024, lds, s>>>(meta, pdofs, inv, t, delta); break;
     default: patch_apply_tri_kernel<TS, 4, NT, U><<<count, 256, lds, s>>>(meta, pdofs, inv, t, delta); break;
   }
 }

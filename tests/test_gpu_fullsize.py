@@ -226,7 +226,7 @@ def test_full_sv_64_rhs_fp32():
     Xh = _host(X)
     rp, col, val = H.csr(4)
     K = sp.csr_matrix((val, col, rp), shape=(N, N))
-    worst = 0.0
+    worst = worst_allow = 0.0
     row_terms = 2 * np.sqrt(np.diff(rp).max())
     for c in range(R):
         assert infos[c]["converged"]
@@ -234,9 +234,10 @@ def test_full_sv_64_rhs_fp32():
         worst = max(worst, rel)
         # the CPU product carries its own rounding, about sqrt(nnz_i) eps (|K| |x|)_i per row
         floor = EPS * np.linalg.norm(abs(K) @ np.abs(Xh[:, c])) / np.linalg.norm(B[:, c])
+        worst_allow = max(worst_allow, row_terms * floor)
         assert rel <= 1.05e-10 + row_terms * floor
-    print(f"[gpu] full size SV 64 RHS: iterations {np.mean([i['iterations'] for i in infos]):.1f}, "
-          f"worst true residual {worst:.2e}")
+    print(f"[measure] full size SV 64 RHS: iterations {np.mean([i['iterations'] for i in infos]):.1f}, "
+          f"worst true residual {worst:.2e}, largest CPU-rounding allowance {worst_allow:.2e}")
     for c in (0, 37, 63):
         x1 = torch.empty((N, 1), dtype=torch.float64, device="cuda")
         _, i1 = H.solve_multi(_dev(B[:, c:c + 1]), x1, 1)

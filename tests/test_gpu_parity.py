@@ -397,10 +397,13 @@ def test_launch_shapes_do_not_change_results(fx, request):
     saved = [H.tuning(l) for l in range(len(OH.levels))]
     ref = torch.empty_like(r)
     H.vcycle(r, ref, 2, 2)
-    for lanes, waves, depth, merged in ((4, 1, 2, 0), (8, 2, 4, 1), (16, 4, 2, 0), (64, 1, 4, 1), (32, 4, 4, 1)):
+    for lanes, waves, depth, merged in ((4, 1, 2, 0), (8, 2, 4, 1), (16, 4, 2, 0), (64, 1, 4, 1), (32, 4, 4, 1),
+                                        (16, 8, 2, 1), (8, 16, 4, 0)):
         for l in range(len(OH.levels)):
-            H.set_tuning(l, k_lanes=lanes, p_lanes=lanes, pt_lanes=lanes, apply_waves_large=waves,
-                         apply_waves_small=waves, apply_depth_large=depth, apply_depth_small=depth,
+            # 8 and 16 waves exist for the tiled storage only (patches of at most 224 DoFs, one RHS)
+            w = waves if (waves <= 4 or (l > 0 and H.level_info(l).max_n <= 224)) else 4
+            H.set_tuning(l, k_lanes=lanes, p_lanes=lanes, pt_lanes=lanes, apply_waves_large=w,
+                         apply_waves_small=w, apply_depth_large=depth, apply_depth_small=depth,
                          apply_merged=merged)
         e = torch.empty_like(r)
         H.vcycle(r, e, 2, 2)

@@ -140,6 +140,15 @@ def test_noalloc_smoothing_rejects_levels_beyond_its_scratch():
     assert vk.lib.vk_smooth_noalloc(H.h, 4, 1 << 20, 1 << 21, 1) == vk.VK_ESTATE
 
 
+def test_tuning_cache_needs_a_set_up_hierarchy():
+    """vk_autotune_cached times kernels: before bind/setup it is a state error, whatever the path."""
+    import ctypes
+    H = vk.Hierarchy(2, 2, 2)
+    hit = ctypes.c_int(7)
+    assert vk.lib.vk_autotune_cached(H.h, 2, b"/nonexistent/dir/cache.txt", ctypes.byref(hit)) == vk.VK_ESTATE
+    assert hit.value == 7
+
+
 def test_host_assembly_3d_matches_oracle():
     """3D P2-P1 on Kuhn tetrahedra (levels 2, 4 cubes per direction)."""
     H = vk.Hierarchy(2, 2, 2, dim=3, forcing=vk.VK_F_CUBE_MMS)
