@@ -49,8 +49,8 @@ HBM_PEAK_GBS = 8000.0
 # Sources: profiles/patch_apply_p4p3_64_fp64.md, profiles/many_rhs_sv_p3dp2_64.md,
 # profiles/patch_apply_bdm4_80_fp64.md
 MEASURED_TRAFFIC = {
-    ("patch_apply.hip", "6d321e57784babdb", "p4p3-64", "fp64", 1): 527.6e6,
-    ("patch_apply.hip", "6d321e57784babdb", "bdm4-80", "fp64", 1): 813.9e6,
+    ("patch_apply.hip", "74e54f84d315c303", "p4p3-64", "fp64", 1): 488.1e6,
+    ("patch_apply.hip", "74e54f84d315c303", "bdm4-80", "fp64", 1): 764.8e6,
     ("patch_gemm.hip", "55e68640323c960e", "sv-p3dp2-64", "fp32", 64): 555.2e6,
 }
 

@@ -151,7 +151,9 @@ typedef struct vk_level_info {
   int64_t p_nnz;   /* nonzeros of the prolongation from level-1 (0 on level 0) */
   int64_t inv_elems_full; /* stored elements of the patch inverses, column-major (bound for > 1 RHS) */
   int64_t inv_elems_tri;  /* stored elements in the symmetric tiled storage (bound for 1 RHS): the
-                             8 x 8 tiles on and below the diagonal, zero-padded */
+                             8 x 8 tiles on and below the diagonal, zero-padded; the tiles of the
+                             last block row keep only the 16-byte row chunks (2 doubles / 4 floats)
+                             that hold rows below n */
   double cheb_lambda;     /* VK_SMOOTH_CHEBYSHEV: the eigenvalue estimate of W B K after
                              vk_patches_setup (0 otherwise, and on level 0) */
   int cheb_steps;         /* Arnoldi steps taken (fewer than est_steps on an exact breakdown) */

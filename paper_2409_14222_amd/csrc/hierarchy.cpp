@@ -550,7 +550,13 @@ float time_ms(hipStream_t s, int reps, Fn&& fn) {
 void autotune(vk_hierarchy* h, int reps) {
   const hipStream_t s = h->stream;
   const int lanes[5] = {4, 8, 16, 32, 64};
-  const int waves[5] = {1, 2, 4, 8, 16};  // 8 and 16 only for the tiled apply
+  const int waves[5] = {1, 2, 4, 8, 16};
+  // 8 and 16 waves per patch: tiled apply only, and only tried on levels of few patches (they
+  // shorten the tile loop where the launch is latency-bound; a full chip gains nothing from them).
+  // 16 waves at depth 4 exceed the 64 VGPRs a lane has at 1024 threads and spill: not tried.
+  auto wide_ok = [&](const DevLevel& d, int w, int depth, int count) {
+    return w <= 4 || (d.tri && count <= kWideApplyMaxPatches && !(w == 16 && depth == 4));
+  };
   for (int l = 0; l < h->L(); ++l) {
     DevLevel& d = h->D[l];
     launch_fill(d.N, 1.0, d.b, s);
@@ -580,7 +586,7 @@ void autotune(vk_hierarchy* h, int reps) {
         if (!d.tri && depth != 2) continue;  // the column-major apply has a fixed depth
         for (int nt = 1; nt >= 0; --nt)
           for (int w : waves) {
-            if (!d.tri && w > 4) continue;
+            if (!wide_ok(d, w, depth, count)) continue;
             const float t = time_ms(s, reps, [&] {
               launch_patch_apply(h->fp32(), d.tri, part == 0 ? d.max_n : std::min(d.max_n, 64), w, nt != 0, depth,
                                  count, d.meta + first, d.pdofs, d.inv, d.b, d.delta, s);
@@ -607,7 +613,7 @@ void autotune(vk_hierarchy* h, int reps) {
         if (!d.tri && depth != 2) continue;
         for (int nt = 1; nt >= 0; --nt)
           for (int w : waves) {
-            if (!d.tri && w > 4) continue;
+            if (!wide_ok(d, w, depth, d.J)) continue;
             const float t = time_ms(s, reps, [&] {
               launch_patch_apply(h->fp32(), d.tri, d.max_n, w, nt != 0, depth, d.J, d.meta, d.pdofs, d.inv, d.b,
                                  d.delta, s);

@@ -27,6 +27,8 @@ constexpr int kClassLimit[kClasses] = {32, 64, 128, 224, 512};
 // column-major (the symmetric tiled storage is limited to 224)
 constexpr int kBigSlots = 256;
 constexpr int kTiledMaxN = 224;
+// the autotuner tries 8 and 16 waves per patch only on launches of at most this many patches
+constexpr int kWideApplyMaxPatches = 4096;
 // the fixed per-device scratch of the allocation-free smoothing call (vk_smooth_noalloc)
 constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
 // its address on `device` (looked up once per device with that device current)

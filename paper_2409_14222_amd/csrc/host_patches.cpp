@@ -245,9 +245,11 @@ void finalize_patches(LevelHost& L, std::vector<std::vector<int>>& patches, doub
   off = 0;
   for (int t = 0; t < J; ++t) {
     const int p = L.order[t];
-    const int nb = (L.pptr[p + 1] - L.pptr[p] + 7) / 8;
+    const int nn = L.pptr[p + 1] - L.pptr[p];
+    const int nb = (nn + 7) / 8, nvr = (nn - 8 * (nb - 1) + rpl - 1) / rpl;
     L.inv_off_tri[p] = off;
-    off += (int64_t)nb * (nb + 1) / 2 * 64;
+    // full 8 x 8 tiles above the last block row, then its tiles cut to nvr chunks of rpl rows
+    off += (int64_t)(nb - 1) * nb / 2 * 64 + (int64_t)nb * 8 * rpl * nvr;
   }
   L.inv_elems_tri = off;
 }

@@ -138,12 +138,18 @@ __device__ inline void gather_tile(int n, const int* __restrict__ Ii, const int*
 // element (row k, column c) at ((k / E) * 8 + c) * E + k % E, E = 16 / sizeof
 // (2 doubles or 4 floats): lane c of a tile loads its column in 16-byte
 // pieces while one load instruction across 8 lanes reads 128 contiguous bytes.
-// Padding rows and columns (beyond n) hold zeros.
+// The tiles of the last block row keep only the chunks (E rows) that hold
+// rows below n: nvr = ceil(rem / E) chunks, rem = n - 8 (nb - 1), 8 E nvr
+// elements each.  Padding rows and columns (beyond n) of stored chunks hold zeros.
 template <typename TS>
-__device__ __forceinline__ int64_t tri_pos(int i, int j) {
+__device__ __forceinline__ int64_t tri_pos(int i, int j, int n) {
   constexpr int E = 16 / sizeof(TS);
   const int I = i >> 3, J = j >> 3, k = i & 7, c = j & 7;
-  return ((int64_t)(I * (I + 1) / 2 + J) << 6) + ((k / E) * 8 + c) * E + k % E;
+  const int nb = (n + 7) >> 3, nvr = (n - 8 * (nb - 1) + E - 1) / E;
+  const int64_t inner = ((k / E) * 8 + c) * E + k % E;
+  if (I < nb - 1) return ((int64_t)(I * (I + 1) / 2 + J) << 6) + inner;
+  if (k / E >= nvr) return -1;
+  return ((int64_t)((nb - 1) * nb / 2) << 6) + (int64_t)J * 8 * E * nvr + inner;
 }
 
 template <int NMAX, typename TS>
@@ -241,7 +247,10 @@ __global__ void __launch_bounds__(256) gather_invert_kernel(const int* __restric
     const int m = (n + 7) & ~7;
     for (int e = tid; e < m * m; e += 256) {
       const int jj = e / m, ii = e - jj * m;
-      if ((ii >> 3) >= (jj >> 3)) out[tri_pos<TS>(ii, jj)] = (ii < n && jj < n) ? (TS)T[jj * n + ii] : (TS)0;
+      if ((ii >> 3) >= (jj >> 3)) {
+        const int64_t q = tri_pos<TS>(ii, jj, n);
+        if (q >= 0) out[q] = (ii < n && jj < n) ? (TS)T[jj * n + ii] : (TS)0;
+      }
     }
     return;
   }
@@ -452,7 +461,7 @@ __global__ void __launch_bounds__(1024) gather_invert_big_kernel(const int* __re
       const int i = ti + TX * x;
       if (tri) {
         // padding of the stored tiles was zeroed before the launch
-        if (i < n && (i >> 3) >= (j >> 3)) out[tri_pos<TS>(i, j)] = (TS)a[x][y];
+        if (i < n && (i >> 3) >= (j >> 3)) out[tri_pos<TS>(i, j, n)] = (TS)a[x][y];
       } else if (i < ld) {
         out[(int64_t)j * ld + i] = (TS)a[x][y];
       }
@@ -611,7 +620,7 @@ __global__ void __launch_bounds__(1024) gather_invert_global_kernel(
       for (int i = lane; i < n; i += 64) {
         const double v = M[(int64_t)j * n + i];
         if (tri) {
-          if ((i >> 3) >= (j >> 3)) out[tri_pos<TS>(i, j)] = (TS)v;
+          if ((i >> 3) >= (j >> 3)) out[tri_pos<TS>(i, j, n)] = (TS)v;
         } else {
           out[(int64_t)j * ld + i] = (TS)v;
         }
@@ -718,7 +727,7 @@ __global__ void copy_inverse_kernel(int n, const TS* __restrict__ inv, int64_t o
   const int ld = (n + RPL - 1) / RPL * RPL;
   for (int e = blockIdx.x * 256 + threadIdx.x; e < n * n; e += gridDim.x * 256) {
     const int j = e / n, i = e - j * n;
-    if (tri) out[e] = (double)inv[off + ((i >> 3) >= (j >> 3) ? tri_pos<TS>(i, j) : tri_pos<TS>(j, i))];
+    if (tri) out[e] = (double)inv[off + ((i >> 3) >= (j >> 3) ? tri_pos<TS>(i, j, n) : tri_pos<TS>(j, i, n))];
     else out[e] = (double)inv[off + (int64_t)j * ld + i];
   }
 }

@@ -189,6 +189,8 @@ __global__ void __launch_bounds__(64 * W) patch_apply_tri_kernel(const int4* __r
   if (n > 224 || n <= 0) return;  // the launch sizes LDS for every n of the launch; never taken
   const int nb = (n + 7) >> 3;
   const int T = nb * (nb + 1) / 2;
+  const int T0 = (nb - 1) * nb / 2;               // first tile of the last block row
+  const int nvr = (n - 8 * (nb - 1) + E - 1) / E;  // chunks its tiles keep
   TS* xs = (TS*)smem;   // 8 nb gathered residual entries (zero padding)
   TS* Q = xs + 8 * nb;  // nb x nb x 8 partial vectors
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -199,9 +201,11 @@ __global__ void __launch_bounds__(64 * W) patch_apply_tri_kernel(const int4* __r
   V a[U][NV];
   auto load_step = [&](int s, V* dst) {
     const int tt = min(t0 + s * 8 * W, T - 1);
-    const TS* tp = A + ((int64_t)tt << 6) + c * E;
+    const bool lastrow = tt >= T0;
+    const int64_t tile = lastrow ? ((int64_t)T0 << 6) + (int64_t)(tt - T0) * (8 * E * nvr) : ((int64_t)tt << 6);
+    const TS* tp = A + tile + c * E;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) dst[v] = load16<TS, NT>(tp + v * 8 * E);
+    for (int v = 0; v < NV; ++v) dst[v] = (!lastrow || v < nvr) ? load16<TS, NT>(tp + v * 8 * E) : V{};
   };
 #pragma unroll
   for (int u = 0; u < U; ++u)

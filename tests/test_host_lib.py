@@ -255,7 +255,8 @@ def test_sv_invalid_combinations_are_rejected():
 
 def test_symmetric_tiled_storage_size():
     """The stored inverse of a patch of n DoFs in the tiled layout is the nb (nb + 1) / 2 tiles of
-    8 x 8 on and below the diagonal, nb = ceil(n / 8); the column-major layout rounds n up to 2."""
+    8 x 8 on and below the diagonal, nb = ceil(n / 8), the nb tiles of the last block row cut to
+    the 2-double row chunks below n; the column-major layout rounds n up to 2."""
     for H, levels in ((vk.Hierarchy(4, 2, 3), (1, 2)), (vk.Hierarchy(3, 2, 2, family=vk.VK_SV), (1,)),
                       (vk.Hierarchy(2, 2, 2, dim=3, forcing=vk.VK_F_CUBE_MMS), (1,))):
         for l in levels:
@@ -263,7 +264,8 @@ def test_symmetric_tiled_storage_size():
             n = np.diff(ptr).astype(np.int64)
             nb = (n + 7) // 8
             inf = H.level_info(l)
-            assert inf.inv_elems_tri == int((nb * (nb + 1) // 2 * 64).sum())
+            nvr = (n - 8 * (nb - 1) + 1) // 2  # 2-double chunks of the last block row's n - 8 (nb - 1) rows
+            assert inf.inv_elems_tri == int(((nb - 1) * nb // 2 * 64 + nb * 8 * 2 * nvr).sum())
             assert inf.inv_elems_tri < inf.sum_n2 or n.max() <= 8
 
 
