@@ -106,6 +106,7 @@ _SIGS = {
     "vk_patch_gather": ([_p, _c_int, _c_int, _c_int, _p], _c_int),
     "vk_patch_inverse": ([_p, _c_int, _c_int, _p], _c_int),
     "vk_spmv": ([_p, _c_int, _p, _p], _c_int),
+    "vk_spmv_multi": ([_p, _c_int, _p, _p, _c_int], _c_int),
     "vk_restrict": ([_p, _c_int, _p, _p], _c_int),
     "vk_prolong_add": ([_p, _c_int, _p, _p], _c_int),
     "vk_smooth": ([_p, _c_int, _p, _p, _c_int], _c_int),
@@ -284,6 +285,9 @@ class Hierarchy:
 
     def spmv(self, level, x, y):
         check(lib.vk_spmv(self.h, level, _ptr(x), _ptr(y)))
+
+    def spmv_multi(self, level, X, Y, nrhs):
+        check(lib.vk_spmv_multi(self.h, level, _ptr(X), _ptr(Y), nrhs))
 
     def restrict(self, level, rf, rc):
         check(lib.vk_restrict(self.h, level, _ptr(rf), _ptr(rc)))

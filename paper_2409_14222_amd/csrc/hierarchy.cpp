@@ -26,6 +26,15 @@ namespace {
 
 thread_local std::string g_err;
 
+// K's union groups of a level with patches, runs taken in patch order (built once)
+const vk::UnionGroups& k_unions(const vk::LevelHost& lh) {
+  if (!lh.kunion_built) {
+    lh.kunion = vk::union_groups(lh.K, lh.kgrp, vk::runs_in_patch_order(lh.kgrp, lh.pptr, lh.pdofs));
+    lh.kunion_built = true;
+  }
+  return lh.kunion;
+}
+
 // Lays out every device array of the hierarchy `Hs` in the carver; pointers go
 // to `h` (a scratch object when only sizing).
 // The FGMRES basis also holds the Arnoldi vectors of the Chebyshev estimate
@@ -55,6 +64,16 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     if (l == 0) {
       d.M = cv.take<double>((size_t)lh.N * lh.N);
       continue;
+    }
+    if (R > 32) {
+      const UnionGroups& ug = k_unions(lh);
+      d.nug = ug.ngroups();
+      d.ug_ptr = cv.take<int>(ug.gptr.size());
+      d.ug_row = cv.take<int>(ug.grow.size());
+      d.ug_uptr = cv.take<int>(ug.uptr.size());
+      d.ug_col = cv.take<int>(ug.ucol.size());
+      d.ug_voff = cv.take<int64_t>(ug.voff.size());
+      d.ug_val = cv.take<double>((size_t)ug.nval);
     }
     d.prow = cv.take<int>(lh.P.rowptr.size());
     d.pcol = cv.take<int>(lh.P.col.size());
@@ -126,6 +145,13 @@ void up(T* dst, const std::vector<T>& src, hipStream_t s) {
 }  // namespace
 
 void vk::check_launch() { HIPCHECK(hipGetLastError()); }
+
+void vk::spmm_k(const DevLevel& d, int mode, int R, const double* X, const double* B, double* Y, hipStream_t s) {
+  if (R > 32 && d.nug > 0)
+    launch_spmm_union(mode, d.nug, d.ug_ptr, d.ug_row, d.ug_uptr, d.ug_col, d.ug_voff, d.ug_val, R, X, B, Y, s);
+  else
+    launch_spmm(mode, d.N, d.nkg, d.kgrp, R, d.rowptr, d.col, d.val, X, B, Y, s);
+}
 
 namespace {
 
@@ -646,7 +672,7 @@ void smooth_multi(vk_hierarchy* h, int l, int R, const double* B, double* X, int
     if (stimed) sev = timer_start(h);
     const double* T = B;
     if (!first_zero) {
-      launch_spmm(1, d.N, d.nkg, d.kgrp, R, d.rowptr, d.col, d.val, X, B, d.t, s);
+      spmm_k(d, 1, R, X, B, d.t, s);
       T = d.t;
     }
     const bool timed = h->timing && !h->capturing && l == h->L() - 1;
@@ -689,7 +715,7 @@ void vk::vcycle_multi(vk_hierarchy* h, int l, int R, const double* Rv, double* E
   }
   DevLevel& c = h->D[l - 1];
   smooth_multi(h, l, R, Rv, E, nu_pre, true);
-  launch_spmm(1, d.N, d.nkg, d.kgrp, R, d.rowptr, d.col, d.val, E, Rv, d.t, s);
+  spmm_k(d, 1, R, E, Rv, d.t, s);
   launch_spmm(0, c.N, d.nptg, d.ptgrp, R, d.ptrow, d.ptcol, d.ptval, d.t, nullptr, c.b, s);
   check_launch();
   vcycle_multi(h, l - 1, R, c.b, c.x, nu_pre, nu_post);
@@ -777,7 +803,7 @@ vk_status fgmres_multi(vk_hierarchy* h, int R, const double* B, double* X, const
         double* zj = h->Z + j * NR;
         double* w = h->V + (j + 1) * NR;
         vk::vcycle_multi(h, Lf, R, vj, zj, o.nu_pre, o.nu_post);
-        launch_spmm(0, N, F.nkg, F.kgrp, R, F.rowptr, F.col, F.val, zj, nullptr, w, s);
+        spmm_k(F, 0, R, zj, nullptr, w, s);
         double* h1 = h->small;
         double* h2 = h->small + (size_t)(m + 2) * R;
         double* nn = h->small + (size_t)2 * (m + 2) * R;
@@ -852,7 +878,7 @@ vk_status fgmres_multi(vk_hierarchy* h, int R, const double* B, double* X, const
     HIPCHECK(hipMemcpyAsync(h->mask, mask.data(), R * sizeof(int), hipMemcpyHostToDevice, s));
     launch_axpy_cols(N, R, m, h->nvc, 1.0, h->Z, (int64_t)N * R, h->ydev, X, s);
     launch_project_cols(N, nvel, R, zv, h->mask, X, h->partial, s);
-    launch_spmm(1, N, F.nkg, F.kgrp, R, F.rowptr, F.col, F.val, X, h->bb, h->r, s);
+    spmm_k(F, 1, R, X, h->bb, h->r, s);
     check_launch();
   }
   if (h->timing || h->sweep_timing) collect_timing(h);
@@ -1048,6 +1074,17 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_ws, size_t bytes, int max_r
       up(d.ptval, L.PT.val, s);
       up(d.pgrp, L.pgrp, s);
       up(d.ptgrp, L.ptgrp, s);
+      if (d.nug > 0) {
+        const UnionGroups& ug = k_unions(L);
+        up(d.ug_ptr, ug.gptr, s);
+        up(d.ug_row, ug.grow, s);
+        up(d.ug_uptr, ug.uptr, s);
+        up(d.ug_col, ug.ucol, s);
+        up(d.ug_voff, ug.voff, s);
+        const std::vector<double> v = union_values(L.K, ug);
+        up(d.ug_val, v, s);
+        HIPCHECK(hipStreamSynchronize(s));  // v is released on return
+      }
       up(d.pptr, L.pptr, s);
       up(d.pdofs, L.pdofs, s);
       up(d.dptr, L.dptr, s);
@@ -1267,6 +1304,17 @@ vk_status vk_spmv(vk_hierarchy* h, int level, const double* x, double* y) {
     require_level(h, level, 0);
     DevLevel& d = h->D[level];
     launch_csr(0, d.N, d.k_lanes, d.rowptr, d.col, d.val, x, nullptr, y, h->stream);
+    check_launch();
+    return VK_OK;
+  });
+}
+
+vk_status vk_spmv_multi(vk_hierarchy* h, int level, const double* X, double* Y, int nrhs) {
+  return guarded([&]() -> vk_status {
+    require(h && h->bound && X && Y, VK_ESTATE, "hierarchy not bound or null vector");
+    require_level(h, level, 0);
+    require(nrhs >= 1 && nrhs <= h->max_rhs, VK_EINVAL, "nrhs must be in 1..max_rhs of the bind");
+    spmm_k(h->D[level], 0, nrhs, X, nullptr, Y, h->stream);
     check_launch();
     return VK_OK;
   });

@@ -41,6 +41,11 @@ struct DevLevel {
   double* val = nullptr;
   int *kgrp = nullptr, *pgrp = nullptr, *ptgrp = nullptr;  // row runs with identical patterns (K, P, P^T)
   int nkg = 0, npg = 0, nptg = 0;
+  // K in union groups (bound for more than 32 right-hand sides, levels >= 1; nug = 0 otherwise)
+  int nug = 0;
+  int *ug_ptr = nullptr, *ug_row = nullptr, *ug_uptr = nullptr, *ug_col = nullptr;
+  int64_t* ug_voff = nullptr;
+  double* ug_val = nullptr;
   int *prow = nullptr, *pcol = nullptr, *ptrow = nullptr, *ptcol = nullptr;
   double *pval = nullptr, *ptval = nullptr;
   int *pptr = nullptr, *pdofs = nullptr, *dptr = nullptr, *dslot = nullptr, *order = nullptr, *classes = nullptr;
@@ -133,5 +138,8 @@ struct vk_hierarchy {
 
 namespace vk {
 void check_launch();
+// Y = K X (mode 0), B - K X (1), Y += K X (2) on level d, [N][R] multivectors: over the union
+// groups when bound for more than 32 right-hand sides, else over the runs of identical rows
+void spmm_k(const DevLevel& d, int mode, int R, const double* X, const double* B, double* Y, hipStream_t s);
 void vcycle_multi(vk_hierarchy* h, int l, int R, const double* Rv, double* E, int nu_pre, int nu_post);
 }  // namespace vk

@@ -1,6 +1,7 @@
 // Host-side finite-element building blocks: quadrature on simplices and the
 // equispaced Lagrange basis in barycentric form (Sec. 2, Taylor-Hood spaces).
 #include <algorithm>
+#include <iterator>
 #include <cmath>
 
 #include "vk_internal.hpp"
@@ -166,6 +167,90 @@ std::vector<int> row_groups(const Csr& a, int cap) {
   }
   g.push_back(a.nrows);
   return g;
+}
+
+UnionGroups union_groups(const Csr& a, const std::vector<int>& runs, const std::vector<int>& run_order) {
+  for (int r = 0; r < a.nrows; ++r)
+    for (int q = a.rowptr[r] + 1; q < a.rowptr[r + 1]; ++q)
+      require(a.col[q - 1] < a.col[q], VK_EINVAL, "union groups need ascending column lists");
+  UnionGroups g;
+  g.gptr.push_back(0);
+  g.uptr.push_back(0);
+  std::vector<int> cur, merged;  // the open group's column union
+  int64_t cur_nnz = 0;
+  auto close = [&]() {
+    if (g.grow.size() == (size_t)g.gptr.back()) return;
+    const int rows = (int)g.grow.size() - g.gptr.back();
+    g.voff.push_back(g.nval);
+    const int padded = ((int)cur.size() + 15) / 16 * 16;
+    for (int i = 0; i < padded; ++i) g.ucol.push_back(cur[std::min(i, (int)cur.size() - 1)]);
+    g.nval += (int64_t)padded * rows;
+    g.gptr.push_back((int)g.grow.size());
+    g.uptr.push_back((int)g.ucol.size());
+    cur.clear();
+    cur_nnz = 0;
+  };
+  for (const int ri : run_order) {
+    const int r0 = runs[ri], r1 = runs[ri + 1];
+    const int* c0 = a.col.data() + a.rowptr[r0];
+    const int m = a.rowptr[r0 + 1] - a.rowptr[r0];
+    merged.clear();
+    std::set_union(cur.begin(), cur.end(), c0, c0 + m, std::back_inserter(merged));
+    const int rows = (int)g.grow.size() - g.gptr.back() + (r1 - r0);
+    const int64_t nnz = cur_nnz + (int64_t)(r1 - r0) * m;
+    if (!cur.empty() && ((int)merged.size() > kUnionMaxCols || rows > kUnionMaxRows ||
+                         (double)rows * (double)merged.size() > kUnionMaxFill * (double)nnz)) {
+      close();
+      cur.assign(c0, c0 + m);
+    } else {
+      cur.swap(merged);
+    }
+    cur_nnz += (int64_t)(r1 - r0) * m;
+    for (int r = r0; r < r1; ++r) g.grow.push_back(r);
+  }
+  close();
+  return g;
+}
+
+std::vector<double> union_values(const Csr& a, const UnionGroups& g) {
+  std::vector<double> v((size_t)g.nval, 0.0);
+  for (int gi = 0; gi < g.ngroups(); ++gi) {
+    const int G = g.gptr[gi + 1] - g.gptr[gi];
+    const int* u = g.ucol.data() + g.uptr[gi];
+    double* blk = v.data() + g.voff[gi];
+    for (int t = 0; t < G; ++t) {
+      const int r = g.grow[g.gptr[gi] + t];
+      int j = 0;  // position in the union (ascending; the padding repeats the last column, left at zero)
+      for (int q = a.rowptr[r]; q < a.rowptr[r + 1]; ++q) {
+        while (u[j] < a.col[q]) ++j;
+        blk[(int64_t)(j / 4) * G * 4 + t * 4 + j % 4] = a.val[q];
+      }
+    }
+  }
+  return v;
+}
+
+std::vector<int> runs_in_patch_order(const std::vector<int>& runs, const std::vector<int>& pptr,
+                                     const std::vector<int>& pdofs) {
+  const int nruns = (int)runs.size() - 1;
+  const int nrows = runs.back();
+  std::vector<int> run_of(nrows);
+  for (int ri = 0; ri < nruns; ++ri)
+    for (int r = runs[ri]; r < runs[ri + 1]; ++r) run_of[r] = ri;
+  std::vector<char> seen(nruns, 0);
+  std::vector<int> order;
+  order.reserve(nruns);
+  for (int p = 0; p + 1 < (int)pptr.size(); ++p)
+    for (int q = pptr[p]; q < pptr[p + 1]; ++q) {
+      const int ri = run_of[pdofs[q]];
+      if (!seen[ri]) {
+        seen[ri] = 1;
+        order.push_back(ri);
+      }
+    }
+  for (int ri = 0; ri < nruns; ++ri)
+    if (!seen[ri]) order.push_back(ri);
+  return order;
 }
 
 }  // namespace vk

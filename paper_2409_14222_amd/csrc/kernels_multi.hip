@@ -137,6 +137,127 @@ __global__ void __launch_bounds__(256) spmm_wave_kernel(int ngroups, const int* 
   }
 }
 
+// R > 32 over union groups (up to 16 rows sharing one column list, see union_groups), one group
+// per wave, on the FP64 matrix cores: Y_g (G x R) = V_g (G x U) X[list, :] (U x R) in steps of 4
+// listed columns, v_mfma_f64_16x16x4f64 per 16 right-hand sides.  Lane l holds A[l % 16][l / 16]
+// (value of row l % 16 at the step's column l / 16), B[l / 16][l % 16] (X at the step's column
+// l / 16, right-hand side 16 nb + l % 16), and D[4 r + l / 16][l % 16] in element r; the
+// instruction accumulates D = C + A B as FMAs in ascending k (measured on gfx950), so every row
+// sums its entries in ascending column order as spmm_run does and the results are bitwise those
+// of launch_spmm.  Each listed row of X is read once per group (one 128-byte piece per 16 lanes)
+// and the values once; rows beyond G take zeros, and rows without an entry in a column multiply
+// a stored zero (X finite).  Right-hand sides c >= R run on a clamped column and store nothing.
+//
+// The steps go through a ring of 4 stages: while step k runs, the X rows and values of step k + 3
+// and this lane's column index of step k + 7 are in flight.  Every step issues the same loads
+// (clamped to the last step near the end) in a fixed order, kept by scheduling barriers, so the
+// in-order load counter lets step k wait for its own rows only: the index a step waits for was
+// issued four steps earlier, after every X row still pending; the zeroing of rows beyond G is
+// applied at the product, not at the load, for the same reason.  Column lists are padded to a
+// multiple of 16, so a round of 4 steps is never cut short.  Workgroup b runs on XCD b % 8
+// (round-robin dispatch), so the launch gives XCD x the contiguous range of `per_xcd` blocks
+// starting at x per_xcd: groups come in patch order, and neighbouring groups share X rows in that
+// XCD's L2.
+typedef double dbl4_t __attribute__((ext_vector_type(4)));
+
+#define VK_UNION_STEP(Q, QN)                                                                       \
+  {                                                                                                \
+    const int k = k0 + Q;                                                                          \
+    load(k + 3, ix##QN, x##QN, a##QN);                                                             \
+    ix##QN = cidx(k + 7);                                                                          \
+    __builtin_amdgcn_sched_barrier(0);                                                             \
+    mma(x##Q, a##Q);                                                                               \
+    __builtin_amdgcn_sched_barrier(0);                                                             \
+  }
+
+template <int MODE>
+__global__ void __launch_bounds__(256, 4) spmm_union_kernel(int ngroups, int per_xcd,
+                                                            const int* __restrict__ gptr,
+                                                            const int* __restrict__ grow,
+                                                            const int* __restrict__ uptr,
+                                                            const int* __restrict__ ucol,
+                                                            const int64_t* __restrict__ voff,
+                                                            const double* __restrict__ gval, int R,
+                                                            const double* __restrict__ X,
+                                                            const double* __restrict__ B, double* __restrict__ Y) {
+  const int m = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  const int g = __builtin_amdgcn_readfirstlane(m * 4 + (threadIdx.x >> 6));
+  if (g >= ngroups) return;
+  const int l = threadIdx.x & 63, i = l & 15, kq = l >> 4;
+  const int r0 = __builtin_amdgcn_readfirstlane(gptr[g]);
+  const int G = __builtin_amdgcn_readfirstlane(gptr[g + 1]) - r0;
+  const int u0 = __builtin_amdgcn_readfirstlane(uptr[g]);
+  const int nsteps = (__builtin_amdgcn_readfirstlane(uptr[g + 1]) - u0) >> 2;  // a multiple of 4
+  const int* uc = ucol + u0 + kq;  // this lane's column of step k: uc[4 k]
+  const double* v = gval + voff[g];
+  int cx[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) cx[nb] = min(nb * 16 + i, R - 1);
+  const int ia = min(i, G - 1) * 4 + kq;  // this lane's value in a step's G x 4 block (clamped row)
+  auto cidx = [&](int k) { return uc[4 * min(k, nsteps - 1)]; };
+  auto load = [&](int k, int c, double* x, double& a) {
+    const int64_t xr = (int64_t)c * R;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) x[nb] = X[xr + cx[nb]];
+    a = v[(int64_t)min(k, nsteps - 1) * G * 4 + ia];
+  };
+  dbl4_t acc[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = dbl4_t{0.0, 0.0, 0.0, 0.0};
+  const bool live = i < G;
+  auto mma = [&](const double* x, double a) {
+    const double az = live ? a : 0.0;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+      acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, x[nb], acc[nb], 0, 0, 0);
+  };
+  double x0[4], x1[4], x2[4], x3[4], a0, a1, a2, a3;
+  int ix0 = cidx(0), ix1 = cidx(1), ix2 = cidx(2), ix3 = cidx(3);
+  load(0, ix0, x0, a0);
+  load(1, ix1, x1, a1);
+  load(2, ix2, x2, a2);
+  ix0 = cidx(4);
+  ix1 = cidx(5);
+  ix2 = cidx(6);
+  for (int k0 = 0; k0 < nsteps; k0 += 4) {
+    VK_UNION_STEP(0, 3)
+    VK_UNION_STEP(1, 0)
+    VK_UNION_STEP(2, 1)
+    VK_UNION_STEP(3, 2)
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 4 * r + kq;
+    if (row >= G) continue;
+    const int64_t ob = (int64_t)grow[r0 + row] * R;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      const int c = nb * 16 + i;
+      if (c >= R) continue;
+      const int64_t o = ob + c;
+      if (MODE == 0) Y[o] = acc[nb][r];
+      else if (MODE == 1) Y[o] = B[o] - acc[nb][r];
+      else Y[o] += acc[nb][r];
+    }
+  }
+}
+#undef VK_UNION_STEP
+
+void launch_spmm_union(int mode, int ngroups, const int* gptr, const int* grow, const int* uptr, const int* ucol,
+                       const int64_t* voff, const double* gval, int R, const double* X, const double* B, double* Y,
+                       hipStream_t s) {
+  if (ngroups <= 0) return;
+  const int blocks = (ngroups + 3) / 4;
+  const int per_xcd = (blocks + 7) / 8;
+  const int grid = per_xcd * 8;  // block b covers range block (b % 8) per_xcd + b / 8; those past the end exit
+  if (mode == 0)
+    spmm_union_kernel<0><<<grid, 256, 0, s>>>(ngroups, per_xcd, gptr, grow, uptr, ucol, voff, gval, R, X, B, Y);
+  else if (mode == 1)
+    spmm_union_kernel<1><<<grid, 256, 0, s>>>(ngroups, per_xcd, gptr, grow, uptr, ucol, voff, gval, R, X, B, Y);
+  else
+    spmm_union_kernel<2><<<grid, 256, 0, s>>>(ngroups, per_xcd, gptr, grow, uptr, ucol, voff, gval, R, X, B, Y);
+}
+
 void launch_spmm(int mode, int nrows, int ngroups, const int* grp, int R, const int* rp, const int* col,
                  const double* val, const double* X, const double* B, double* Y, hipStream_t s) {
   (void)nrows;

@@ -317,7 +317,7 @@ void enqueue_residual(Resident* r) {
   const hipStream_t st = r->stream;
   h2d(r, cip(r, CI_JNEXT), hip_(r, HI_ZERO), 64);
   launch_gather_slice(r->N, r->S, r->nvel, r->X, 0, cip(r, CI_JNEXT), cvp(r, CV_ONE), cvp(r, CV_INVNU), F.b, st);
-  launch_spmm(0, r->N, F.nkg, F.kgrp, r->S, F.rowptr, F.col, F.val, F.b, nullptr, F.t, st);
+  spmm_k(F, 0, r->S, F.b, nullptr, F.t, st);
   launch_residual_scaled(r->N, r->S, r->nvel, h->bb, F.t, cvp(r, CV_NU), h->r, st);
   check_launch();
 }
@@ -378,7 +378,7 @@ void enqueue_arnoldi(Resident* r, int m, int nu_pre, int nu_post) {
   vcycle_multi(h, h->L() - 1, r->S, F.b, F.x, nu_pre, nu_post);
   launch_scatter_slice(r->N, r->S, r->nvel, F.x, cvp(r, CV_ONE), cvp(r, CV_NU), cip(r, CI_JC), h->Z, slice, st);
   // w = K_nu z_j = D_L K_1 (D_R z_j) and D_R z_j is the V-cycle output itself
-  launch_spmm(0, r->N, F.nkg, F.kgrp, r->S, F.rowptr, F.col, F.val, F.x, nullptr, F.t, st);
+  spmm_k(F, 0, r->S, F.x, nullptr, F.t, st);
   h2d(r, cip(r, CI_MASK), hip_(r, HI_ZERO), 64);
   launch_gather_slice(r->N, r->S, r->nvel, F.t, 0, cip(r, CI_MASK), cvp(r, CV_NU), cvp(r, CV_ONE), r->W, st);
   // CGS2 against v_0 .. v_j (per-column counts), norm, normalisation, store as v_{j+1}

@@ -32,6 +32,31 @@ Csr transpose(const Csr& a);
 // followed by nrows: a many-right-hand-side product reads each input row once per run
 std::vector<int> row_groups(const Csr& a, int cap);
 
+// Rows gathered into groups that share one ascending column list (the union of their rows'
+// lists, padded to a multiple of 16 with its last column): a many-right-hand-side product loads
+// each listed input row once for the whole group and multiplies a stored zero where a row has no
+// entry.  Values are dense per group, [step of 4 columns][row of the group][4].
+struct UnionGroups {
+  std::vector<int> gptr, grow;  // group g: rows grow[gptr[g] .. gptr[g + 1])
+  std::vector<int> uptr, ucol;  // its columns ucol[uptr[g] .. uptr[g + 1])
+  std::vector<int64_t> voff;    // offset of its value block
+  int64_t nval = 0;             // total values
+  int ngroups() const { return (int)gptr.size() - 1; }
+};
+constexpr int kUnionMaxRows = 16;     // rows per group (one block of the 16 x 16 matrix-core product)
+constexpr int kUnionMaxCols = 96;     // columns before padding (a single run may exceed it alone)
+constexpr double kUnionMaxFill = 2.0;  // stored values over the group's nonzeros
+// Groups of a's rows: the runs of `runs` (row_groups) taken in `run_order`, each appended to the
+// open group while the group stays within the three limits above.  Rows of a must have ascending
+// column lists.
+UnionGroups union_groups(const Csr& a, const std::vector<int>& runs, const std::vector<int>& run_order);
+// the dense value blocks of `g` (g.nval values)
+std::vector<double> union_values(const Csr& a, const UnionGroups& g);
+// run indices of `runs` in the order their rows first appear in the patch lists (patch id order),
+// then the runs no patch touches
+std::vector<int> runs_in_patch_order(const std::vector<int>& runs, const std::vector<int>& pptr,
+                                     const std::vector<int>& pdofs);
+
 // ---------------------------------------------------------------- FEM kernels (host_fem.cpp)
 // Collapsed Gauss-Legendre rule on the reference simplex with q points per
 // direction: points as barycentric coordinates (dim+1 per point) and weights
@@ -73,6 +98,9 @@ struct LevelHost {
   Csr P, PT;                 // prolongation from level-1 (rows: this level) and its transpose
   // runs of consecutive rows with identical column lists (at most 8 rows): starts, then the row count
   std::vector<int> kgrp, pgrp, ptgrp;
+  // K's rows in union groups for more than 32 right-hand sides (built on first need, levels >= 1)
+  mutable UnionGroups kunion;
+  mutable bool kunion_built = false;
   std::vector<double> b;     // right-hand side (finest level only)
   // patches (host_patches.cpp)
   std::vector<int> pptr, pdofs;   // patch i: pdofs[pptr[i] .. pptr[i+1])

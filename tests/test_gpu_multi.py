@@ -222,6 +222,40 @@ def sv_wide(hier):
     return H64, H32, OH, OV
 
 
+@pytest.mark.parametrize("R", [64, 49, 33])
+def test_spmv_multi_wide_groups(sv_wide, R):
+    """Y = K X for more than 32 columns (rows in groups sharing one column list, FP64 matrix cores)
+    gives bitwise what two products of at most 32 columns give (one run of identical rows at a time,
+    FMAs in ascending column order), on every level; it lies within the FP64 summation bound of the
+    exact product with the library's matrix, and within that plus the assembly rounding of the
+    oracle's product."""
+    import scipy.sparse as sp
+    H64, _, OH, OV = sv_wide
+    for l in range(len(OH.levels)):
+        L = OH.levels[l]
+        X = synth.vector(L.N * R, 2100 + R + l).reshape(L.N, R)
+        Y = torch.empty((L.N, R), dtype=torch.float64, device="cuda")
+        H64.spmv_multi(l, _dev(X), Y, R)
+        halves = []
+        for c0, c1 in ((0, 32), (32, R)):
+            Yh = torch.empty((L.N, c1 - c0), dtype=torch.float64, device="cuda")
+            H64.spmv_multi(l, _dev(X[:, c0:c1]), Yh, c1 - c0)
+            halves.append(_host(Yh))
+        got = _host(Y)
+        assert np.array_equal(got, np.concatenate(halves, axis=1)), l
+        rp, col, val = H64.csr(l)
+        K = sp.csr_matrix((val, col, rp), shape=(L.N, L.N))
+        m = np.diff(rp)[:, None]
+        absKX = abs(K) @ np.abs(X)
+        ratio = (np.abs(got - K @ X) / np.maximum(2 * (m + 2) * EPS * absKX, 1e-300)).max()
+        # the oracle assembles K on its own: entries agree to the quadrature sums' rounding
+        bound = (2 * (L.k + 3) ** 2 + 2 * m + 4) * EPS * absKX
+        ratio_o = (np.abs(got - L.K @ X) / np.maximum(bound, 1e-300)).max()
+        print(f"[gpu-multi] SV wide level {l} R={R}: K X worst error / bound {ratio:.2e} (library matrix), "
+              f"{ratio_o:.2e} (oracle matrix)")
+        assert ratio <= 1.0 and ratio_o <= 1.0
+
+
 @pytest.mark.parametrize("R", [64, 49])
 def test_smooth_multi_wide_fp64(sv_wide, R):
     """One FP64 sweep on R columns from a random start: each column's correction against the
