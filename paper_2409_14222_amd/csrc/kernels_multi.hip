@@ -149,7 +149,8 @@ __global__ void __launch_bounds__(256) spmm_wave_kernel(int ngroups, const int* 
 // a stored zero (X finite).  Right-hand sides c >= R run on a clamped column and store nothing.
 //
 // The steps go through a ring of 4 stages: while step k runs, the X rows and values of step k + 3
-// and this lane's column index of step k + 7 are in flight.  Every step issues the same loads
+// and this lane's column index of step k + 7 are in flight; the output rows are read at the
+// start and B (Y for Y += A X) while the last four steps run.  Every step issues the same loads
 // (clamped to the last step near the end) in a fixed order, kept by scheduling barriers, so the
 // in-order load counter lets step k wait for its own rows only: the index a step waits for was
 // issued four steps earlier, after every X row still pending; the zeroing of rows beyond G is
@@ -212,32 +213,50 @@ __global__ void __launch_bounds__(256, 4) spmm_union_kernel(int ngroups, int per
       acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, x[nb], acc[nb], 0, 0, 0);
   };
   double x0[4], x1[4], x2[4], x3[4], a0, a1, a2, a3;
-  int ix0 = cidx(0), ix1 = cidx(1), ix2 = cidx(2), ix3 = cidx(3);
-  load(0, ix0, x0, a0);
-  load(1, ix1, x1, a1);
-  load(2, ix2, x2, a2);
-  ix0 = cidx(4);
-  ix1 = cidx(5);
-  ix2 = cidx(6);
-  for (int k0 = 0; k0 < nsteps; k0 += 4) {
+  // every index load before the first row loads, so that on entering the loop each pending
+  // index is as old (in loads issued after it) as in the loop's steady state
+  const int c0 = cidx(0), c1 = cidx(1), c2 = cidx(2);
+  int ix3 = cidx(3), ix0 = cidx(4), ix1 = cidx(5), ix2 = cidx(6);
+  int rows[4];  // this lane's output rows 4 r + l / 16 (clamped), needed only at the end
+#pragma unroll
+  for (int r = 0; r < 4; ++r) rows[r] = grow[r0 + min(4 * r + kq, G - 1)];
+  __builtin_amdgcn_sched_barrier(0);
+  load(0, c0, x0, a0);
+  load(1, c1, x1, a1);
+  load(2, c2, x2, a2);
+  __builtin_amdgcn_sched_barrier(0);
+  for (int k0 = 0; k0 < nsteps - 4; k0 += 4) {
     VK_UNION_STEP(0, 3)
     VK_UNION_STEP(1, 0)
     VK_UNION_STEP(2, 1)
     VK_UNION_STEP(3, 2)
   }
+  // the last round: its one remaining row load, then B (or Y) under the last four products
+  load(nsteps - 1, ix3, x3, a3);
+  double bv[4][4];
+  if (MODE != 0) {
+    const double* src = MODE == 1 ? B : Y;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) bv[r][nb] = src[(int64_t)rows[r] * R + cx[nb]];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  mma(x0, a0);
+  mma(x1, a1);
+  mma(x2, a2);
+  mma(x3, a3);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int row = 4 * r + kq;
-    if (row >= G) continue;
-    const int64_t ob = (int64_t)grow[r0 + row] * R;
+    if (4 * r + kq >= G) continue;
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
       const int c = nb * 16 + i;
       if (c >= R) continue;
-      const int64_t o = ob + c;
+      const int64_t o = (int64_t)rows[r] * R + c;
       if (MODE == 0) Y[o] = acc[nb][r];
-      else if (MODE == 1) Y[o] = B[o] - acc[nb][r];
-      else Y[o] += acc[nb][r];
+      else if (MODE == 1) Y[o] = bv[r][nb] - acc[nb][r];
+      else Y[o] = bv[r][nb] + acc[nb][r];
     }
   }
 }
