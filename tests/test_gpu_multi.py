@@ -256,6 +256,41 @@ def test_spmv_multi_wide_groups(sv_wide, R):
         assert ratio <= 1.0 and ratio_o <= 1.0
 
 
+@pytest.mark.parametrize("case", ["p4p3", "p2p1_3d", "bdm3", "q3q2"])
+def test_spmv_multi_groups_every_family(case):
+    """The union-group K product of a hierarchy bound for 64 right-hand sides gives bitwise the
+    <= 32-column product on every level of each discretisation (rows of very different lengths:
+    3D vertex stars, BDM interior-penalty rows, quadrilateral cells) and lies within the FP64
+    summation bound of the exact product with the library's matrix."""
+    import scipy.sparse as sp
+    import paper_2409_14222_amd as vk
+    k, n0, nl, kw = {"p4p3": (4, 4, 3, {}),
+                     "p2p1_3d": (2, 2, 3, dict(dim=3, forcing=vk.VK_F_CUBE_MMS)),
+                     "bdm3": (3, 2, 3, dict(family=vk.VK_BDM, forcing=vk.VK_F_PAPER_MMS)),
+                     "q3q2": (3, 2, 3, dict(family=vk.VK_TH_QUAD))}[case]
+    print(f"[gpu-multi] {case}: hierarchy for 64 right-hand sides", flush=True)
+    H = vk.Hierarchy(k, n0, nl, **kw).bind(max_rhs=64).setup()
+    R = 64
+    for l in range(nl):
+        rp, col, val = H.csr(l)
+        N = len(rp) - 1
+        X = synth.vector(N * R, 2300 + l).reshape(N, R)
+        Y = torch.empty((N, R), dtype=torch.float64, device="cuda")
+        H.spmv_multi(l, _dev(X), Y, R)
+        halves = []
+        for c0 in (0, 32):
+            Yh = torch.empty((N, 32), dtype=torch.float64, device="cuda")
+            H.spmv_multi(l, _dev(X[:, c0:c0 + 32]), Yh, 32)
+            halves.append(_host(Yh))
+        got = _host(Y)
+        assert np.array_equal(got, np.concatenate(halves, axis=1)), (case, l)
+        K = sp.csr_matrix((val, col, rp), shape=(N, N))
+        bound = 2 * (np.diff(rp)[:, None] + 2) * EPS * (abs(K) @ np.abs(X))
+        ratio = (np.abs(got - K @ X) / np.maximum(bound, 1e-300)).max()
+        print(f"[gpu-multi] {case} level {l}: K X worst error / bound {ratio:.2e}")
+        assert ratio <= 1.0
+
+
 @pytest.mark.parametrize("R", [64, 49])
 def test_smooth_multi_wide_fp64(sv_wide, R):
     """One FP64 sweep on R columns from a random start: each column's correction against the
