@@ -153,12 +153,13 @@ __global__ void __launch_bounds__(256) spmm_wave_kernel(int ngroups, const int* 
 // start and B (Y for Y += A X) while the last four steps run.  Every step issues the same loads
 // (clamped to the last step near the end) in a fixed order, kept by scheduling barriers, so the
 // in-order load counter lets step k wait for its own rows only: the index a step waits for was
-// issued four steps earlier, after every X row still pending; the zeroing of rows beyond G is
-// applied at the product, not at the load, for the same reason.  Column lists are padded to a
-// multiple of 16, so a round of 4 steps is never cut short.  Workgroup b runs on XCD b % 8
-// (round-robin dispatch), so the launch gives XCD x the contiguous range of `per_xcd` blocks
-// starting at x per_xcd: groups come in patch order, and neighbouring groups share X rows in that
-// XCD's L2.
+// issued four steps earlier, after every X row still pending (a group's first indices all go
+// out before its first rows, so the loop is entered in the same state); the zeroing of rows
+// beyond G is applied at the product, not at the load, for the same reason.  Column lists are
+// padded to a multiple of 16, so a round of 4 steps is never cut short.  Workgroup b runs on
+// XCD b % 8 (round-robin dispatch), so the launch gives XCD x the contiguous range of `per_xcd`
+// blocks starting at x per_xcd: groups come in patch order, and neighbouring groups share X rows
+// in that XCD's L2.
 typedef double dbl4_t __attribute__((ext_vector_type(4)));
 
 #define VK_UNION_STEP(Q, QN)                                                                       \
