@@ -64,7 +64,7 @@ enum {
 enum {
   VK_TH = 0, /* Taylor-Hood (P_k, P_{k-1}), continuous pressure */
   VK_SV = 1, /* Scott-Vogelius (P_k, dP_{k-1}) on the barycentric refinement of each level (Sec. 2) */
-  VK_TH_QUAD = 2 /* Taylor-Hood (Q_k, Q_{k-1}) on the n x n mesh of squares (2D, 2 <= k <= 7): tensor
+  VK_TH_QUAD = 2 /* Taylor-Hood (Q_k, Q_{k-1}) on the n x n mesh of squares (2D, 2 <= k <= 8): tensor
                     equispaced Lagrange bases, the same free-DoF numbering as VK_TH (the Q_k nodes
                     are the points of the P_k lattice), composite patches of vertices, edge
                     interiors and cell interiors (Sec. 3.1) */,
@@ -103,7 +103,7 @@ enum { VK_WEIGHT_MULTIPLICITY = 0, VK_WEIGHT_NONE = 1 };
 /* Problem statement (Sec. 2 weak form; Sec. 3 hierarchy; Sec. 4 mesh). */
 typedef struct vk_problem {
   int dim;          /* 2 (triangles) or 3 (Kuhn tetrahedra, k = 2 only) */
-  int family;       /* VK_TH, VK_SV (2D, 2 <= k <= 4, VK_PATCH_MACRO), VK_TH_QUAD (2D, 2 <= k <= 7)
+  int family;       /* VK_TH, VK_SV (2D, 2 <= k <= 4, VK_PATCH_MACRO), VK_TH_QUAD (2D, 2 <= k <= 8)
                        or VK_BDM (2D, 1 <= k <= 8, VK_PATCH_EXTENDED) */
   int k;            /* velocity order, pressure order k-1; 2 <= k <= 8 in 2D (VK_BDM: from 1) */
   int n_coarse;     /* cells per direction on level 0 (>= 1) */
@@ -220,7 +220,7 @@ vk_status vk_hierarchy_bind(vk_hierarchy* h, void* d_workspace, size_t bytes, in
  * from the CSR matrix (Sec. 3.1), inverts it by Gauss-Jordan elimination in
  * FP64 and stores the inverse (FP64 or FP32).  Patches of up to 224 DoFs are
  * eliminated with partial pivoting (largest |entry| of the column, ties to the
- * lowest row); larger ones (224 < n <= 512, vertex stars of P6..P8) by blocked
+ * lowest row); larger ones (224 < n <= 768, vertex stars of P6..P8, Q7, Q8) by blocked
  * Gauss-Jordan without pivoting, which relies on the patch ordering (velocity
  * DoFs before pressure DoFs: the pivots run through the positive definite
  * velocity block, then the negative definite pressure Schur complement) and

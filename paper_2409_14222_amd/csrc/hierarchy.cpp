@@ -928,7 +928,7 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
             VK_EINVAL, "unsupported family");
     if (p.family == VK_SV) require(p.k >= 2 && p.k <= 4, VK_EINVAL, "Scott-Vogelius supports 2 <= k <= 4");
     if (p.family == VK_TH_QUAD)
-      require(p.k >= 2 && p.k <= 7, VK_EINVAL, "quadrilateral Taylor-Hood supports 2 <= k <= 7");
+      require(p.k >= 2 && p.k <= 8, VK_EINVAL, "quadrilateral Taylor-Hood supports 2 <= k <= 8");
     if (p.family == VK_BDM) {
       require(p.k >= 1 && p.k <= 8, VK_EINVAL, "BDM supports 1 <= k <= 8");
       require(p.forcing == VK_F_PAPER_MMS, VK_EINVAL, "BDM levels take the paper's field (VK_F_PAPER_MMS)");
@@ -980,7 +980,7 @@ vk_status vk_hierarchy_create(const vk_problem* prob, const vk_patch_opts* opts,
         L.pgrp = row_groups(L.P, 8);
         L.ptgrp = row_groups(L.PT, 8);
         build_patches(L, opts->construct, opts->omega, opts->store);
-        require(L.max_n <= kClassLimit[kClasses - 1], VK_EINVAL, "patches above 512 DoFs are not supported");
+        require(L.max_n <= kClassLimit[kClasses - 1], VK_EINVAL, "patches above 768 DoFs are not supported");
         if (opts->smoother == VK_SMOOTH_CHEBYSHEV || opts->weighting == VK_WEIGHT_NONE) {
           // W (and omega for the damped sweep only)
           const double om = opts->smoother == VK_SMOOTH_CHEBYSHEV ? 1.0 : opts->omega;

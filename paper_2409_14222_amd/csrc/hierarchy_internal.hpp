@@ -20,9 +20,9 @@
 
 namespace vk {
 
-// patch size classes of the setup (one inversion kernel each): n <= 32, 64, 128, 224, 512
-constexpr int kClasses = 5;
-constexpr int kClassLimit[kClasses] = {32, 64, 128, 224, 512};
+// patch size classes of the setup (one inversion kernel each): n <= 32, 64, 128, 224, 512, 768
+constexpr int kClasses = 6;
+constexpr int kClassLimit[kClasses] = {32, 64, 128, 224, 512, 768};
 // patches above 224 DoFs: inverted in global scratch slots (at most this many at once), stored
 // column-major (the symmetric tiled storage is limited to 224)
 constexpr int kBigSlots = 256;
@@ -58,7 +58,7 @@ struct DevLevel {
   double cheb_lambda = 0.0, cheb_theta = 0.0, cheb_delta = 0.0;  // estimate and interval centre / half-width
   int cheb_steps = 0;
   double* M = nullptr;  // coarsest level
-  int class_count[kClasses] = {0, 0, 0, 0, 0};  // patches per size class of kClassLimit (ids in `classes`)
+  int class_count[kClasses] = {0, 0, 0, 0, 0, 0};  // patches per size class of kClassLimit (ids in `classes`)
   // launch shapes (never change results): lanes per CSR row of K, P, P^T;
   // waves per patch for the large (n > 64, first in `order`) and small patches
   int k_lanes = 32, p_lanes = 8, pt_lanes = 8, waves_large = 1, waves_small = 1, n_large = 0;

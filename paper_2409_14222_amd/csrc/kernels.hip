@@ -470,25 +470,27 @@ __global__ void __launch_bounds__(1024) gather_invert_big_kernel(const int* __re
 }
 
 // ============================================================================
-// Patches with 224 < n <= 512 (vertex stars of P6 .. P8): the FP64 matrix
-// (up to 2 MiB) lives in a global scratch slot of the workgroup and is inverted
-// in place by blocked Gauss-Jordan without pivoting.  The patch's DoFs are
+// Patches with 224 < n <= 768 (vertex stars of P6 .. P8, Q7 and Q8): the FP64
+// matrix (up to 4.5 MiB) lives in a global scratch slot of the workgroup and is
+// inverted in place by blocked Gauss-Jordan without pivoting (blocks of BS = 16
+// columns up to 512 DoFs, of 8 above, where two 16 x NMAXG LDS panels would
+// not fit).  The patch's DoFs are
 // ascending with the velocity before the pressure, so the pivots run through
 // the symmetric positive definite velocity block and then through the negative
 // definite Schur complement of the pressure; a pivot of magnitude at most
-// n eps max|K_i|, or a non-finite one, reports the patch as singular.  One step on the pivot block K (16 columns):
+// n eps max|K_i|, or a non-finite one, reports the patch as singular.  One step on the pivot block K (BS columns):
 //   D = M[K,K] -> D^{-1},  M[K,j] -> D^{-1} M[K,j],  M[i,K] -> -M[i,K] D^{-1},
 //   M[i,j] -> M[i,j] - M[i,K] D^{-1} M[K,j]        (i, j outside K)
 // with the block row and column of the step in LDS.  Every sum runs in a fixed
 // order.  A grid of `slots` workgroups walks the patch list (each its own slot).
 // ============================================================================
-template <typename TS>
+template <typename TS, int NMAXG, int BS>
 __global__ void __launch_bounds__(1024) gather_invert_global_kernel(
     const int* __restrict__ list, int count, const int* __restrict__ pptr, const int* __restrict__ pdofs,
     const int* __restrict__ rowptr, const int* __restrict__ col, const double* __restrict__ val,
     const int64_t* __restrict__ inv_off, TS* __restrict__ inv, int* __restrict__ singular, double* __restrict__ scratch,
     int64_t slot_elems, bool tri) {
-  constexpr int NMAXG = 512, BS = 16, NT = 1024;
+  constexpr int NT = 1024;
   __shared__ int Ii[NMAXG];
   __shared__ double Dl[BS * BS];
   __shared__ double Rl[BS * NMAXG];  // block row  [s][j]
@@ -535,7 +537,7 @@ __global__ void __launch_bounds__(1024) gather_invert_global_kernel(
     for (int k0 = 0; k0 < n; k0 += BS) {
       const int kb = min(BS, n - k0);
       if (tid < BS * BS) {
-        const int r = tid & (BS - 1), c = tid >> 4;
+        const int r = tid % BS, c = tid / BS;
         Dl[c * BS + r] = (r < kb && c < kb) ? M[(int64_t)(k0 + c) * n + k0 + r] : (r == c ? 1.0 : 0.0);
       }
       for (int e = tid; e < BS * n; e += NT) {
@@ -544,11 +546,11 @@ __global__ void __launch_bounds__(1024) gather_invert_global_kernel(
         Cl[e] = sidx < kb ? M[(int64_t)(k0 + sidx) * n + j] : 0.0;
       }
       __syncthreads();
-      // D -> D^{-1}: unpivoted scalar Gauss-Jordan on the 16 x 16 block (identity padding)
+      // D -> D^{-1}: unpivoted scalar Gauss-Jordan on the BS x BS block (identity padding)
       for (int j = 0; j < kb; ++j) {
         const double piv = Dl[j * BS + j];
         double nv = 0.0;
-        const int r = tid & (BS - 1), c = tid >> 4;
+        const int r = tid % BS, c = tid / BS;
         if (tid < BS * BS) {
           const double arc = Dl[c * BS + r], arj = Dl[j * BS + r], ajc = Dl[c * BS + j];
           if (r == j && c == j) nv = 1.0 / piv;
@@ -589,7 +591,7 @@ __global__ void __launch_bounds__(1024) gather_invert_global_kernel(
         }
       }
       if (tid < BS * BS) {
-        const int r = tid & (BS - 1), c = tid >> 4;
+        const int r = tid % BS, c = tid / BS;
         if (r < kb && c < kb) M[(int64_t)(k0 + c) * n + k0 + r] = Dl[c * BS + r];
       }
       __syncthreads();
@@ -647,12 +649,20 @@ void launch_gather_invert(int nmax, bool fp32, bool tri, int count, const int* l
   if (count <= 0) return;
   if (nmax > 224) {
     const int grid = std::min(count, slots);
-    if (fp32)
-      gather_invert_global_kernel<float><<<grid, 1024, 0, s>>>(list, count, pptr, pdofs, rowptr, col, val, inv_off,
-                                                               (float*)inv, singular, scratch, slot_elems, tri);
-    else
-      gather_invert_global_kernel<double><<<grid, 1024, 0, s>>>(list, count, pptr, pdofs, rowptr, col, val, inv_off,
-                                                                (double*)inv, singular, scratch, slot_elems, tri);
+    if (nmax > 512) {
+      if (fp32)
+        gather_invert_global_kernel<float, 768, 8><<<grid, 1024, 0, s>>>(
+            list, count, pptr, pdofs, rowptr, col, val, inv_off, (float*)inv, singular, scratch, slot_elems, tri);
+      else
+        gather_invert_global_kernel<double, 768, 8><<<grid, 1024, 0, s>>>(
+            list, count, pptr, pdofs, rowptr, col, val, inv_off, (double*)inv, singular, scratch, slot_elems, tri);
+    } else if (fp32) {
+      gather_invert_global_kernel<float, 512, 16><<<grid, 1024, 0, s>>>(
+          list, count, pptr, pdofs, rowptr, col, val, inv_off, (float*)inv, singular, scratch, slot_elems, tri);
+    } else {
+      gather_invert_global_kernel<double, 512, 16><<<grid, 1024, 0, s>>>(
+          list, count, pptr, pdofs, rowptr, col, val, inv_off, (double*)inv, singular, scratch, slot_elems, tri);
+    }
     return;
   }
   if (nmax <= 32)

@@ -18,9 +18,9 @@ int csr_default_lanes(double mean_row);
 // float: column-major (leading dimension rounded to 2 doubles / 4 floats), or
 // with `tri` the symmetric tiled storage (the 8 x 8 tiles on and below the
 // diagonal; the padding must have been zeroed).  `list` holds `count` patch ids
-// whose size is <= nmax (32, 64, 128, 224 or 512).  `singular` receives the smallest
-// patch id with a zero pivot (initialise to INT_MAX).  nmax 512 (blocked, unpivoted, in
-// global memory) needs `slots` scratch slots of slot_elems >= n^2 doubles each.
+// whose size is <= nmax (32, 64, 128, 224, 512 or 768).  `singular` receives the smallest
+// patch id with a zero pivot (initialise to INT_MAX).  nmax 512 and 768 (blocked, unpivoted, in
+// global memory) need `slots` scratch slots of slot_elems >= n^2 doubles each.
 void launch_gather_invert(int nmax, bool fp32, bool tri, int count, const int* list, const int* pptr,
                           const int* pdofs, const int* rowptr, const int* col, const double* val,
                           const int64_t* inv_off, void* inv, int* singular, double* scratch, int64_t slot_elems,

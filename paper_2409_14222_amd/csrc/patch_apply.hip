@@ -125,12 +125,12 @@ __global__ void __launch_bounds__(64 * W) patch_apply_kernel(const int4* __restr
                                                              TS* __restrict__ delta) {
   constexpr int RPL = 16 / sizeof(TS);
   constexpr int NTH = 64 * W;
-  __shared__ TS xs[512];
+  __shared__ TS xs[768];
   __shared__ TS red[8 * 64 * RPL];
   const int4 m4 = meta[blockIdx.x];
   const int base = m4.x, n = m4.y;
   const int64_t off = (int64_t)(uint32_t)m4.z | ((int64_t)m4.w << 32);
-  if (n > 512 || n <= 0) return;  // the host rejects patches above 512 DoFs; never taken
+  if (n > 768 || n <= 0) return;  // the host rejects patches above 768 DoFs; never taken
   const int ld = (n + RPL - 1) / RPL * RPL;
   const TS* A = inv + off;
   for (int r0 = 0; r0 < ld; r0 += 64 * RPL) {

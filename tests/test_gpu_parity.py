@@ -128,6 +128,13 @@ def q7q6():
     return _quad_fixture(7, 2, 2)
 
 
+@pytest.fixture(scope="module")
+def q8q7():
+    """Q8-Q7 on 4x4 squares, levels 2/4: vertex stars of 579 DoFs (global-memory inversion in blocks
+    of 8 columns, the 768-DoF size class)."""
+    return _quad_fixture(8, 2, 2)
+
+
 def _bdm_fixture(k, n0, nl):
     import paper_2409_14222_amd as vk
     from oracle import fields, solve
@@ -174,16 +181,18 @@ def bdm8():
 # a random relative rhs perturbation of 1e-10 moves the P6-P5 8x8 solution by up to 1.7e-5 and the
 # P8-P7 4x4 solution by up to 7.3e-5 (sparse direct solves), so two 1e-10-residual solutions may
 # differ by twice that; iteration counts and residual histories are still compared tightly.
-# Quadrilaterals, measured the same way: Q2-Q1 16x16 1.4e-7, Q4-Q3 8x8 9.0e-7, Q7-Q6 4x4 1.1e-5
+# Quadrilaterals, measured the same way: Q2-Q1 16x16 1.4e-7, Q4-Q3 8x8 9.0e-7, Q7-Q6 4x4 1.1e-5,
+# Q8-Q7 4x4 2.9e-5
 # BDM with interior penalty, the same way: BDM1 8x8 2.6e-9, BDM2 8x8 2.1e-8, BDM4 8x8 1.4e-7,
 # BDM6 4x4 4.6e-7, BDM8 2x2 9.9e-7
 XTOL = {"p2p1": 1e-8, "p4p3": 1e-8, "p2p1_3d": 1e-8, "p3dp2_sv": 1e-6, "p6p5": 4e-5, "p8p7": 1.5e-4,
-        "q2q1": 3e-7, "q4q3": 2e-6, "q7q6": 2.2e-5, "bdm1": 1e-8, "bdm2": 5e-8, "bdm4": 3e-7, "bdm6": 1e-6, "bdm8": 2e-6}
+        "q2q1": 3e-7, "q4q3": 2e-6, "q7q6": 2.2e-5, "q8q7": 6e-5, "bdm1": 1e-8, "bdm2": 5e-8, "bdm4": 3e-7,
+        "bdm6": 1e-6, "bdm8": 2e-6}
 # the GPU and oracle FP64 solves follow one Krylov trajectory (equal counts, histories checked), so their
 # solutions agree far more closely than two arbitrary 1e-10-residual solutions: 1e-9 for every fixture
 TRAJ_TOL = 1e-9
-ALL = ["p2p1", "p4p3", "p2p1_3d", "p3dp2_sv", "p6p5", "p8p7", "q2q1", "q4q3", "q7q6", "bdm1", "bdm2", "bdm4",
-       "bdm6", "bdm8"]
+ALL = ["p2p1", "p4p3", "p2p1_3d", "p3dp2_sv", "p6p5", "p8p7", "q2q1", "q4q3", "q7q6", "q8q7", "bdm1", "bdm2",
+       "bdm4", "bdm6", "bdm8"]
 
 
 def _assembly_terms(L):

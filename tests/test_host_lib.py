@@ -390,7 +390,7 @@ def test_solution_errors_match_oracle_norms(case):
         vk.Hierarchy(2, 2, 2, forcing=vk.VK_F_RANDOM, coeffs=np.ones((2, 2, 2))).solution_errors(np.zeros(10))
 
 
-@pytest.mark.parametrize("k,n0,nl", [(2, 4, 3), (3, 2, 3), (5, 2, 2), (7, 2, 2)])
+@pytest.mark.parametrize("k,n0,nl", [(2, 4, 3), (3, 2, 3), (5, 2, 2), (7, 2, 2), (8, 2, 2)])
 def test_host_assembly_quad_matches_oracle(k, n0, nl):
     """Quadrilateral Taylor-Hood: the library's host assembly, transfers and patches against the
     oracle's (independent tensor bases and point location)."""
@@ -429,7 +429,7 @@ def test_quad_errors_and_limits():
     x = rng.standard_normal(OH.finest.N) * 0.01
     got, ref = H.solution_errors(x), norms.errors(OH.finest, x)
     assert abs(got[0] - ref[0]) <= 1e-11 * ref[0] and abs(got[1] - ref[1]) <= 1e-11 * ref[1]
-    for kw in ({"k": 8}, {"k": 2, "dim": 3}, {"k": 3, "construct": vk.VK_PATCH_STAR}):
+    for kw in ({"k": 9}, {"k": 2, "dim": 3}, {"k": 3, "construct": vk.VK_PATCH_STAR}):
         k = kw.pop("k")
         with pytest.raises(vk.VkError) as e:
             vk.Hierarchy(k, 2, 2, family=vk.VK_TH_QUAD, **kw)
