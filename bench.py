@@ -47,10 +47,11 @@ HBM_PEAK_GBS = 8000.0
 # source file of that kernel (its hash) and the workload; any change to that
 # file invalidates them (reported as null).
 # Sources: profiles/patch_apply_p4p3_64_fp64.md, profiles/many_rhs_sv_p3dp2_64.md,
-# profiles/patch_apply_bdm4_80_fp64.md
+# profiles/patch_apply_bdm4_80_fp64.md, profiles/patch_apply_p2p1_3d_16_fp64.md
 MEASURED_TRAFFIC = {
     ("patch_apply.hip", "74e54f84d315c303", "p4p3-64", "fp64", 1): 488.1e6,
     ("patch_apply.hip", "74e54f84d315c303", "bdm4-80", "fp64", 1): 764.8e6,
+    ("patch_apply.hip", "74e54f84d315c303", "p2p1-3d-16", "fp64", 1): 533.6e6,
     ("patch_gemm.hip", "55e68640323c960e", "sv-p3dp2-64", "fp32", 64): 555.2e6,
 }
 
