@@ -68,6 +68,7 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     if (R > 32) {
       const UnionGroups& ug = k_unions(lh);
       d.nug = ug.ngroups();
+      d.ug_nval = ug.nval;
       d.ug_ptr = cv.take<int>(ug.gptr.size());
       d.ug_row = cv.take<int>(ug.grow.size());
       d.ug_uptr = cv.take<int>(ug.uptr.size());
@@ -147,10 +148,15 @@ void up(T* dst, const std::vector<T>& src, hipStream_t s) {
 void vk::check_launch() { HIPCHECK(hipGetLastError()); }
 
 void vk::spmm_k(const DevLevel& d, int mode, int R, const double* X, const double* B, double* Y, hipStream_t s) {
-  if (R > 32 && d.nug > 0)
-    launch_spmm_union(mode, d.nug, d.ug_ptr, d.ug_row, d.ug_uptr, d.ug_col, d.ug_voff, d.ug_val, R, X, B, Y, s);
-  else
+  if (R > 32 && d.nug > 0) {
+    // values, X, Y and (modes 1, 2) B: beyond the last-level cache nothing survives to the next
+    // launch, so the single-use operands stream and the L2 keeps the shared X rows
+    const double bytes = 8.0 * ((double)d.ug_nval + (mode == 0 ? 2.0 : 3.0) * d.N * R);
+    launch_spmm_union(mode, d.nug, d.ug_ptr, d.ug_row, d.ug_uptr, d.ug_col, d.ug_voff, d.ug_val, R, X, B, Y,
+                      bytes > kLastLevelCacheBytes, s);
+  } else {
     launch_spmm(mode, d.N, d.nkg, d.kgrp, R, d.rowptr, d.col, d.val, X, B, Y, s);
+  }
 }
 
 namespace {

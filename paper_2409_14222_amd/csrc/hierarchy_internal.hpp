@@ -29,6 +29,9 @@ constexpr int kBigSlots = 256;
 constexpr int kTiledMaxN = 224;
 // the autotuner tries 8 and 16 waves per patch only on launches of at most this many patches
 constexpr int kWideApplyMaxPatches = 4096;
+// MI355X's last-level (Infinity) cache: many-RHS K products that move more bytes than this in
+// one launch stream their single-use operands past the caches
+constexpr double kLastLevelCacheBytes = 256.0 * (1 << 20);
 // the fixed per-device scratch of the allocation-free smoothing call (vk_smooth_noalloc)
 constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
 // its address on `device` (looked up once per device with that device current)
@@ -46,6 +49,7 @@ struct DevLevel {
   int *ug_ptr = nullptr, *ug_row = nullptr, *ug_uptr = nullptr, *ug_col = nullptr;
   int64_t* ug_voff = nullptr;
   double* ug_val = nullptr;
+  int64_t ug_nval = 0;
   int *prow = nullptr, *pcol = nullptr, *ptrow = nullptr, *ptcol = nullptr;
   double *pval = nullptr, *ptval = nullptr;
   int *pptr = nullptr, *pdofs = nullptr, *dptr = nullptr, *dslot = nullptr, *order = nullptr, *classes = nullptr;

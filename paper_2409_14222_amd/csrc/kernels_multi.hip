@@ -150,7 +150,9 @@ __global__ void __launch_bounds__(256) spmm_wave_kernel(int ngroups, const int* 
 //
 // The steps go through a ring of 4 stages: while step k runs, the X rows and values of step k + 3
 // and this lane's column index of step k + 7 are in flight; the output rows are read at the
-// start and B (Y for Y += A X) while the last four steps run.  Every step issues the same loads
+// start and B (Y for Y += A X) while the last four steps run.  With NT the values, B (Y) and the
+// output go through the caches as streaming (non-temporal) accesses, leaving the L2 to the X rows
+// that neighbouring groups share.  Every step issues the same loads
 // (clamped to the last step near the end) in a fixed order, kept by scheduling barriers, so the
 // in-order load counter lets step k wait for its own rows only: the index a step waits for was
 // issued four steps earlier, after every X row still pending (a group's first indices all go
@@ -172,7 +174,7 @@ typedef double dbl4_t __attribute__((ext_vector_type(4)));
     __builtin_amdgcn_sched_barrier(0);                                                             \
   }
 
-template <int MODE>
+template <int MODE, bool NT>
 __global__ void __launch_bounds__(256, 4) spmm_union_kernel(int ngroups, int per_xcd,
                                                             const int* __restrict__ gptr,
                                                             const int* __restrict__ grow,
@@ -201,7 +203,8 @@ __global__ void __launch_bounds__(256, 4) spmm_union_kernel(int ngroups, int per
     const int64_t xr = (int64_t)c * R;
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) x[nb] = X[xr + cx[nb]];
-    a = v[(int64_t)min(k, nsteps - 1) * G * 4 + ia];
+    const double* va = v + (int64_t)min(k, nsteps - 1) * G * 4 + ia;
+    a = NT ? __builtin_nontemporal_load(va) : *va;
   };
   dbl4_t acc[4];
 #pragma unroll
@@ -240,7 +243,10 @@ __global__ void __launch_bounds__(256, 4) spmm_union_kernel(int ngroups, int per
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) bv[r][nb] = src[(int64_t)rows[r] * R + cx[nb]];
+      for (int nb = 0; nb < 4; ++nb) {
+        const double* sb = src + (int64_t)rows[r] * R + cx[nb];
+        bv[r][nb] = NT ? __builtin_nontemporal_load(sb) : *sb;
+      }
   }
   __builtin_amdgcn_sched_barrier(0);
   mma(x0, a0);
@@ -255,9 +261,9 @@ __global__ void __launch_bounds__(256, 4) spmm_union_kernel(int ngroups, int per
       const int c = nb * 16 + i;
       if (c >= R) continue;
       const int64_t o = (int64_t)rows[r] * R + c;
-      if (MODE == 0) Y[o] = acc[nb][r];
-      else if (MODE == 1) Y[o] = bv[r][nb] - acc[nb][r];
-      else Y[o] = bv[r][nb] + acc[nb][r];
+      const double y = MODE == 0 ? acc[nb][r] : MODE == 1 ? bv[r][nb] - acc[nb][r] : bv[r][nb] + acc[nb][r];
+      if (NT) __builtin_nontemporal_store(y, Y + o);
+      else Y[o] = y;
     }
   }
 }
@@ -265,17 +271,23 @@ __global__ void __launch_bounds__(256, 4) spmm_union_kernel(int ngroups, int per
 
 void launch_spmm_union(int mode, int ngroups, const int* gptr, const int* grow, const int* uptr, const int* ucol,
                        const int64_t* voff, const double* gval, int R, const double* X, const double* B, double* Y,
-                       hipStream_t s) {
+                       bool nontemporal, hipStream_t s) {
   if (ngroups <= 0) return;
   const int blocks = (ngroups + 3) / 4;
   const int per_xcd = (blocks + 7) / 8;
   const int grid = per_xcd * 8;  // block b covers range block (b % 8) per_xcd + b / 8; those past the end exit
-  if (mode == 0)
-    spmm_union_kernel<0><<<grid, 256, 0, s>>>(ngroups, per_xcd, gptr, grow, uptr, ucol, voff, gval, R, X, B, Y);
-  else if (mode == 1)
-    spmm_union_kernel<1><<<grid, 256, 0, s>>>(ngroups, per_xcd, gptr, grow, uptr, ucol, voff, gval, R, X, B, Y);
-  else
-    spmm_union_kernel<2><<<grid, 256, 0, s>>>(ngroups, per_xcd, gptr, grow, uptr, ucol, voff, gval, R, X, B, Y);
+#define VK_UNION_LAUNCH(M, NT) \
+  spmm_union_kernel<M, NT><<<grid, 256, 0, s>>>(ngroups, per_xcd, gptr, grow, uptr, ucol, voff, gval, R, X, B, Y)
+  if (nontemporal) {
+    if (mode == 0) VK_UNION_LAUNCH(0, true);
+    else if (mode == 1) VK_UNION_LAUNCH(1, true);
+    else VK_UNION_LAUNCH(2, true);
+  } else {
+    if (mode == 0) VK_UNION_LAUNCH(0, false);
+    else if (mode == 1) VK_UNION_LAUNCH(1, false);
+    else VK_UNION_LAUNCH(2, false);
+  }
+#undef VK_UNION_LAUNCH
 }
 
 void launch_spmm(int mode, int nrows, int ngroups, const int* grp, int R, const int* rp, const int* col,

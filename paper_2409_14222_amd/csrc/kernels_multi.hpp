@@ -15,10 +15,11 @@ void launch_spmm(int mode, int nrows, int ngroups, const int* grp, int R, const 
 // the same product for 32 < R <= 64 over union groups (UnionGroups of vk_internal.hpp: rows grow
 // of group g sharing the column list ucol[uptr[g] ..] padded to a multiple of 16, dense values at
 // gval + voff[g] in steps of 4 columns), at most 16 rows per group, on the FP64 matrix cores;
-// bitwise the results of launch_spmm
+// bitwise the results of launch_spmm; `nontemporal` streams the values, B and Y past the caches
+// (for products larger than the last-level cache; never changes results)
 void launch_spmm_union(int mode, int ngroups, const int* gptr, const int* grow, const int* uptr, const int* ucol,
                        const int64_t* voff, const double* gval, int R, const double* X, const double* B, double* Y,
-                       hipStream_t s);
+                       bool nontemporal, hipStream_t s);
 // Delta_i = K_i^{-1} T[I_i, :] for `count` patches (meta as for the single-vector apply);
 // FP32 inverses run on the matrix cores (FP32 accumulation), FP64 inverses (n <= 128) on vector FMAs.
 // nmax: the largest patch among the `count` (sizes the LDS block).
