@@ -52,7 +52,7 @@ MEASURED_TRAFFIC = {
     ("patch_apply.hip", "74e54f84d315c303", "p4p3-64", "fp64", 1): 488.1e6,
     ("patch_apply.hip", "74e54f84d315c303", "bdm4-80", "fp64", 1): 764.8e6,
     ("patch_apply.hip", "74e54f84d315c303", "p2p1-3d-16", "fp64", 1): 533.6e6,
-    ("patch_gemm.hip", "55e68640323c960e", "sv-p3dp2-64", "fp32", 64): 555.2e6,
+    ("patch_gemm.hip", "47b5326cadb9cfcc", "sv-p3dp2-64", "fp32", 64): 456.6e6,
 }
 
 

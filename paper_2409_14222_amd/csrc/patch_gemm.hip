@@ -12,10 +12,10 @@ namespace vk {
 // ============================================================================
 // Patch GEMM on the matrix cores: Delta_i = K_i^{-1} T[I_i, 0:R] with FP32
 // inverses, FP32 inputs and FP32 accumulation (v_mfma_f32_16x16x4_f32).  One
-// 256-thread workgroup per patch.  The residual block T[I_i, :] is gathered
-// once into LDS as FP32 (zero-padded to 64 columns and to a multiple of 4
-// rows); the inverse streams from HBM as the A operand.  Wave w computes the
-// 16-row tiles w, w + 4, ..., each against the four 16-column tiles.
+// workgroup per patch.  The residual block T[I_i, :] is gathered once into LDS
+// as FP32 (zero-padded to 64 columns and to a multiple of 4 rows); the inverse
+// streams from HBM as the A operand.  Each 16-row tile of the result is taken
+// against the four 16-column tiles.
 // Operand layout of the instruction (lane l): A[l % 16][l / 16],
 // B[l / 16][l % 16], result rows 4 (l / 16) + i, column l % 16.
 // ============================================================================
@@ -33,9 +33,15 @@ typedef float floatx4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int bs_index(int j, int c) { return j * 64 + (c ^ ((j & 1) << 4)); }
 
 // FULL: all four 16-column tiles hold right-hand sides (R > 48), so the MFMA
-// sequence carries no per-tile test.
-template <int NW, bool FULL>
-__global__ void __launch_bounds__(64 * NW) patch_gemm_mfma_kernel(const int4* __restrict__ meta,
+// sequence carries no per-tile test.  KP > 0: patches of at most 64 KP DoFs on
+// NW = 4 KP waves, one 16-row tile each in at most KP passes of 64 columns; the
+// compiler then keeps a wave in about 52 VGPRs (KP = 1), and the workgroup's waves
+// share the LDS block that a workgroup of KP waves per patch held alone, so 8 waves
+// per SIMD fit instead of 3 (SV P3-dP2 macro patches of 56 DoFs, 64 right-hand
+// sides: 126.5 -> 78.0 us per 8,192 patches; the same tiles in the same order, so
+// the same bits).
+template <int NW, bool FULL, int KP = 0>
+__global__ void __launch_bounds__(64 * NW, KP > 0 ? 16 / NW : 1) patch_gemm_mfma_kernel(const int4* __restrict__ meta,
                                                                   const int* __restrict__ pdofs,
                                                                   const float* __restrict__ inv,
                                                                   const double* __restrict__ T, int R, int nmax,
@@ -44,7 +50,7 @@ __global__ void __launch_bounds__(64 * NW) patch_gemm_mfma_kernel(const int4* __
   const int4 m4 = meta[blockIdx.x];
   const int base = m4.x, n = m4.y;
   const int64_t off = (int64_t)(uint32_t)m4.z | ((int64_t)m4.w << 32);
-  if (n > nmax || n <= 0 || n > 64 * NW) return;  // the launch sizes LDS and waves for every n; never taken
+  if (n > nmax || n <= 0 || n > (KP > 0 ? 64 * KP : 64 * NW)) return;  // the launch sizes LDS and waves for every n; never taken
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int ld = (n + 3) / 4 * 4;  // FP32 inverses: leading dimension rounded to 4
   const int nk = ld;               // depth padded to the MFMA depth 4
@@ -102,7 +108,7 @@ __global__ void __launch_bounds__(64 * NW) patch_gemm_mfma_kernel(const int4* __
     floatx4_t acc[4];
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[ct] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < nk; k0 += 64) {
+    for (int k0 = 0; k0 < (KP > 0 ? min(nk, 64 * KP) : nk); k0 += 64) {
       if (k0 > 0) load_a(rt, k0);
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
@@ -117,7 +123,7 @@ __global__ void __launch_bounds__(64 * NW) patch_gemm_mfma_kernel(const int4* __
         }
       }
     }
-    if (rt + NW < ntiles) load_a(rt + NW, 0);
+    if (KP == 0 && rt + NW < ntiles) load_a(rt + NW, 0);
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
       const int c = ct * 16 + lr;
@@ -127,6 +133,7 @@ __global__ void __launch_bounds__(64 * NW) patch_gemm_mfma_kernel(const int4* __
         if (r < n && c < R) D[(uint32_t)(r * R + c)] = acc[ct][i];
       }
     }
+    if (KP > 0) break;  // at most NW tiles
   }
 }
 
@@ -188,9 +195,9 @@ static void mfma_launch(int count, int nmax, size_t lds, const int4* meta, const
   else if (nmax > 128)
     patch_gemm_mfma_kernel<4, FULL><<<count, 256, lds, s>>>(meta, pdofs, inv, T, R, nmax, delta);
   else if (nmax > 64)
-    patch_gemm_mfma_kernel<2, FULL><<<count, 128, lds, s>>>(meta, pdofs, inv, T, R, nmax, delta);
+    patch_gemm_mfma_kernel<8, FULL, 2><<<count, 512, lds, s>>>(meta, pdofs, inv, T, R, nmax, delta);
   else
-    patch_gemm_mfma_kernel<1, FULL><<<count, 64, lds, s>>>(meta, pdofs, inv, T, R, nmax, delta);
+    patch_gemm_mfma_kernel<4, FULL, 1><<<count, 256, lds, s>>>(meta, pdofs, inv, T, R, nmax, delta);
 }
 
 void launch_patch_gemm(bool fp32, int count, int nmax, const int4* meta, const int* pdofs, const void* inv,
