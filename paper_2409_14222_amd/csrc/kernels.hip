@@ -762,19 +762,23 @@ __global__ void __launch_bounds__(256) scatter_kernel(int N, const int* __restri
   const int d = blockIdx.x * 256 + threadIdx.x;
   if (d >= N) return;
   const int q0 = dptr[d], q1 = dptr[d + 1];
+  // the epilogue's operands are requested with the first slots
+  const double sc = scale[d];
+  double xo, dvo;
+  scatter_prev<MODE>(x, dv, d, xo, dvo);
   double s = 0.0;
-  for (int q = q0; q < q1; q += 8) {
-    int idx[8];
+  for (int q = q0; q < q1; q += 16) {
+    int idx[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) idx[u] = q + u < q1 ? dslot[q + u] : -1;
-    TD v[8];
+    for (int u = 0; u < 16; ++u) idx[u] = q + u < q1 ? dslot[q + u] : -1;
+    TD v[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = idx[u] >= 0 ? delta[idx[u]] : (TD)0;
+    for (int u = 0; u < 16; ++u) v[u] = idx[u] >= 0 ? delta[idx[u]] : (TD)0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < 16; ++u)
       if (q + u < q1) s += (double)v[u];
   }
-  scatter_store<MODE>(scale[d] * s, c1, c2, x, dv, d);
+  scatter_put<MODE>(sc * s, c1, c2, xo, dvo, x, dv, d);
 }
 
 template <int MODE>

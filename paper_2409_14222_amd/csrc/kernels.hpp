@@ -48,18 +48,34 @@ void launch_patch_apply(bool fp32, bool tri, int nmax, int waves, bool nontempor
 // kChebFirstSet dv = c2 y, x = dv; kChebFirstAdd dv = c2 y, x += dv; kChebNext dv = c1 dv + c2 y, x += dv.
 enum ScatterMode { kScatterAdd = 0, kScatterSet = 1, kChebFirstSet = 2, kChebFirstAdd = 3, kChebNext = 4 };
 
+// the values of x and dv that the epilogue reads (the others are left 0), so that a kernel can
+// request them before its sums
 template <int MODE>
-__device__ __forceinline__ void scatter_store(double y, double c1, double c2, double* x, double* dv, int64_t o) {
+__device__ __forceinline__ void scatter_prev(const double* x, const double* dv, int64_t o, double& xo, double& dvo) {
+  xo = (MODE == kScatterAdd || MODE == kChebFirstAdd || MODE == kChebNext) ? x[o] : 0.0;
+  dvo = MODE == kChebNext ? dv[o] : 0.0;
+}
+
+template <int MODE>
+__device__ __forceinline__ void scatter_put(double y, double c1, double c2, double xo, double dvo, double* x, double* dv,
+                                            int64_t o) {
   if (MODE == kScatterAdd) {
-    x[o] += y;
+    x[o] = xo + y;
   } else if (MODE == kScatterSet) {
     x[o] = y;
   } else {
-    const double d = MODE == kChebNext ? c1 * dv[o] + c2 * y : c2 * y;
+    const double d = MODE == kChebNext ? c1 * dvo + c2 * y : c2 * y;
     dv[o] = d;
     if (MODE == kChebFirstSet) x[o] = d;
-    else x[o] += d;
+    else x[o] = xo + d;
   }
+}
+
+template <int MODE>
+__device__ __forceinline__ void scatter_store(double y, double c1, double c2, double* x, double* dv, int64_t o) {
+  double xo, dvo;
+  scatter_prev<MODE>(x, dv, o, xo, dvo);
+  scatter_put<MODE>(y, c1, c2, xo, dvo, x, dv, o);
 }
 
 // x[d] += scale[d] * sum_{slots of d, ascending patch id} delta[slot]

@@ -36,6 +36,14 @@ __device__ __forceinline__ void spmm_run(int r0, int c, int R, const int* __rest
                                          const double* __restrict__ X, const double* __restrict__ B,
                                          double* __restrict__ Y, bool store = true) {
   const int qb = rowptr[r0], m = rowptr[r0 + 1] - qb;  // every row of the run has m entries
+  // B (Y for Y += A X) of the run's rows is requested with the first row loads of X, so that the
+  // run waits for memory once rather than twice
+  double pre[G];
+  if (MODE != 0) {
+    const double* src = MODE == 1 ? B : Y;
+#pragma unroll
+    for (int t = 0; t < G; ++t) pre[t] = src[(int64_t)(r0 + t) * R + c];
+  }
   double acc[G];
 #pragma unroll
   for (int t = 0; t < G; ++t) acc[t] = 0.0;
@@ -82,8 +90,8 @@ __device__ __forceinline__ void spmm_run(int r0, int c, int R, const int* __rest
   for (int t = 0; t < G; ++t) {
     const int64_t o = (int64_t)(r0 + t) * R + c;
     if (MODE == 0) Y[o] = acc[t];
-    else if (MODE == 1) Y[o] = B[o] - acc[t];
-    else Y[o] += acc[t];
+    else if (MODE == 1) Y[o] = pre[t] - acc[t];
+    else Y[o] = pre[t] + acc[t];
   }
 }
 
