@@ -49,10 +49,10 @@ HBM_PEAK_GBS = 8000.0
 # Sources: profiles/patch_apply_p4p3_64_fp64.md, profiles/many_rhs_sv_p3dp2_64.md,
 # profiles/patch_apply_bdm4_80_fp64.md, profiles/patch_apply_p2p1_3d_16_fp64.md
 MEASURED_TRAFFIC = {
-    ("patch_apply.hip", "74e54f84d315c303", "p4p3-64", "fp64", 1): 488.1e6,
-    ("patch_apply.hip", "74e54f84d315c303", "bdm4-80", "fp64", 1): 764.8e6,
-    ("patch_apply.hip", "74e54f84d315c303", "p2p1-3d-16", "fp64", 1): 533.6e6,
-    ("patch_gemm.hip", "47b5326cadb9cfcc", "sv-p3dp2-64", "fp32", 64): 456.6e6,
+    ("patch_apply.hip", "5deac05388636b60", "p4p3-64", "fp64", 1): 487.8e6,
+    ("patch_apply.hip", "5deac05388636b60", "bdm4-80", "fp64", 1): 764.8e6,
+    ("patch_apply.hip", "5deac05388636b60", "p2p1-3d-16", "fp64", 1): 533.5e6,
+    ("patch_gemm.hip", "010fc9744420da47", "sv-p3dp2-64", "fp32", 64): 456.6e6,
 }
 
 
