@@ -74,10 +74,25 @@ def test_smooth_multi_fp32_matrix_cores(hier, k):
     """FP32 inverses on the matrix cores: error within the FP32 rounding bound (k = 8: 8-wave
     workgroups for the 435-DoF patches)."""
     _, H32, OH, OV = hier[k]
-    R = 16
+    _check_fp32_sweep_from_zero(H32, OH, OV, 16, 1000)
+
+
+@pytest.mark.parametrize("R", [64, 40])
+def test_smooth_multi_fp32_matrix_cores_wide_p4p3(hier, R):
+    """P4-P3 patches of up to 64 DoFs on 4 waves and of 65..123 DoFs on 8 (one 16-row tile per
+    wave), with all four 16-column tiles holding right-hand sides (R = 64) or the fourth empty
+    (R = 40): every column within the FP32 rounding bound."""
+    import paper_2409_14222_amd as vk
+    _, _, OH, OV = hier[4]
+    H32 = vk.Hierarchy(4, 4, 3, store=vk.VK_STORE_FP32).bind(max_rhs=64).setup()
+    assert H32.level_info(2).max_n > 64
+    _check_fp32_sweep_from_zero(H32, OH, OV, R, 1100 + R)
+
+
+def _check_fp32_sweep_from_zero(H32, OH, OV, R, seed):
     l = len(OH.levels) - 1
     L, S = OH.levels[l], OV.smoothers[l]
-    B = synth.vector(L.N * R, 1000).reshape(L.N, R)
+    B = synth.vector(L.N * R, seed).reshape(L.N, R)
     X = _dev(np.zeros((L.N, R)))
     H32.smooth_multi(l, _dev(B), X, R, 1)    # x = 0 + omega W sum_i R_i^T K_i^{-1} R_i b
     got = _host(X)
