@@ -24,6 +24,14 @@ using namespace vk;
 
 namespace {
 
+// the longest run of a row-group start list (runs of identical column lists hold at most 8 rows)
+int longest_run(const std::vector<int>& grp) {
+  int m = 1;
+  for (size_t i = 0; i + 1 < grp.size(); ++i) m = std::max(m, grp[i + 1] - grp[i]);
+  require(m <= 8, VK_EINVAL, "a run of identical rows longer than 8");
+  return m;
+}
+
 thread_local std::string g_err;
 
 // K's union groups of a level with patches, runs taken in patch order (built once)
@@ -57,6 +65,7 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.col = cv.take<int>(lh.K.col.size());
     d.val = cv.take<double>(lh.K.val.size());
     d.nkg = (int)lh.kgrp.size() - 1;
+    d.kg_max = longest_run(lh.kgrp);
     d.kgrp = cv.take<int>(lh.kgrp.size());
     d.b = cv.take<double>((size_t)lh.N * R);
     d.x = cv.take<double>((size_t)lh.N * R);
@@ -83,8 +92,10 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
     d.ptcol = cv.take<int>(lh.PT.col.size());
     d.ptval = cv.take<double>(lh.PT.val.size());
     d.npg = (int)lh.pgrp.size() - 1;
+    d.pg_max = longest_run(lh.pgrp);
     d.pgrp = cv.take<int>(lh.pgrp.size());
     d.nptg = (int)lh.ptgrp.size() - 1;
+    d.ptg_max = longest_run(lh.ptgrp);
     d.ptgrp = cv.take<int>(lh.ptgrp.size());
     d.p_mean = (double)lh.P.nnz() / std::max(1, lh.P.nrows);
     d.pt_mean = (double)lh.PT.nnz() / std::max(1, lh.PT.nrows);
@@ -155,7 +166,7 @@ void vk::spmm_k(const DevLevel& d, int mode, int R, const double* X, const doubl
     launch_spmm_union(mode, d.nug, d.ug_ptr, d.ug_row, d.ug_uptr, d.ug_col, d.ug_voff, d.ug_val, R, X, B, Y,
                       bytes > kLastLevelCacheBytes, s);
   } else {
-    launch_spmm(mode, d.N, d.nkg, d.kgrp, R, d.rowptr, d.col, d.val, X, B, Y, s);
+    launch_spmm(mode, d.kg_max, d.nkg, d.kgrp, R, d.rowptr, d.col, d.val, X, B, Y, s);
   }
 }
 
@@ -722,10 +733,10 @@ void vk::vcycle_multi(vk_hierarchy* h, int l, int R, const double* Rv, double* E
   DevLevel& c = h->D[l - 1];
   smooth_multi(h, l, R, Rv, E, nu_pre, true);
   spmm_k(d, 1, R, E, Rv, d.t, s);
-  launch_spmm(0, c.N, d.nptg, d.ptgrp, R, d.ptrow, d.ptcol, d.ptval, d.t, nullptr, c.b, s);
+  launch_spmm(0, d.ptg_max, d.nptg, d.ptgrp, R, d.ptrow, d.ptcol, d.ptval, d.t, nullptr, c.b, s);
   check_launch();
   vcycle_multi(h, l - 1, R, c.b, c.x, nu_pre, nu_post);
-  launch_spmm(2, d.N, d.npg, d.pgrp, R, d.prow, d.pcol, d.pval, c.x, nullptr, E, s);
+  launch_spmm(2, d.pg_max, d.npg, d.pgrp, R, d.prow, d.pcol, d.pval, c.x, nullptr, E, s);
   check_launch();
   smooth_multi(h, l, R, Rv, E, nu_post, false);
 }

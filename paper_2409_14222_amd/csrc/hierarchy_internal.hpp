@@ -44,6 +44,7 @@ struct DevLevel {
   double* val = nullptr;
   int *kgrp = nullptr, *pgrp = nullptr, *ptgrp = nullptr;  // row runs with identical patterns (K, P, P^T)
   int nkg = 0, npg = 0, nptg = 0;
+  int kg_max = 8, pg_max = 8, ptg_max = 8;  // the longest run of each
   // K in union groups (bound for more than 32 right-hand sides, levels >= 1; nug = 0 otherwise)
   int nug = 0;
   int *ug_ptr = nullptr, *ug_row = nullptr, *ug_uptr = nullptr, *ug_col = nullptr;

@@ -95,7 +95,27 @@ __device__ __forceinline__ void spmm_run(int r0, int c, int R, const int* __rest
   }
 }
 
-template <int MODE>
+// One run of G <= GMAX rows: the cases above GMAX (the longest run the matrix holds, passed by
+// the host) are not compiled, so a matrix of short runs (velocity pairs, continuous pressure)
+// keeps the registers of its kernel low.
+template <int MODE, int GMAX>
+__device__ __forceinline__ void spmm_run_any(int G, int r0, int c, int R, const int* __restrict__ rowptr,
+                                             const int* __restrict__ col, const double* __restrict__ val,
+                                             const double* __restrict__ X, const double* __restrict__ B,
+                                             double* __restrict__ Y, bool store = true) {
+  switch (G) {
+    case 1: spmm_run<MODE, 1>(r0, c, R, rowptr, col, val, X, B, Y, store); break;
+    case 2: if constexpr (GMAX >= 2) spmm_run<MODE, 2>(r0, c, R, rowptr, col, val, X, B, Y, store); break;
+    case 3: if constexpr (GMAX >= 3) spmm_run<MODE, 3>(r0, c, R, rowptr, col, val, X, B, Y, store); break;
+    case 4: if constexpr (GMAX >= 4) spmm_run<MODE, 4>(r0, c, R, rowptr, col, val, X, B, Y, store); break;
+    case 5: if constexpr (GMAX >= 5) spmm_run<MODE, 5>(r0, c, R, rowptr, col, val, X, B, Y, store); break;
+    case 6: if constexpr (GMAX >= 6) spmm_run<MODE, 6>(r0, c, R, rowptr, col, val, X, B, Y, store); break;
+    case 7: if constexpr (GMAX >= 7) spmm_run<MODE, 7>(r0, c, R, rowptr, col, val, X, B, Y, store); break;
+    default: if constexpr (GMAX >= 8) spmm_run<MODE, 8>(r0, c, R, rowptr, col, val, X, B, Y, store); break;
+  }
+}
+
+template <int MODE, int GMAX>
 __global__ void __launch_bounds__(256) spmm_kernel(int ngroups, const int* __restrict__ grp, int R, int Rp,
                                                    const int* __restrict__ rowptr, const int* __restrict__ col,
                                                    const double* __restrict__ val, const double* __restrict__ X,
@@ -105,23 +125,14 @@ __global__ void __launch_bounds__(256) spmm_kernel(int ngroups, const int* __res
   const int c = threadIdx.x % Rp;
   if (g >= ngroups || c >= R) return;
   const int r0 = grp[g];
-  switch (grp[g + 1] - r0) {
-    case 1: spmm_run<MODE, 1>(r0, c, R, rowptr, col, val, X, B, Y); break;
-    case 2: spmm_run<MODE, 2>(r0, c, R, rowptr, col, val, X, B, Y); break;
-    case 3: spmm_run<MODE, 3>(r0, c, R, rowptr, col, val, X, B, Y); break;
-    case 4: spmm_run<MODE, 4>(r0, c, R, rowptr, col, val, X, B, Y); break;
-    case 5: spmm_run<MODE, 5>(r0, c, R, rowptr, col, val, X, B, Y); break;
-    case 6: spmm_run<MODE, 6>(r0, c, R, rowptr, col, val, X, B, Y); break;
-    case 7: spmm_run<MODE, 7>(r0, c, R, rowptr, col, val, X, B, Y); break;
-    default: spmm_run<MODE, 8>(r0, c, R, rowptr, col, val, X, B, Y); break;  // runs are capped at 8 rows
-  }
+  spmm_run_any<MODE, GMAX>(grp[g + 1] - r0, r0, c, R, rowptr, col, val, X, B, Y);
 }
 
 // R > 32: one run per wave.  The run index is made wave-uniform (readfirstlane), so the row
 // pointers, column indices and values, identical for all lanes, are fetched by scalar loads and
 // only the accumulators and the X rows occupy vector registers.  Lanes c >= R follow the same
 // control flow on a clamped column and store nothing.
-template <int MODE>
+template <int MODE, int GMAX>
 __global__ void __launch_bounds__(256) spmm_wave_kernel(int ngroups, const int* __restrict__ grp, int R,
                                                         const int* __restrict__ rowptr,
                                                         const int* __restrict__ col, const double* __restrict__ val,
@@ -133,16 +144,8 @@ __global__ void __launch_bounds__(256) spmm_wave_kernel(int ngroups, const int* 
   const int cl = c < R ? c : R - 1;
   const bool st = c < R;
   const int r0 = __builtin_amdgcn_readfirstlane(grp[g]);
-  switch (__builtin_amdgcn_readfirstlane(grp[g + 1]) - r0) {
-    case 1: spmm_run<MODE, 1>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
-    case 2: spmm_run<MODE, 2>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
-    case 3: spmm_run<MODE, 3>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
-    case 4: spmm_run<MODE, 4>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
-    case 5: spmm_run<MODE, 5>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
-    case 6: spmm_run<MODE, 6>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
-    case 7: spmm_run<MODE, 7>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
-    default: spmm_run<MODE, 8>(r0, cl, R, rowptr, col, val, X, B, Y, st); break;
-  }
+  spmm_run_any<MODE, GMAX>(__builtin_amdgcn_readfirstlane(grp[g + 1]) - r0, r0, cl, R, rowptr, col, val, X, B, Y,
+                           st);
 }
 
 // R > 32 over union groups (up to 16 rows sharing one column list, see union_groups), one group
@@ -298,23 +301,30 @@ void launch_spmm_union(int mode, int ngroups, const int* gptr, const int* grow, 
 #undef VK_UNION_LAUNCH
 }
 
-void launch_spmm(int mode, int nrows, int ngroups, const int* grp, int R, const int* rp, const int* col,
-                 const double* val, const double* X, const double* B, double* Y, hipStream_t s) {
-  (void)nrows;
-  if (ngroups <= 0) return;
+template <int GMAX>
+static void spmm_dispatch(int mode, int ngroups, const int* grp, int R, const int* rp, const int* col,
+                          const double* val, const double* X, const double* B, double* Y, hipStream_t s) {
   if (R > 32) {
     const int grid = (ngroups + 3) / 4;
-    if (mode == 0) spmm_wave_kernel<0><<<grid, 256, 0, s>>>(ngroups, grp, R, rp, col, val, X, B, Y);
-    else if (mode == 1) spmm_wave_kernel<1><<<grid, 256, 0, s>>>(ngroups, grp, R, rp, col, val, X, B, Y);
-    else spmm_wave_kernel<2><<<grid, 256, 0, s>>>(ngroups, grp, R, rp, col, val, X, B, Y);
+    if (mode == 0) spmm_wave_kernel<0, GMAX><<<grid, 256, 0, s>>>(ngroups, grp, R, rp, col, val, X, B, Y);
+    else if (mode == 1) spmm_wave_kernel<1, GMAX><<<grid, 256, 0, s>>>(ngroups, grp, R, rp, col, val, X, B, Y);
+    else spmm_wave_kernel<2, GMAX><<<grid, 256, 0, s>>>(ngroups, grp, R, rp, col, val, X, B, Y);
     return;
   }
   const int Rp = pow2_at_least(R);
   const int gpb = 256 / Rp;
   const int grid = (ngroups + gpb - 1) / gpb;
-  if (mode == 0) spmm_kernel<0><<<grid, 256, 0, s>>>(ngroups, grp, R, Rp, rp, col, val, X, B, Y);
-  else if (mode == 1) spmm_kernel<1><<<grid, 256, 0, s>>>(ngroups, grp, R, Rp, rp, col, val, X, B, Y);
-  else spmm_kernel<2><<<grid, 256, 0, s>>>(ngroups, grp, R, Rp, rp, col, val, X, B, Y);
+  if (mode == 0) spmm_kernel<0, GMAX><<<grid, 256, 0, s>>>(ngroups, grp, R, Rp, rp, col, val, X, B, Y);
+  else if (mode == 1) spmm_kernel<1, GMAX><<<grid, 256, 0, s>>>(ngroups, grp, R, Rp, rp, col, val, X, B, Y);
+  else spmm_kernel<2, GMAX><<<grid, 256, 0, s>>>(ngroups, grp, R, Rp, rp, col, val, X, B, Y);
+}
+
+void launch_spmm(int mode, int gmax, int ngroups, const int* grp, int R, const int* rp, const int* col,
+                 const double* val, const double* X, const double* B, double* Y, hipStream_t s) {
+  if (ngroups <= 0) return;
+  if (gmax <= 2) spmm_dispatch<2>(mode, ngroups, grp, R, rp, col, val, X, B, Y, s);
+  else if (gmax <= 4) spmm_dispatch<4>(mode, ngroups, grp, R, rp, col, val, X, B, Y, s);
+  else spmm_dispatch<8>(mode, ngroups, grp, R, rp, col, val, X, B, Y, s);
 }
 
 // ============================================================================

@@ -9,8 +9,9 @@
 namespace vk {
 
 // Y = A X (mode 0), Y = B - A X (mode 1), Y += A X (mode 2); grp: the ngroups + 1 starts of the
-// runs of rows with identical column lists (at most 8 rows each, from row_groups)
-void launch_spmm(int mode, int nrows, int ngroups, const int* grp, int R, const int* rowptr, const int* col,
+// runs of rows with identical column lists (at most 8 rows each, from row_groups); gmax: the
+// longest of those runs (1..8; the kernel is compiled for runs up to 2, 4 or 8 rows)
+void launch_spmm(int mode, int gmax, int ngroups, const int* grp, int R, const int* rowptr, const int* col,
                  const double* val, const double* X, const double* B, double* Y, hipStream_t s);
 // the same product for 32 < R <= 64 over union groups (UnionGroups of vk_internal.hpp: rows grow
 // of group g sharing the column list ucol[uptr[g] ..] padded to a multiple of 16, dense values at
