@@ -266,8 +266,8 @@ vk_status vk_patch_inverse(vk_hierarchy* h, int level, int patch, double* d_out)
 vk_status vk_spmv(vk_hierarchy* h, int level, const double* d_x, double* d_y);
 /* d_Y = K_level d_X for nrhs (1..max_rhs of the bind) right-hand sides, [N][nrhs] row-major, the
    product the many-right-hand-side smoother and FGMRES use: each row sums its entries in
-   ascending column order (X finite), for more than 32 columns over groups of rows that share one
-   column list on the FP64 matrix cores, with the same bits as at 32 columns or fewer.
+   ascending column order (X finite), for more than 8 columns over groups of rows that share one
+   column list on the FP64 matrix cores, with the same bits as at 8 columns or fewer.
    VK_EINVAL for nrhs out of range. */
 vk_status vk_spmv_multi(vk_hierarchy* h, int level, const double* d_X, double* d_Y, int nrhs);
 /* d_rc = P_level^T d_rf (restriction from level to level-1) */

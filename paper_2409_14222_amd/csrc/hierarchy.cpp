@@ -74,7 +74,7 @@ void carve(const std::vector<LevelHost>& Hs, bool fp32, vk_hierarchy* h, Carver&
       d.M = cv.take<double>((size_t)lh.N * lh.N);
       continue;
     }
-    if (R > 32) {
+    if (R > kUnionMinRhs) {
       const UnionGroups& ug = k_unions(lh);
       d.nug = ug.ngroups();
       d.ug_nval = ug.nval;
@@ -159,7 +159,7 @@ void up(T* dst, const std::vector<T>& src, hipStream_t s) {
 void vk::check_launch() { HIPCHECK(hipGetLastError()); }
 
 void vk::spmm_k(const DevLevel& d, int mode, int R, const double* X, const double* B, double* Y, hipStream_t s) {
-  if (R > 32 && d.nug > 0) {
+  if (R > kUnionMinRhs && d.nug > 0) {
     // values, X, Y and (modes 1, 2) B: beyond the last-level cache nothing survives to the next
     // launch, so the single-use operands stream and the L2 keeps the shared X rows
     const double bytes = 8.0 * ((double)d.ug_nval + (mode == 0 ? 2.0 : 3.0) * d.N * R);

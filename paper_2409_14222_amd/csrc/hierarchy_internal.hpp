@@ -29,6 +29,9 @@ constexpr int kBigSlots = 256;
 constexpr int kTiledMaxN = 224;
 // the autotuner tries 8 and 16 waves per patch only on launches of at most this many patches
 constexpr int kWideApplyMaxPatches = 4096;
+// many-RHS K products run over union groups (FP64 matrix cores) above this many right-hand sides,
+// and over runs of identical rows up to it (both give the same bits)
+constexpr int kUnionMinRhs = 8;
 // MI355X's last-level (Infinity) cache: many-RHS K products that move more bytes than this in
 // one launch stream their single-use operands past the caches
 constexpr double kLastLevelCacheBytes = 256.0 * (1 << 20);
@@ -45,7 +48,7 @@ struct DevLevel {
   int *kgrp = nullptr, *pgrp = nullptr, *ptgrp = nullptr;  // row runs with identical patterns (K, P, P^T)
   int nkg = 0, npg = 0, nptg = 0;
   int kg_max = 8, pg_max = 8, ptg_max = 8;  // the longest run of each
-  // K in union groups (bound for more than 32 right-hand sides, levels >= 1; nug = 0 otherwise)
+  // K in union groups (bound for more than kUnionMinRhs right-hand sides, levels >= 1; nug = 0 otherwise)
   int nug = 0;
   int *ug_ptr = nullptr, *ug_row = nullptr, *ug_uptr = nullptr, *ug_col = nullptr;
   int64_t* ug_voff = nullptr;
@@ -144,7 +147,7 @@ struct vk_hierarchy {
 namespace vk {
 void check_launch();
 // Y = K X (mode 0), B - K X (1), Y += K X (2) on level d, [N][R] multivectors: over the union
-// groups when bound for more than 32 right-hand sides, else over the runs of identical rows
+// groups for more than kUnionMinRhs right-hand sides, else over the runs of identical rows
 void spmm_k(const DevLevel& d, int mode, int R, const double* X, const double* B, double* Y, hipStream_t s);
 void vcycle_multi(vk_hierarchy* h, int l, int R, const double* Rv, double* E, int nu_pre, int nu_post);
 }  // namespace vk

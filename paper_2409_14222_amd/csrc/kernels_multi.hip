@@ -148,9 +148,10 @@ __global__ void __launch_bounds__(256) spmm_wave_kernel(int ngroups, const int* 
                            st);
 }
 
-// R > 32 over union groups (up to 16 rows sharing one column list, see union_groups), one group
-// per wave, on the FP64 matrix cores: Y_g (G x R) = V_g (G x U) X[list, :] (U x R) in steps of 4
-// listed columns, v_mfma_f64_16x16x4f64 per 16 right-hand sides.  Lane l holds A[l % 16][l / 16]
+// Over union groups (up to 16 rows sharing one column list, see union_groups), one group per
+// wave, on the FP64 matrix cores: Y_g (G x R) = V_g (G x U) X[list, :] (U x R) in steps of 4
+// listed columns, v_mfma_f64_16x16x4f64 per 16 right-hand sides (NB = ceil(R / 16) of them, so
+// 1 <= R <= 64).  Lane l holds A[l % 16][l / 16]
 // (value of row l % 16 at the step's column l / 16), B[l / 16][l % 16] (X at the step's column
 // l / 16, right-hand side 16 nb + l % 16), and D[4 r + l / 16][l % 16] in element r; the
 // instruction accumulates D = C + A B as FMAs in ascending k (measured on gfx950), so every row
@@ -185,8 +186,8 @@ typedef double dbl4_t __attribute__((ext_vector_type(4)));
     __builtin_amdgcn_sched_barrier(0);                                                             \
   }
 
-template <int MODE, bool NT>
-__global__ void __launch_bounds__(256, 4) spmm_union_kernel(int ngroups, int per_xcd,
+template <int MODE, bool NT, int NB>
+__global__ void __launch_bounds__(256, NB == 4 ? 4 : 1) spmm_union_kernel(int ngroups, int per_xcd,
                                                             const int* __restrict__ gptr,
                                                             const int* __restrict__ grow,
                                                             const int* __restrict__ uptr,
@@ -205,29 +206,29 @@ __global__ void __launch_bounds__(256, 4) spmm_union_kernel(int ngroups, int per
   const int nsteps = (__builtin_amdgcn_readfirstlane(uptr[g + 1]) - u0) >> 2;  // a multiple of 4
   const int* uc = ucol + u0 + kq;  // this lane's column of step k: uc[4 k]
   const double* v = gval + voff[g];
-  int cx[4];
+  int cx[NB];
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) cx[nb] = min(nb * 16 + i, R - 1);
+  for (int nb = 0; nb < NB; ++nb) cx[nb] = min(nb * 16 + i, R - 1);
   const int ia = min(i, G - 1) * 4 + kq;  // this lane's value in a step's G x 4 block (clamped row)
   auto cidx = [&](int k) { return uc[4 * min(k, nsteps - 1)]; };
   auto load = [&](int k, int c, double* x, double& a) {
     const int64_t xr = (int64_t)c * R;
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) x[nb] = X[xr + cx[nb]];
+    for (int nb = 0; nb < NB; ++nb) x[nb] = X[xr + cx[nb]];
     const double* va = v + (int64_t)min(k, nsteps - 1) * G * 4 + ia;
     a = NT ? __builtin_nontemporal_load(va) : *va;
   };
-  dbl4_t acc[4];
+  dbl4_t acc[NB];
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) acc[nb] = dbl4_t{0.0, 0.0, 0.0, 0.0};
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = dbl4_t{0.0, 0.0, 0.0, 0.0};
   const bool live = i < G;
   auto mma = [&](const double* x, double a) {
     const double az = live ? a : 0.0;
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb)
+    for (int nb = 0; nb < NB; ++nb)
       acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, x[nb], acc[nb], 0, 0, 0);
   };
-  double x0[4], x1[4], x2[4], x3[4], a0, a1, a2, a3;
+  double x0[NB], x1[NB], x2[NB], x3[NB], a0, a1, a2, a3;
   // every index load before the first row loads, so that on entering the loop each pending
   // index is as old (in loads issued after it) as in the loop's steady state
   const int c0 = cidx(0), c1 = cidx(1), c2 = cidx(2);
@@ -248,13 +249,13 @@ __global__ void __launch_bounds__(256, 4) spmm_union_kernel(int ngroups, int per
   }
   // the last round: its one remaining row load, then B (or Y) under the last four products
   load(nsteps - 1, ix3, x3, a3);
-  double bv[4][4];
+  double bv[4][NB];
   if (MODE != 0) {
     const double* src = MODE == 1 ? B : Y;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
+      for (int nb = 0; nb < NB; ++nb) {
         const double* sb = src + (int64_t)rows[r] * R + cx[nb];
         bv[r][nb] = NT ? __builtin_nontemporal_load(sb) : *sb;
       }
@@ -268,7 +269,7 @@ __global__ void __launch_bounds__(256, 4) spmm_union_kernel(int ngroups, int per
   for (int r = 0; r < 4; ++r) {
     if (4 * r + kq >= G) continue;
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
+    for (int nb = 0; nb < NB; ++nb) {
       const int c = nb * 16 + i;
       if (c >= R) continue;
       const int64_t o = (int64_t)rows[r] * R + c;
@@ -287,17 +288,26 @@ void launch_spmm_union(int mode, int ngroups, const int* gptr, const int* grow, 
   const int blocks = (ngroups + 3) / 4;
   const int per_xcd = (blocks + 7) / 8;
   const int grid = per_xcd * 8;  // block b covers range block (b % 8) per_xcd + b / 8; those past the end exit
-#define VK_UNION_LAUNCH(M, NT) \
-  spmm_union_kernel<M, NT><<<grid, 256, 0, s>>>(ngroups, per_xcd, gptr, grow, uptr, ucol, voff, gval, R, X, B, Y)
-  if (nontemporal) {
-    if (mode == 0) VK_UNION_LAUNCH(0, true);
-    else if (mode == 1) VK_UNION_LAUNCH(1, true);
-    else VK_UNION_LAUNCH(2, true);
-  } else {
-    if (mode == 0) VK_UNION_LAUNCH(0, false);
-    else if (mode == 1) VK_UNION_LAUNCH(1, false);
-    else VK_UNION_LAUNCH(2, false);
+  // NB tiles of 16 right-hand sides per wave
+#define VK_UNION_LAUNCH(M, NT, NB) \
+  spmm_union_kernel<M, NT, NB><<<grid, 256, 0, s>>>(ngroups, per_xcd, gptr, grow, uptr, ucol, voff, gval, R, X, B, Y)
+#define VK_UNION_MODES(NT, NB)                  \
+  {                                             \
+    if (mode == 0) VK_UNION_LAUNCH(0, NT, NB);  \
+    else if (mode == 1) VK_UNION_LAUNCH(1, NT, NB); \
+    else VK_UNION_LAUNCH(2, NT, NB);            \
   }
+  if (R > 32) {
+    if (nontemporal) VK_UNION_MODES(true, 4)
+    else VK_UNION_MODES(false, 4)
+  } else if (R > 16) {
+    if (nontemporal) VK_UNION_MODES(true, 2)
+    else VK_UNION_MODES(false, 2)
+  } else {
+    if (nontemporal) VK_UNION_MODES(true, 1)
+    else VK_UNION_MODES(false, 1)
+  }
+#undef VK_UNION_MODES
 #undef VK_UNION_LAUNCH
 }
 

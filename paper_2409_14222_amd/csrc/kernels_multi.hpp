@@ -13,7 +13,7 @@ namespace vk {
 // longest of those runs (1..8; the kernel is compiled for runs up to 2, 4 or 8 rows)
 void launch_spmm(int mode, int gmax, int ngroups, const int* grp, int R, const int* rowptr, const int* col,
                  const double* val, const double* X, const double* B, double* Y, hipStream_t s);
-// the same product for 32 < R <= 64 over union groups (UnionGroups of vk_internal.hpp: rows grow
+// the same product for 1 <= R <= 64 over union groups (UnionGroups of vk_internal.hpp: rows grow
 // of group g sharing the column list ucol[uptr[g] ..] padded to a multiple of 16, dense values at
 // gval + voff[g] in steps of 4 columns), at most 16 rows per group, on the FP64 matrix cores;
 // bitwise the results of launch_spmm; `nontemporal` streams the values, B and Y past the caches

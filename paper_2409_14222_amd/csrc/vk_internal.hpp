@@ -98,7 +98,7 @@ struct LevelHost {
   Csr P, PT;                 // prolongation from level-1 (rows: this level) and its transpose
   // runs of consecutive rows with identical column lists (at most 8 rows): starts, then the row count
   std::vector<int> kgrp, pgrp, ptgrp;
-  // K's rows in union groups for more than 32 right-hand sides (built on first need, levels >= 1)
+  // K's rows in union groups for more than 8 right-hand sides (built on first need, levels >= 1)
   mutable UnionGroups kunion;
   mutable bool kunion_built = false;
   std::vector<double> b;     // right-hand side (finest level only)

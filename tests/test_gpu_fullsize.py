@@ -245,20 +245,20 @@ def test_full_sv_64_rhs_fp32():
         assert i1[0]["iterations"] == infos[c]["iterations"]
     # the K products at this size: the finest level's (about 750 MB per launch, past the last-level
     # cache) streams its single-use operands, the coarser ones do not; both give bitwise the
-    # <= 32-column products and lie within the FP64 summation bound
+    # <= 8-column run products and lie within the FP64 summation bound
     for l in (4, 3):
         rp, col, val = H.csr(l)
         Kl = sp.csr_matrix((val, col, rp), shape=(len(rp) - 1, len(rp) - 1))
         Xl = synth.vector(Kl.shape[0] * R, 2500 + l).reshape(Kl.shape[0], R)
         Y = torch.empty((Kl.shape[0], R), dtype=torch.float64, device="cuda")
         H.spmv_multi(l, _dev(Xl), Y, R)
-        halves = []
-        for c0 in (0, 32):
-            Yh = torch.empty((Kl.shape[0], 32), dtype=torch.float64, device="cuda")
-            H.spmv_multi(l, _dev(Xl[:, c0:c0 + 32]), Yh, 32)
-            halves.append(_host(Yh))
+        slices = []
+        for c0 in range(0, R, 8):
+            Yh = torch.empty((Kl.shape[0], 8), dtype=torch.float64, device="cuda")
+            H.spmv_multi(l, _dev(Xl[:, c0:c0 + 8]), Yh, 8)
+            slices.append(_host(Yh))
         got = _host(Y)
-        assert np.array_equal(got, np.concatenate(halves, axis=1)), l
+        assert np.array_equal(got, np.concatenate(slices, axis=1)), l
         m = np.diff(rp)[:, None]
         ratio = (np.abs(got - Kl @ Xl) / np.maximum(2 * (m + 2) * EPS * (abs(Kl) @ np.abs(Xl)), 1e-300)).max()
         print(f"[measure] full size SV level {l} K X (64 columns): worst error / summation bound {ratio:.2e}")

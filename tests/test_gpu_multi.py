@@ -223,8 +223,9 @@ def test_multi_graph_replays_match_eager(store):
 
 # ---------------------------------------------------------------- the 64-RHS shape at 16x16
 # The Scott-Vogelius many-RHS workload solves 64 right-hand sides at once.  Batches of more than
-# 32 columns take their own kernels (wave-per-row SpMM, wave-per-DoF scatter) and more than 48
-# the full-width matrix-core GEMM; these cases run them at 16x16, where the oracle can follow
+# 32 columns take their own kernels (wave-per-row transfer SpMM, wave-per-DoF scatter) and more
+# than 48 the full-width matrix-core GEMM; K products of more than 8 columns run over union
+# groups on the FP64 matrix cores.  These cases run them at 16x16, where the oracle can follow
 # sampled columns one by one.
 
 @pytest.fixture(scope="module")
@@ -237,13 +238,13 @@ def sv_wide(hier):
     return H64, H32, OH, OV
 
 
-@pytest.mark.parametrize("R", [64, 49, 33])
+@pytest.mark.parametrize("R", [64, 49, 33, 32, 17, 16, 9])
 def test_spmv_multi_wide_groups(sv_wide, R):
-    """Y = K X for more than 32 columns (rows in groups sharing one column list, FP64 matrix cores)
-    gives bitwise what two products of at most 32 columns give (one run of identical rows at a time,
-    FMAs in ascending column order), on every level; it lies within the FP64 summation bound of the
-    exact product with the library's matrix, and within that plus the assembly rounding of the
-    oracle's product."""
+    """Y = K X for more than 8 columns (rows in groups sharing one column list, FP64 matrix cores,
+    1, 2 or 4 tiles of 16 columns per wave) gives bitwise what products of at most 8 columns give
+    (one run of identical rows at a time, FMAs in ascending column order), on every level; it lies
+    within the FP64 summation bound of the exact product with the library's matrix, and within that
+    plus the assembly rounding of the oracle's product."""
     import scipy.sparse as sp
     H64, _, OH, OV = sv_wide
     for l in range(len(OH.levels)):
@@ -251,13 +252,14 @@ def test_spmv_multi_wide_groups(sv_wide, R):
         X = synth.vector(L.N * R, 2100 + R + l).reshape(L.N, R)
         Y = torch.empty((L.N, R), dtype=torch.float64, device="cuda")
         H64.spmv_multi(l, _dev(X), Y, R)
-        halves = []
-        for c0, c1 in ((0, 32), (32, R)):
+        slices = []
+        for c0 in range(0, R, 8):
+            c1 = min(R, c0 + 8)
             Yh = torch.empty((L.N, c1 - c0), dtype=torch.float64, device="cuda")
             H64.spmv_multi(l, _dev(X[:, c0:c1]), Yh, c1 - c0)
-            halves.append(_host(Yh))
+            slices.append(_host(Yh))
         got = _host(Y)
-        assert np.array_equal(got, np.concatenate(halves, axis=1)), l
+        assert np.array_equal(got, np.concatenate(slices, axis=1)), l
         rp, col, val = H64.csr(l)
         K = sp.csr_matrix((val, col, rp), shape=(L.N, L.N))
         m = np.diff(rp)[:, None]
@@ -273,8 +275,8 @@ def test_spmv_multi_wide_groups(sv_wide, R):
 
 @pytest.mark.parametrize("case", ["p4p3", "p2p1_3d", "bdm3", "q3q2"])
 def test_spmv_multi_groups_every_family(case):
-    """The union-group K product of a hierarchy bound for 64 right-hand sides gives bitwise the
-    <= 32-column product on every level of each discretisation (rows of very different lengths:
+    """The union-group K product of a hierarchy bound for 64 right-hand sides gives, for 64 and for
+    16 columns, bitwise the <= 8-column run product on every level of each discretisation (rows of very different lengths:
     3D vertex stars, BDM interior-penalty rows, quadrilateral cells) and lies within the FP64
     summation bound of the exact product with the library's matrix."""
     import scipy.sparse as sp
@@ -285,25 +287,25 @@ def test_spmv_multi_groups_every_family(case):
                      "q3q2": (3, 2, 3, dict(family=vk.VK_TH_QUAD))}[case]
     print(f"[gpu-multi] {case}: hierarchy for 64 right-hand sides", flush=True)
     H = vk.Hierarchy(k, n0, nl, **kw).bind(max_rhs=64).setup()
-    R = 64
-    for l in range(nl):
-        rp, col, val = H.csr(l)
-        N = len(rp) - 1
-        X = synth.vector(N * R, 2300 + l).reshape(N, R)
-        Y = torch.empty((N, R), dtype=torch.float64, device="cuda")
-        H.spmv_multi(l, _dev(X), Y, R)
-        halves = []
-        for c0 in (0, 32):
-            Yh = torch.empty((N, 32), dtype=torch.float64, device="cuda")
-            H.spmv_multi(l, _dev(X[:, c0:c0 + 32]), Yh, 32)
-            halves.append(_host(Yh))
-        got = _host(Y)
-        assert np.array_equal(got, np.concatenate(halves, axis=1)), (case, l)
-        K = sp.csr_matrix((val, col, rp), shape=(N, N))
-        bound = 2 * (np.diff(rp)[:, None] + 2) * EPS * (abs(K) @ np.abs(X))
-        ratio = (np.abs(got - K @ X) / np.maximum(bound, 1e-300)).max()
-        print(f"[gpu-multi] {case} level {l}: K X worst error / bound {ratio:.2e}")
-        assert ratio <= 1.0
+    for R in (64, 16):
+        for l in range(nl):
+            rp, col, val = H.csr(l)
+            N = len(rp) - 1
+            X = synth.vector(N * R, 2300 + l).reshape(N, R)
+            Y = torch.empty((N, R), dtype=torch.float64, device="cuda")
+            H.spmv_multi(l, _dev(X), Y, R)
+            slices = []
+            for c0 in range(0, R, 8):
+                Yh = torch.empty((N, 8), dtype=torch.float64, device="cuda")
+                H.spmv_multi(l, _dev(X[:, c0:c0 + 8]), Yh, 8)
+                slices.append(_host(Yh))
+            got = _host(Y)
+            assert np.array_equal(got, np.concatenate(slices, axis=1)), (case, R, l)
+            K = sp.csr_matrix((val, col, rp), shape=(N, N))
+            bound = 2 * (np.diff(rp)[:, None] + 2) * EPS * (abs(K) @ np.abs(X))
+            ratio = (np.abs(got - K @ X) / np.maximum(bound, 1e-300)).max()
+            print(f"[gpu-multi] {case} R={R} level {l}: K X worst error / bound {ratio:.2e}")
+            assert ratio <= 1.0
 
 
 @pytest.mark.parametrize("R", [64, 49])
