@@ -350,9 +350,26 @@ __global__ void __launch_bounds__(256) scatter_multi_kernel(int N, int R, int Rp
   const int d = blockIdx.x * rpb + threadIdx.x / Rp;
   const int c = threadIdx.x % Rp;
   if (d >= N || c >= R) return;
+  const int q0 = dptr[d], q1 = dptr[d + 1];
+  const int64_t o = (int64_t)d * R + c;
+  // the epilogue's operands are requested with the first slots; 16 slot rows in flight, summed
+  // in ascending slot order
+  const double sc = scale[d];
+  double xo, dvo;
+  scatter_prev<MODE>(X, DV, o, xo, dvo);
   double s = 0.0;
-  for (int q = dptr[d]; q < dptr[d + 1]; ++q) s += (double)delta[(int64_t)dslot[q] * R + c];
-  scatter_store<MODE>(scale[d] * s, c1, c2, X, DV, (int64_t)d * R + c);
+  for (int q = q0; q < q1; q += 16) {
+    int idx[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) idx[u] = dslot[min(q + u, q1 - 1)];
+    TD v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = delta[(int64_t)idx[u] * R + c];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (q + u < q1) s += (double)v[u];
+  }
+  scatter_put<MODE>(sc * s, c1, c2, xo, dvo, X, DV, o);
 }
 
 // R > 32: four DoFs per wave, made wave-uniform so that the slot lists come by scalar loads; the
