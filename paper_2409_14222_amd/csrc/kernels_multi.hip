@@ -151,9 +151,9 @@ __global__ void __launch_bounds__(256) spmm_wave_kernel(int ngroups, const int* 
 // Over union groups (up to 16 rows sharing one column list, see union_groups), one group per
 // wave, on the FP64 matrix cores: Y_g (G x R) = V_g (G x U) X[list, :] (U x R) in steps of 4
 // listed columns, v_mfma_f64_16x16x4f64 per 16 right-hand sides (NB = ceil(R / 16) of them, so
-// 1 <= R <= 64).  Lane l holds A[l % 16][l / 16]
-// (value of row l % 16 at the step's column l / 16), B[l / 16][l % 16] (X at the step's column
-// l / 16, right-hand side 16 nb + l % 16), and D[4 r + l / 16][l % 16] in element r; the
+// 1 <= R <= 64).  Lane l holds A[l % 16][l / 16] (value of row l % 16 at the step's column
+// l / 16), B[l / 16][l % 16] (X at the step's column l / 16, right-hand side 16 nb + l % 16),
+// and D[4 r + l / 16][l % 16] in element r; the
 // instruction accumulates D = C + A B as FMAs in ascending k (measured on gfx950), so every row
 // sums its entries in ascending column order as spmm_run does and the results are bitwise those
 // of launch_spmm.  Each listed row of X is read once per group (one 128-byte piece per 16 lanes)
@@ -291,11 +291,11 @@ void launch_spmm_union(int mode, int ngroups, const int* gptr, const int* grow, 
   // NB tiles of 16 right-hand sides per wave
 #define VK_UNION_LAUNCH(M, NT, NB) \
   spmm_union_kernel<M, NT, NB><<<grid, 256, 0, s>>>(ngroups, per_xcd, gptr, grow, uptr, ucol, voff, gval, R, X, B, Y)
-#define VK_UNION_MODES(NT, NB)                  \
-  {                                             \
-    if (mode == 0) VK_UNION_LAUNCH(0, NT, NB);  \
+#define VK_UNION_MODES(NT, NB)                      \
+  {                                                 \
+    if (mode == 0) VK_UNION_LAUNCH(0, NT, NB);      \
     else if (mode == 1) VK_UNION_LAUNCH(1, NT, NB); \
-    else VK_UNION_LAUNCH(2, NT, NB);            \
+    else VK_UNION_LAUNCH(2, NT, NB);                \
   }
   if (R > 32) {
     if (nontemporal) VK_UNION_MODES(true, 4)
