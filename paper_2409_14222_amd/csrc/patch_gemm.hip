@@ -140,8 +140,8 @@ __global__ void __launch_bounds__(64 * NW, KP > 0 ? 16 / NW : 1) patch_gemm_mfma
 // FP64 inverses: vector FMAs.  The residual block T[I_i, 0:R] sits in LDS as
 // [n][W] doubles, W = 16 ceil(R / 16); wave g computes the 16 columns
 // 16 g .. 16 g + 15 (waves past ceil(R / 16) leave after the gather) for rows
-// r, r + 64, ...  The columns of the inverse stream from HBM 8 at a time
-// (unconditional clamped loads); every column sums in ascending j.
+// r, r + 64, ...  The columns of the inverse stream from HBM 16 at a time;
+// every column sums in ascending j.
 __global__ void __launch_bounds__(256) patch_gemm_f64_kernel(const int4* __restrict__ meta,
                                                              const int* __restrict__ pdofs,
                                                              const double* __restrict__ inv,
@@ -167,16 +167,36 @@ __global__ void __launch_bounds__(256) patch_gemm_f64_kernel(const int4* __restr
     double acc[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-    for (int j0 = 0; j0 < n; j0 += 8) {
-      double a[8];
+    // whole batches of 16 columns without a test (a test per column let the compiler sink each
+    // load next to its use, one load in flight), then the last partial batch with clamped loads
+    // and the terms past n dropped by a select
+    int j0 = 0;
+    for (; j0 + 16 <= n; j0 += 16) {
+      double a[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = A[(int64_t)min(j0 + u, n - 1) * ld + r];
+      for (int u = 0; u < 16; ++u) a[u] = A[(int64_t)(j0 + u) * ld + r];
+      __builtin_amdgcn_sched_barrier(0);  // all 16 loads go out before the first product
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (j0 + u >= n) break;
+      for (int u = 0; u < 16; ++u) {
         const double* b = Bd + (j0 + u) * W + 16 * g;
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[v] += a[u] * b[v];
+      }
+    }
+    if (j0 < n) {
+      double a[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) a[u] = A[(int64_t)min(j0 + u, n - 1) * ld + r];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const bool on = j0 + u < n;
+        const double* b = Bd + min(j0 + u, n - 1) * W + 16 * g;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const double t = acc[v] + a[u] * b[v];
+          acc[v] = on ? t : acc[v];
+        }
       }
     }
 #pragma unroll
