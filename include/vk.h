@@ -240,6 +240,18 @@ vk_status vk_level_csr(const vk_hierarchy* h, int level, int* h_rowptr, int* h_c
 vk_status vk_level_prolongation(const vk_hierarchy* h, int level, int* h_rowptr, int* h_col,
                                 double* h_val); /* P from level-1 to level, rows = level's DoFs */
 vk_status vk_level_patches(const vk_hierarchy* h, int level, int* h_ptr, int* h_dofs);
+/* K's rows of level >= 1 in union groups, the layout of the K products of more than 8
+ * right-hand sides (host copies, for tests).  h_sizes[0..3] receive the group count, the row
+ * count (n_free), the listed columns and the stored values.  With non-null arrays (sized from
+ * those counts) also: h_gptr (groups + 1 starts into h_grow), h_grow (K's rows: runs of
+ * identical column lists taken in patch order, at most 16 rows per group), h_uptr (groups + 1
+ * starts into h_ucol), h_ucol (a group's ascending column union, padded to a multiple of 16 by
+ * repeating its last column), h_voff (groups, start of a group's values) and h_val (per group
+ * the dense G x U block in steps of 4 listed columns, [step][row][4], zeros where a row has no
+ * entry and in the padding).  Builds the groups on first use.  VK_EINVAL for a bad level or a
+ * null h_sizes; the arrays are all given or all null. */
+vk_status vk_level_union_groups(const vk_hierarchy* h, int level, int64_t* h_sizes, int* h_gptr, int* h_grow,
+                                int* h_uptr, int* h_ucol, int64_t* h_voff, double* h_val);
 /* Discretisation errors of a finest-level solution h_x (host, n_free values) against the
  * manufactured solution of the problem's field (Sec. 4, stopping criteria): h_err[0] = the
  * relative H^1 error of the velocity ||u - u_h||_1 / ||u||_1 (boundary nodes take the exact

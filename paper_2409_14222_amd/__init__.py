@@ -101,6 +101,7 @@ _SIGS = {
     "vk_level_csr": ([_p, _c_int, _p, _p, _p], _c_int),
     "vk_level_prolongation": ([_p, _c_int, _p, _p, _p], _c_int),
     "vk_level_patches": ([_p, _c_int, _p, _p], _c_int),
+    "vk_level_union_groups": ([_p, _c_int, _p, _p, _p, _p, _p, _p, _p], _c_int),
     "vk_dof_coords": ([_p, _c_int, _p, _p], _c_int),
     "vk_rhs": ([_p, _p], _c_int),
     "vk_patch_gather": ([_p, _c_int, _c_int, _c_int, _p], _c_int),
@@ -217,6 +218,17 @@ class Hierarchy:
         rp = np.empty(inf.n_free + 1, np.int32); col = np.empty(inf.nnz, np.int32); val = np.empty(inf.nnz)
         check(lib.vk_level_csr(self.h, level, _ptr(rp), _ptr(col), _ptr(val)))
         return rp, col, val
+
+    def union_groups(self, level):
+        """K's union groups on `level` (host copies): gptr, grow, uptr, ucol, voff, val."""
+        sizes = np.zeros(4, np.int64)
+        check(lib.vk_level_union_groups(self.h, level, _ptr(sizes), None, None, None, None, None, None))
+        ng, nr, nc, nv = (int(x) for x in sizes)
+        gptr = np.empty(ng + 1, np.int32); grow = np.empty(nr, np.int32); uptr = np.empty(ng + 1, np.int32)
+        ucol = np.empty(nc, np.int32); voff = np.empty(ng, np.int64); val = np.empty(nv)
+        check(lib.vk_level_union_groups(self.h, level, _ptr(sizes), _ptr(gptr), _ptr(grow), _ptr(uptr), _ptr(ucol),
+                                        _ptr(voff), _ptr(val)))
+        return gptr, grow, uptr, ucol, voff, val
 
     def prolongation(self, level):
         inf = self.level_info(level)

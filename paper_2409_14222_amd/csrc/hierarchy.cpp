@@ -1207,6 +1207,32 @@ vk_status vk_level_csr(const vk_hierarchy* h, int level, int* rp, int* col, doub
   });
 }
 
+vk_status vk_level_union_groups(const vk_hierarchy* h, int level, int64_t* sizes, int* gptr, int* grow, int* uptr,
+                                int* ucol, int64_t* voff, double* val) {
+  return guarded([&]() -> vk_status {
+    require(h && sizes, VK_EINVAL, "null argument");
+    require_level(h, level, 1);
+    const bool all = gptr && grow && uptr && ucol && voff && val;
+    require(all || !(gptr || grow || uptr || ucol || voff || val), VK_EINVAL,
+            "union group arrays: give all of them or none");
+    const LevelHost& L = h->H[level];
+    const UnionGroups& g = k_unions(L);
+    sizes[0] = g.ngroups();
+    sizes[1] = (int64_t)g.grow.size();
+    sizes[2] = (int64_t)g.ucol.size();
+    sizes[3] = g.nval;
+    if (!all) return VK_OK;
+    std::copy(g.gptr.begin(), g.gptr.end(), gptr);
+    std::copy(g.grow.begin(), g.grow.end(), grow);
+    std::copy(g.uptr.begin(), g.uptr.end(), uptr);
+    std::copy(g.ucol.begin(), g.ucol.end(), ucol);
+    std::copy(g.voff.begin(), g.voff.end(), voff);
+    const std::vector<double> v = union_values(L.K, g);
+    std::copy(v.begin(), v.end(), val);
+    return VK_OK;
+  });
+}
+
 vk_status vk_level_prolongation(const vk_hierarchy* h, int level, int* rp, int* col, double* val) {
   return guarded([&]() -> vk_status {
     require(h && rp && col && val, VK_EINVAL, "null argument");

@@ -110,6 +110,15 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(vk.VkError) as e:
         vk.check(vk.lib.vk_patches_setup(H.h))
     assert e.value.code == vk.VK_ESTATE
+    # union groups exist on levels with patches only, and take all of their arrays or none
+    with pytest.raises(vk.VkError) as e:
+        H.union_groups(0)
+    assert e.value.code == vk.VK_EINVAL
+    sizes = np.zeros(4, np.int64)
+    some = np.zeros(16, np.int32)
+    with pytest.raises(vk.VkError) as e:
+        vk.check(vk.lib.vk_level_union_groups(H.h, 1, vk._ptr(sizes), vk._ptr(some), None, None, None, None, None))
+    assert e.value.code == vk.VK_EINVAL
 
 
 def test_server_create_validates_streams():
@@ -491,3 +500,55 @@ def test_bdm_invalid_combinations_are_rejected():
     rp, col, val = H1.csr(1)
     assert np.abs(val - O1.K.data).max() <= 1e-12 * np.abs(O1.K.data).max()
     assert np.abs(H0.csr(1)[2] - val).max() > 1.0
+
+
+@pytest.mark.parametrize("case", ["p4p3", "sv", "bdm2", "p2p1_3d"])
+def test_union_groups_hold_k_exactly(case):
+    """K's union groups (the layout of the K products of more than 8 right-hand sides): every row
+    in exactly one group of at most 16 rows, the rows of a group in blocks of consecutive rows with
+    identical column lists, the listed columns the ascending union of the rows' columns padded to
+    a multiple of 16 by its last column, at most 96 of them unless the group is one block, at most
+    twice the group's nonzeros stored, and the dense [step][row][4] blocks holding exactly K's
+    entries with zeros elsewhere, so that the blocks reproduce K X."""
+    kw = {"p4p3": dict(k=4, n0=2, nl=3), "sv": dict(k=3, n0=2, nl=3, family=vk.VK_SV),
+          "bdm2": dict(k=2, n0=2, nl=3, family=vk.VK_BDM, forcing=vk.VK_F_PAPER_MMS),
+          "p2p1_3d": dict(k=2, n0=2, nl=2, dim=3, forcing=vk.VK_F_CUBE_MMS)}[case]
+    k, n0, nl = kw.pop("k"), kw.pop("n0"), kw.pop("nl")
+    H = vk.Hierarchy(k, n0, nl, **kw)
+    rng = np.random.default_rng(7)
+    for l in range(1, nl):
+        rp, col, val = H.csr(l)
+        N = len(rp) - 1
+        K = _csr_matrix(rp, col, val, N, N)
+        gptr, grow, uptr, ucol, voff, gval = H.union_groups(l)
+        assert np.array_equal(np.sort(grow), np.arange(N))
+        X = rng.standard_normal((N, 3))
+        Y = np.zeros((N, 3))
+        off = 0
+        for g in range(len(gptr) - 1):
+            rows = grow[gptr[g]:gptr[g + 1]]
+            G = len(rows)
+            u = ucol[uptr[g]:uptr[g + 1]]
+            assert 1 <= G <= 16 and len(u) % 16 == 0 and voff[g] == off
+            U = len(np.unique(u))
+            assert np.all(np.diff(u[:U]) > 0) and np.all(u[U:] == u[U - 1])
+            cols = [col[rp[r]:rp[r + 1]] for r in rows]
+            assert np.array_equal(u[:U], np.unique(np.concatenate(cols)))
+            # blocks of consecutive rows with identical column lists
+            blocks = 1 + sum(1 for a, b, ca, cb in zip(rows, rows[1:], cols, cols[1:])
+                             if b != a + 1 or not np.array_equal(ca, cb))
+            assert U <= 96 or blocks == 1
+            nnz = sum(len(c) for c in cols)
+            assert G * U <= 2 * nnz
+            blk = gval[off:off + G * len(u)].reshape(len(u) // 4, G, 4)
+            dense = blk.transpose(1, 0, 2).reshape(G, len(u))
+            ref = np.zeros((G, len(u)))
+            for t, r in enumerate(rows):
+                pos = np.searchsorted(u[:U], col[rp[r]:rp[r + 1]])
+                ref[t, pos] = val[rp[r]:rp[r + 1]]
+            assert np.array_equal(dense, ref)
+            Y[rows] = dense @ X[u]
+            off += G * len(u)
+        assert off == len(gval)
+        m = np.diff(rp)[:, None]
+        assert np.all(np.abs(Y - K @ X) <= 2 * (m + 2) * np.finfo(float).eps * (abs(K) @ np.abs(X)))
