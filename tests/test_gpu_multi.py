@@ -192,19 +192,19 @@ def test_columns_are_independent(hier, store):
         assert np.array_equal(shuffled[:, pos], batch[:, c])
 
 
-@pytest.mark.parametrize("store", ["fp64", "fp32"])
-def test_multi_graph_replays_match_eager(store):
+@pytest.mark.parametrize("store,max_rhs,R", [("fp64", 6, 5), ("fp32", 6, 5), ("fp64", 16, 12)])
+def test_multi_graph_replays_match_eager(store, max_rhs, R):
     """Many-RHS Arnoldi steps replayed from captured HIP graphs give bitwise the eager result,
-    also with columns converging at different iterations; replays are interleaved with eager
-    solves and host synchronisations and every one is checked."""
+    also with columns converging at different iterations (12 columns: the K products over union
+    groups); replays are interleaved with eager solves and host synchronisations and every one
+    is checked."""
     import paper_2409_14222_amd as vk
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         st = vk.VK_STORE_FP32 if store == "fp32" else vk.VK_STORE_FP64
-        H = vk.Hierarchy(2, 4, 3, store=st).bind(max_rhs=6).setup()
+        H = vk.Hierarchy(2, 4, 3, store=st).bind(max_rhs=max_rhs).setup()
         N = H.level_info(2).n_free
-        R = 5
-        B = np.stack([H.rhs_random(synth.forcing_coeffs(300 + j)) * (10.0 ** -j) for j in range(R)], axis=1)
+        B = np.stack([H.rhs_random(synth.forcing_coeffs(300 + j)) * (10.0 ** -(j % 6)) for j in range(R)], axis=1)
         B[:, 2] = 0.0  # a column that is done before the first iteration
         Bd = _dev(B)
         X_eager = torch.empty((N, R), dtype=torch.float64, device="cuda")
